@@ -1,0 +1,172 @@
+/*
+ * mgemm.h -- C ABI of libmgemm, a single-precision general matrix-matrix
+ * multiply for AMD Instinct MI355X (gfx950).
+ *
+ * The operation is the Level-3 BLAS SGEMM routine (Aberdeen & Baxter,
+ * Section 1: the library "implements the SGEMM interface of Level-3 BLAS";
+ * A is M x K, B is K x N and the product costs 2MNK flops):
+ *
+ *     C <- alpha * op(A) * op(B) + beta * C
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Storage.  Column-major, as in BLAS: element (r, c) of a stored array X
+ *   with leading dimension ldX is X[r + c*ldX].  op(X) is X for trans 'N'
+ *   or 'n', and X^T for 'T', 't', 'C' or 'c' (real data: the conjugate
+ *   transpose is the transpose).  A is stored M x K ('N') or K x M ('T');
+ *   B is stored K x N ('N') or N x K ('T'); C is stored M x N.  Only the
+ *   leading stored-rows x columns part of each array is referenced.
+ * Pointers.  A, B and C are DEVICE pointers owned by the caller (for
+ *   example torch tensors).  The library never frees or keeps them.  C must
+ *   not overlap the referenced part of A or B.
+ * Scalars.  alpha == 0 or K == 0: A and B are not read and C <- beta*C.
+ *   beta == 0: C is not read, so NaN or Inf in C do not propagate.
+ *   M == 0, N == 0, or ((alpha == 0 or K == 0) and beta == 1): nothing is
+ *   launched and the call returns MGEMM_OK.
+ * Sizes.  64-bit.  Leading dimensions: lda >= max(1, stored rows of A),
+ *   ldb >= max(1, stored rows of B), ldc >= max(1, M).
+ * Streams.  `stream` is a hipStream_t (NULL = the default stream).  Calls
+ *   enqueue work and return; a fault inside a kernel is reported by the
+ *   caller's next synchronisation, as usual for HIP.  Calls on different
+ *   streams may be made from different threads.
+ * Errors.  Return value 0 (MGEMM_OK) on success.  A negative value -i
+ *   names the illegal argument by its position in the BLAS SGEMM argument
+ *   list: 1 transA, 2 transB, 3 M, 4 N, 5 K, 7 A, 8 lda, 9 B, 10 ldb,
+ *   12 C, 13 ldc (a NULL A, B or C is illegal only when it would be
+ *   read or written).  Arguments are checked in that order, before any
+ *   HIP call, so a bad call launches nothing.  Positive values are the
+ *   MGEMM_ERR_* codes below.  mgemm_last_error() gives a text for the last
+ *   failing call on the calling thread.
+ */
+#ifndef MGEMM_H
+#define MGEMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MGEMM_OK              0
+#define MGEMM_ERR_HIP         100 /* a HIP runtime call failed */
+#define MGEMM_ERR_NO_DEVICE   101 /* no HIP device is visible */
+#define MGEMM_ERR_ARCH        102 /* the current device is not gfx950 */
+#define MGEMM_ERR_ALLOC       103 /* device memory for a workspace or plan */
+#define MGEMM_ERR_ALIAS       105 /* C overlaps the referenced part of A or B */
+#define MGEMM_ERR_UNSUPPORTED 106 /* unknown precision or tile configuration */
+#define MGEMM_ERR_BAD_PLAN    107 /* NULL or already destroyed plan */
+#define MGEMM_ERR_BAD_PROBLEM 108 /* a grouped problem failed validation */
+
+/* Arithmetic used for the product (the result is always FP32). */
+#define MGEMM_PREC_FP32        0 /* FP32 operands, FP32 MFMA, FP32 accumulate */
+#define MGEMM_PREC_BF16X3      1 /* x = hi + lo in BF16 (round to nearest even);
+                                    hi*hi + hi*lo + lo*hi on BF16 MFMA,
+                                    FP32 accumulate; lo*lo is dropped */
+#define MGEMM_PREC_FP16_SCALED 2 /* power-of-two scale per 32-row panel of
+                                    op(A) and per 32-column panel of op(B),
+                                    FP16 MFMA, FP32 accumulate, exact unscale */
+
+/*
+ * The SGEMM operation above (paper, Section 1), computed in FP32 on FP32
+ * MFMA with a tile configuration the library chooses.  The 14 arguments
+ * follow the BLAS SGEMM order, plus the stream.
+ */
+int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
+                float alpha, const float *A, int64_t lda,
+                const float *B, int64_t ldb,
+                float beta, float *C, int64_t ldc, void *stream);
+
+/*
+ * The same operation in one of the MGEMM_PREC_* arithmetics, with an
+ * explicit tile configuration `config` (0 .. mgemm_config_count(precision)-1)
+ * or -1 for the library's choice.  MGEMM_PREC_FP16_SCALED allocates a small
+ * stream-ordered workspace ((M+N)/32 exponents) and frees it in stream
+ * order; an allocation failure returns MGEMM_ERR_ALLOC.
+ */
+int mgemm_sgemm_ex(char transA, char transB, int64_t M, int64_t N, int64_t K,
+                   float alpha, const float *A, int64_t lda,
+                   const float *B, int64_t ldb,
+                   float beta, float *C, int64_t ldc, void *stream,
+                   int precision, int config);
+
+/* Number of tile configurations for a precision (0 for an unknown one). */
+int mgemm_config_count(int precision);
+
+/*
+ * Description of one configuration: BM, BN, BK (the work-group tile of C
+ * and the K depth of one staged slab) and the number of threads per
+ * work-group.  Returns MGEMM_ERR_UNSUPPORTED for an unknown pair.
+ */
+int mgemm_config_info(int precision, int config, int *bm, int *bn, int *bk,
+                      int *threads);
+
+/* The configuration mgemm_sgemm_ex(..., config = -1) would use. */
+int mgemm_default_config(int precision, char transA, char transB,
+                         int64_t M, int64_t N, int64_t K);
+
+/* ---- many independent products in one persistent launch ---------------- */
+
+/*
+ * One problem of a batch: C_i <- alpha_i op(A_i) op(B_i) + beta_i C_i with
+ * the conventions above (device pointers, column-major).
+ */
+typedef struct mgemm_problem {
+    char transA, transB;
+    int64_t M, N, K;
+    float alpha, beta;
+    const float *A; int64_t lda;
+    const float *B; int64_t ldb;
+    float *C; int64_t ldc;
+} mgemm_problem;
+
+typedef struct mgemm_plan mgemm_plan;
+
+/*
+ * Build a plan for `count` problems (host array, copied): validates every
+ * problem (on failure returns MGEMM_ERR_BAD_PROBLEM with *bad_index set and
+ * *bad_status the BLAS-style code of the first bad argument), picks a tile
+ * configuration per problem from `bucket_configs` (an array of 4 entries
+ * indexed by size bucket, see mgemm_grouped_bucket; NULL = library
+ * defaults), uploads the descriptor table and tile list to device memory,
+ * and records one launch of the persistent grouped kernel on `stream` into
+ * a HIP graph.  The C_i must not overlap each other.  Device memory owned
+ * by the plan is freed by mgemm_grouped_plan_destroy.
+ */
+int mgemm_grouped_plan_create(const mgemm_problem *problems, int64_t count,
+                              int precision, const int *bucket_configs,
+                              void *stream, mgemm_plan **out_plan,
+                              int64_t *bad_index, int *bad_status);
+
+/* Replay the plan's graph on `stream` (hipGraphLaunch). */
+int mgemm_grouped_plan_launch(mgemm_plan *plan, void *stream);
+
+/* Launch the plan's persistent kernel directly on `stream` (no graph). */
+int mgemm_grouped_plan_run(mgemm_plan *plan, void *stream);
+
+/* Number of tiles and of work-groups of the plan's persistent launch. */
+int mgemm_grouped_plan_info(const mgemm_plan *plan, int64_t *tiles,
+                            int64_t *workgroups);
+
+/* Free the plan (waits for nothing: the caller synchronises first).
+ * A NULL or already destroyed plan returns MGEMM_ERR_BAD_PLAN. */
+int mgemm_grouped_plan_destroy(mgemm_plan *plan);
+
+/* Size bucket (0..3) of a grouped problem, by max(M, N). */
+int mgemm_grouped_bucket(int64_t M, int64_t N, int64_t K);
+
+/* ---- status ------------------------------------------------------------ */
+
+/* Static text for a status code. */
+const char *mgemm_status_string(int status);
+
+/* Text for the last failing call on this thread ("" if none). */
+const char *mgemm_last_error(void);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int mgemm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MGEMM_H */

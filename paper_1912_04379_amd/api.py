@@ -1,0 +1,117 @@
+"""BLAS-style and torch-style entry points (argument marshalling only)."""
+import ctypes
+
+from ._lib import PRECISIONS, check, lib
+
+
+def stream_handle(stream=None):
+    """hipStream_t of a torch stream (None: torch's current stream)."""
+    if isinstance(stream, int):
+        return stream
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+def _prec(precision):
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _check_tensor(t, name):
+    if t is None or isinstance(t, int):
+        return
+    import torch
+    if t.dtype != torch.float32:
+        raise TypeError("%s must be float32, got %s" % (name, t.dtype))
+    if not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+
+
+def sgemm(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, *,
+          precision="fp32", config=-1, stream=None):
+    """C <- alpha op(A) op(B) + beta C on column-major device buffers.
+
+    A, B, C are float32 device tensors (their storage is read as flat
+    column-major arrays from data_ptr()) or raw device addresses.  Raises
+    MgemmError on any non-zero status.
+    """
+    for t, n in ((A, "A"), (B, "B"), (C, "C")):
+        _check_tensor(t, n)
+    p = _prec(precision)
+    s = stream_handle(stream)
+    L = lib()
+    if p == 0 and config == -1:
+        st = L.mgemm_sgemm(transA.encode(), transB.encode(), M, N, K, alpha, _ptr(A), lda,
+                           _ptr(B), ldb, beta, _ptr(C), ldc, s)
+    else:
+        st = L.mgemm_sgemm_ex(transA.encode(), transB.encode(), M, N, K, alpha, _ptr(A), lda,
+                              _ptr(B), ldb, beta, _ptr(C), ldc, s, p, config)
+    return check(st)
+
+
+def colmajor_view(T):
+    """How a 2-D tensor T (r x c, torch semantics) enters a column-major
+    product as its transpose T^T: returns (trans, ld) such that op(X) = T^T
+    where X is the stored array at T.data_ptr().
+
+    A row-major T (stride (ld, 1)) is stored column-major as T^T (c x r):
+    op 'N'.  A column-major T (stride (1, ld)), e.g. a transposed view, is
+    stored as T itself: op 'T'.
+    """
+    r, c = T.shape
+    s0, s1 = T.stride()
+    if s1 == 1 and (s0 >= max(1, c) or r <= 1):
+        return "N", max(1, s0, c)
+    if s0 == 1 and (s1 >= max(1, r) or c <= 1):
+        return "T", max(1, s1, r)
+    raise ValueError("tensor must have unit stride in one dimension")
+
+
+def matmul(X, W, *, precision="fp32", config=-1, out=None, stream=None):
+    """Y = X @ W for 2-D float32 device tensors, Y row-major (b x o).
+
+    Row-major Y is column-major Y^T = W^T X^T, so this is one call
+    sgemm(opW, opX, o, b, i, 1, W, ldw, X, ldx, 0, Y, o).
+    """
+    import torch
+    b, i = X.shape
+    i2, o = W.shape
+    if i != i2:
+        raise ValueError("inner dimensions differ: %d vs %d" % (i, i2))
+    if out is None:
+        out = torch.empty((b, o), dtype=torch.float32, device=X.device)
+    if out.shape != (b, o) or out.stride() != (o, 1) and b > 0 and o > 0:
+        raise ValueError("out must be a contiguous (b x o) tensor")
+    tw, ldw = colmajor_view(W)
+    tx, ldx = colmajor_view(X)
+    sgemm(tw, tx, o, b, i, 1.0, W, ldw, X, ldx, 0.0, out, max(1, o),
+          precision=precision, config=config, stream=stream)
+    return out
+
+
+def config_count(precision="fp32"):
+    return lib().mgemm_config_count(_prec(precision))
+
+
+def config_info(precision, config):
+    v = [ctypes.c_int() for _ in range(4)]
+    check(lib().mgemm_config_info(_prec(precision), config, *[ctypes.byref(x) for x in v]))
+    return dict(bm=v[0].value, bn=v[1].value, bk=v[2].value, threads=v[3].value)
+
+
+def default_config(precision, transA, transB, M, N, K):
+    return lib().mgemm_default_config(_prec(precision), transA.encode(), transB.encode(),
+                                      M, N, K)
+
+
+def version():
+    return lib().mgemm_version()

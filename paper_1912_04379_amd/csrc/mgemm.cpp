@@ -1,0 +1,259 @@
+// mgemm.cpp -- host side of the C ABI declared in include/mgemm.h:
+// argument validation (BLAS order, before any HIP call), quick returns,
+// device checks, configuration choice and kernel dispatch.
+#include "mgemm.h"
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "host_common.hpp"
+#include "kernels.hpp"
+
+namespace mgemm {
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+static int hip_fail(hipError_t e, const char* where) {
+    return fail(MGEMM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int trans_code(char t) {
+    if (t == 'N' || t == 'n') return 0;
+    if (t == 'T' || t == 't' || t == 'C' || t == 'c') return 1;
+    return -1;
+}
+
+static int64_t max1(int64_t v) { return v > 1 ? v : 1; }
+
+// Byte ranges [lo, hi) touched by the referenced part of a stored array.
+static void extent(const void* p, int64_t rows, int64_t cols, int64_t ld, uintptr_t& lo,
+                   uintptr_t& hi) {
+    lo = (uintptr_t)p;
+    hi = lo + (uintptr_t)(((cols - 1) * ld + rows) * (int64_t)sizeof(float));
+}
+
+int validate(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
+             const float* A, int64_t lda, const float* B, int64_t ldb, float beta,
+             const float* C, int64_t ldc, std::string& why) {
+    const int ta = trans_code(transA), tb = trans_code(transB);
+    if (ta < 0) { why = "transA must be N, T or C"; return -1; }
+    if (tb < 0) { why = "transB must be N, T or C"; return -2; }
+    if (M < 0) { why = "M < 0"; return -3; }
+    if (N < 0) { why = "N < 0"; return -4; }
+    if (K < 0) { why = "K < 0"; return -5; }
+    const int64_t rows_a = ta ? K : M, rows_b = tb ? N : K;
+    const bool reads_ab = alpha != 0.0f && K > 0 && M > 0 && N > 0;
+    if (reads_ab && A == nullptr) { why = "A is NULL"; return -7; }
+    if (lda < max1(rows_a)) { why = "lda < max(1, stored rows of A)"; return -8; }
+    if (reads_ab && B == nullptr) { why = "B is NULL"; return -9; }
+    if (ldb < max1(rows_b)) { why = "ldb < max(1, stored rows of B)"; return -10; }
+    if (M > 0 && N > 0 && C == nullptr) { why = "C is NULL"; return -12; }
+    if (ldc < max1(M)) { why = "ldc < max(1, M)"; return -13; }
+    (void)beta;
+    return 0;
+}
+
+// C must not overlap the referenced part of A or B (the kernels read A and
+// B while other work-groups write C).
+bool overlaps(int ta, int tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
+              int64_t lda, const float* B, int64_t ldb, const float* C, int64_t ldc) {
+    if (alpha == 0.0f || K == 0 || M == 0 || N == 0) return false;
+    uintptr_t clo, chi, lo, hi;
+    extent(C, M, N, ldc, clo, chi);
+    extent(A, ta ? K : M, ta ? M : K, lda, lo, hi);
+    if (lo < chi && clo < hi) return true;
+    extent(B, tb ? N : K, tb ? K : N, ldb, lo, hi);
+    return lo < chi && clo < hi;
+}
+
+// Per-device check that the current device is a gfx950: 0 unknown,
+// 1 ok, 2 wrong architecture.
+static std::atomic<int> g_dev_state[64];
+
+int check_device(int* out_dev) {
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return fail(MGEMM_ERR_NO_DEVICE, "no HIP device is visible");
+    }
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (out_dev) *out_dev = dev;
+    int state = dev < 64 ? g_dev_state[dev].load(std::memory_order_relaxed) : 0;
+    if (state == 0) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        state = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0 ? 1 : 2;
+        if (dev < 64) g_dev_state[dev].store(state, std::memory_order_relaxed);
+        if (state == 2)
+            return fail(MGEMM_ERR_ARCH, std::string("device is ") + prop.gcnArchName +
+                                            ", this library is built for gfx950");
+    }
+    if (state == 2) return fail(MGEMM_ERR_ARCH, "device is not a gfx950");
+    return MGEMM_OK;
+}
+
+int config_count(int precision) {
+    switch (precision) {
+        case MGEMM_PREC_FP32: return f32_config_count();
+        case MGEMM_PREC_BF16X3: return bf16x3_config_count();
+        case MGEMM_PREC_FP16_SCALED: return f16s_config_count();
+        default: return 0;
+    }
+}
+
+static int default_config(int precision, int64_t M, int64_t N, int64_t K) {
+    switch (precision) {
+        case MGEMM_PREC_FP32: return f32_default_config(M, N, K);
+        case MGEMM_PREC_BF16X3: return bf16x3_default_config(M, N, K);
+        case MGEMM_PREC_FP16_SCALED: return f16s_default_config(M, N, K);
+        default: return -1;
+    }
+}
+
+static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
+                      const float* A, int64_t lda, const float* B, int64_t ldb, float beta,
+                      float* C, int64_t ldc, void* stream, int precision, int config) {
+    std::string why;
+    const int bad = validate(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, why);
+    if (bad) return fail(bad, why);
+    if (precision < 0 || precision > MGEMM_PREC_FP16_SCALED)
+        return fail(MGEMM_ERR_UNSUPPORTED, "unknown precision");
+    if (config < -1 || config >= config_count(precision))
+        return fail(MGEMM_ERR_UNSUPPORTED, "unknown tile configuration");
+    const int ta = trans_code(transA), tb = trans_code(transB);
+    // Quick returns (reference BLAS).
+    if (M == 0 || N == 0) return MGEMM_OK;
+    const bool no_product = alpha == 0.0f || K == 0;
+    if (no_product && beta == 1.0f) return MGEMM_OK;
+    if (overlaps(ta, tb, M, N, K, alpha, A, lda, B, ldb, C, ldc))
+        return fail(MGEMM_ERR_ALIAS, "C overlaps A or B");
+    int st = check_device(nullptr);
+    if (st) return st;
+
+    hipStream_t s = (hipStream_t)stream;
+    GemmDesc d{A, B, C, M, N, K, lda, ldb, ldc, alpha, beta, nullptr, nullptr};
+    hipError_t e;
+    if (no_product) {
+        e = launch_scale_c(d, s);
+        return e == hipSuccess ? MGEMM_OK : hip_fail(e, "scale kernel launch");
+    }
+    const int cfg = config >= 0 ? config : default_config(precision, M, N, K);
+    switch (precision) {
+        case MGEMM_PREC_FP32:
+            e = launch_f32(cfg, ta, tb, d, s);
+            break;
+        case MGEMM_PREC_BF16X3:
+            e = launch_bf16x3(cfg, ta, tb, d, s);
+            break;
+        default: {
+            // Stream-ordered workspace for the panel exponents.
+            const int64_t pa = (M + 31) / 32, pb = (N + 31) / 32;
+            int* ex = nullptr;
+            e = hipMallocAsync((void**)&ex, (size_t)(pa + pb) * sizeof(int), s);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(MGEMM_ERR_ALLOC, "workspace for FP16 panel exponents");
+            }
+            d.expA = ex;
+            d.expB = ex + pa;
+            e = launch_f16_exponents(ta, tb, d, ex, ex + pa, s);
+            if (e == hipSuccess) e = launch_f16s(cfg, ta, tb, d, s);
+            hipError_t e2 = hipFreeAsync(ex, s);
+            if (e == hipSuccess) e = e2;
+            break;
+        }
+    }
+    return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
+}
+
+}  // namespace mgemm
+
+using namespace mgemm;
+
+extern "C" {
+
+int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
+                const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+                int64_t ldc, void* stream) {
+    return sgemm_impl(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream,
+                      MGEMM_PREC_FP32, -1);
+}
+
+int mgemm_sgemm_ex(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
+                   const float* A, int64_t lda, const float* B, int64_t ldb, float beta,
+                   float* C, int64_t ldc, void* stream, int precision, int config) {
+    return sgemm_impl(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream,
+                      precision, config);
+}
+
+int mgemm_config_count(int precision) { return config_count(precision); }
+
+int mgemm_config_info(int precision, int config, int* bm, int* bn, int* bk, int* threads) {
+    if (config < 0 || config >= config_count(precision))
+        return fail(MGEMM_ERR_UNSUPPORTED, "unknown tile configuration");
+    TileConfigInfo t = precision == MGEMM_PREC_FP32     ? f32_config_info(config)
+                       : precision == MGEMM_PREC_BF16X3 ? bf16x3_config_info(config)
+                                                        : f16s_config_info(config);
+    if (bm) *bm = t.bm;
+    if (bn) *bn = t.bn;
+    if (bk) *bk = t.bk;
+    if (threads) *threads = t.threads;
+    return MGEMM_OK;
+}
+
+int mgemm_default_config(int precision, char transA, char transB, int64_t M, int64_t N,
+                         int64_t K) {
+    (void)transA;
+    (void)transB;
+    return default_config(precision, M, N, K);
+}
+
+const char* mgemm_status_string(int status) {
+    if (status < 0) {
+        switch (-status) {
+            case 1: return "illegal argument 1 (transA)";
+            case 2: return "illegal argument 2 (transB)";
+            case 3: return "illegal argument 3 (M)";
+            case 4: return "illegal argument 4 (N)";
+            case 5: return "illegal argument 5 (K)";
+            case 7: return "illegal argument 7 (A)";
+            case 8: return "illegal argument 8 (lda)";
+            case 9: return "illegal argument 9 (B)";
+            case 10: return "illegal argument 10 (ldb)";
+            case 12: return "illegal argument 12 (C)";
+            case 13: return "illegal argument 13 (ldc)";
+            default: return "illegal argument";
+        }
+    }
+    switch (status) {
+        case MGEMM_OK: return "success";
+        case MGEMM_ERR_HIP: return "HIP runtime error";
+        case MGEMM_ERR_NO_DEVICE: return "no HIP device";
+        case MGEMM_ERR_ARCH: return "device is not gfx950";
+        case MGEMM_ERR_ALLOC: return "device memory allocation failed";
+        case MGEMM_ERR_ALIAS: return "C overlaps A or B";
+        case MGEMM_ERR_UNSUPPORTED: return "unsupported precision or configuration";
+        case MGEMM_ERR_BAD_PLAN: return "invalid plan";
+        case MGEMM_ERR_BAD_PROBLEM: return "invalid problem in a grouped batch";
+        default: return "unknown status";
+    }
+}
+
+const char* mgemm_last_error(void) { return g_last_error.c_str(); }
+
+int mgemm_version(void) { return 100; }
+
+}  // extern "C"

@@ -1,0 +1,212 @@
+// sgemm_f32.hip -- FP32 GEMM on gfx950 FP32 MFMA (v_mfma_f32_32x32x2_f32).
+//
+// C <- alpha op(A) op(B) + beta C, FP32 in, FP32 accumulate, FP32 out.
+// The paper's recipe (Sections 2 and 3) -- accumulate in registers as long
+// as possible, reuse every loaded operand several times, stage blocks of
+// A and B close to the arithmetic, prefetch the next block while computing
+// the current one -- maps onto gfx950 as:
+//   * registers:  each wave owns an (FM*32) x (FN*32) block of C held in
+//                 MFMA accumulators for the whole K loop; each operand value
+//                 read from LDS feeds FN (or FM) MFMAs;
+//   * L1 block:   a BM x BK slab of op(A) and a BK x BN slab of op(B) in LDS;
+//   * prefetch:   the next slab is loaded from global memory into registers
+//                 while the MFMAs run on the current LDS buffer (two LDS
+//                 buffers, one barrier per slab);
+//   * L2 block:   XCD-aware, band-ordered tile rasterisation.
+#include "kernels.hpp"
+
+namespace mgemm {
+
+template <int BM_, int BN_, int BK_, int WGM_, int WGN_>
+struct CfgF32 {
+    static constexpr int BM = BM_, BN = BN_, BK = BK_;
+    static constexpr int WGM = WGM_, WGN = WGN_;
+    static constexpr int NT = 64 * WGM * WGN;
+    static constexpr int WM = BM / WGM, WN = BN / WGN;
+    static constexpr int FM = WM / 32, FN = WN / 32;
+    static constexpr int S = BK + 4;  // LDS row stride (floats): 16-byte
+                                      // aligned rows, conflict-free b128 reads
+    static constexpr int STAGE = (BM + BN) * S;
+    static constexpr int SMEM_FLOATS = 2 * STAGE;
+    static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile must be 32-aligned");
+    static_assert(BK % 8 == 0, "BK must be a multiple of 8");
+};
+
+template <int BP, int BK, int NT, bool KC>
+__device__ inline void stage_to_lds(const SlabLoader<BP, BK, NT, KC>& ld, float* Xs,
+                                    int tid) {
+    constexpr int S = BK + 4;
+#pragma unroll
+    for (int q = 0; q < SlabLoader<BP, BK, NT, KC>::PER_THREAD; ++q) {
+        int p, kq;
+        SlabLoader<BP, BK, NT, KC>::group_pos(tid + q * NT, p, kq);
+        *reinterpret_cast<f32x4*>(Xs + p * S + 4 * kq) = ld.v[q];
+    }
+}
+
+// One BM x BN tile of C at (m0, n0).  AK / BKC: op(A) / op(B) contiguous
+// along K in memory (A 'T' / B 'N').
+template <class Cfg, bool AK, bool BKC>
+__device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float* smem) {
+    constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, NT = Cfg::NT, S = Cfg::S;
+    constexpr int FM = Cfg::FM, FN = Cfg::FN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int l32 = lane & 31, h = lane >> 5;
+    const int wm = (wave % Cfg::WGM) * Cfg::WM;
+    const int wn = (wave / Cfg::WGM) * Cfg::WN;
+
+    SlabLoader<BM, BK, NT, AK> la;
+    SlabLoader<BN, BK, NT, BKC> lb;
+
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = f32x16{};
+
+    const int64_t nk = (d.K + BK - 1) / BK;
+    la.load(d.A, d.lda, d.M, d.K, m0, 0, tid);
+    lb.load(d.B, d.ldb, d.N, d.K, n0, 0, tid);
+    stage_to_lds(la, smem, tid);
+    stage_to_lds(lb, smem + BM * S, tid);
+    __syncthreads();
+
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        float* cur = smem + (kt & 1) * Cfg::STAGE;
+        float* nxt = smem + ((kt + 1) & 1) * Cfg::STAGE;
+        const bool more = kt + 1 < nk;
+        if (more) {
+            la.load(d.A, d.lda, d.M, d.K, m0, (kt + 1) * BK, tid);
+            lb.load(d.B, d.ldb, d.N, d.K, n0, (kt + 1) * BK, tid);
+        }
+        const float* As = cur;
+        const float* Bs = cur + BM * S;
+        // MFMA step (c, e): lanes with h = 0 supply k = 4c + e, lanes with
+        // h = 1 supply k = BK/2 + 4c + e; every k of the slab is used once.
+#pragma unroll
+        for (int c = 0; c < BK / 8; ++c) {
+            f32x4 a[FM], b[FN];
+            const int ko = h * (BK / 2) + 4 * c;
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                a[i] = *reinterpret_cast<const f32x4*>(As + (wm + 32 * i + l32) * S + ko);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                b[j] = *reinterpret_cast<const f32x4*>(Bs + (wn + 32 * j + l32) * S + ko);
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        // rows of D = n (from op(B)), columns of D = m (op(A))
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
+                            b[j][e], a[i][e], acc[i][j], 0, 0, 0);
+        }
+        if (more) {
+            stage_to_lds(la, nxt, tid);
+            stage_to_lds(lb, nxt + BM * S, tid);
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                store_c(d, m0 + wm + 32 * i + l32, n0 + wn + 32 * j + mfma32_row(r, lane),
+                        acc[i][j][r], 1.0f);
+}
+
+template <class Cfg, bool AK, bool BKC>
+__global__ __launch_bounds__(Cfg::NT) void sgemm_f32_kernel(GemmDesc d, uint32_t tiles_m,
+                                                           uint32_t tiles_n) {
+    __shared__ __attribute__((aligned(16))) float smem[Cfg::SMEM_FLOATS];
+    uint32_t tm, tn;
+    grouped_tile<8>(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
+    tile_f32<Cfg, AK, BKC>(d, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
+}
+
+template <class Cfg>
+static hipError_t launch_cfg(bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
+    const int64_t tiles_m = (d.M + Cfg::BM - 1) / Cfg::BM;
+    const int64_t tiles_n = (d.N + Cfg::BN - 1) / Cfg::BN;
+    const int64_t tiles = tiles_m * tiles_n;
+    if (tiles_m > 0xffffffffLL || tiles_n > 0xffffffffLL || tiles > 0xffffffffLL)
+        return hipErrorInvalidValue;
+    dim3 grid((uint32_t)tiles), block(Cfg::NT);
+    const uint32_t tmm = (uint32_t)tiles_m, tnn = (uint32_t)tiles_n;
+    // op(A) is K-contiguous for A 'T'; op(B) is K-contiguous for B 'N'.
+    if (!ta && !tb)
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, false, true>), grid, block, 0, s, d, tmm, tnn);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, false, false>), grid, block, 0, s, d, tmm, tnn);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, true, true>), grid, block, 0, s, d, tmm, tnn);
+    else
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, true, false>), grid, block, 0, s, d, tmm, tnn);
+    return hipGetLastError();
+}
+
+using F32Cfg0 = CfgF32<128, 128, 16, 2, 2>;  // 4 waves of 64x64
+using F32Cfg1 = CfgF32<64, 64, 16, 2, 2>;    // 4 waves of 32x32 (small problems)
+using F32Cfg2 = CfgF32<128, 128, 32, 2, 2>;  // deeper slab
+using F32Cfg3 = CfgF32<256, 128, 16, 2, 2>;  // 4 waves of 128x64
+
+template <class Cfg>
+static TileConfigInfo info_of() { return {Cfg::BM, Cfg::BN, Cfg::BK, Cfg::NT}; }
+
+int f32_config_count() { return 4; }
+
+TileConfigInfo f32_config_info(int cfg) {
+    switch (cfg) {
+        case 0: return info_of<F32Cfg0>();
+        case 1: return info_of<F32Cfg1>();
+        case 2: return info_of<F32Cfg2>();
+        case 3: return info_of<F32Cfg3>();
+        default: return {0, 0, 0, 0};
+    }
+}
+
+int f32_default_config(int64_t M, int64_t N, int64_t K) {
+    (void)K;
+    const int64_t big_tiles = ((M + 127) / 128) * ((N + 127) / 128);
+    return big_tiles >= 512 ? 0 : 1;
+}
+
+hipError_t launch_f32(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
+    switch (cfg) {
+        case 0: return launch_cfg<F32Cfg0>(ta, tb, d, s);
+        case 1: return launch_cfg<F32Cfg1>(ta, tb, d, s);
+        case 2: return launch_cfg<F32Cfg2>(ta, tb, d, s);
+        case 3: return launch_cfg<F32Cfg3>(ta, tb, d, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// C <- beta C, for alpha == 0 or K == 0.  beta == 0 writes zeros and never
+// reads C.  Grid-stride over rows (x) and columns (y) of C.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void scale_c_kernel(float* C, int64_t M, int64_t N,
+                                                      int64_t ldc, float beta) {
+    for (int64_t n = blockIdx.y; n < N; n += gridDim.y)
+        for (int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x; m < M;
+             m += (int64_t)gridDim.x * 256) {
+            float* c = C + m + n * ldc;
+            *c = beta == 0.0f ? 0.0f : beta * *c;
+        }
+}
+
+hipError_t launch_scale_c(const GemmDesc& d, hipStream_t s) {
+    const int64_t gx = (d.M + 255) / 256 < 64 ? (d.M + 255) / 256 : 64;
+    const int64_t gy = d.N < 4096 ? d.N : 4096;
+    hipLaunchKernelGGL(scale_c_kernel, dim3((uint32_t)gx, (uint32_t)gy), dim3(256), 0, s,
+                       d.C, d.M, d.N, d.ldc, d.beta);
+    return hipGetLastError();
+}
+
+}  // namespace mgemm

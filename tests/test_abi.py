@@ -1,0 +1,125 @@
+"""The C ABI without a GPU: every declared symbol is exported, arguments are
+checked in BLAS order before any HIP call, quick returns launch nothing."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1912_04379_amd as mg
+from paper_1912_04379_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mgemm.h")
+
+# Fake device addresses: validation and quick returns never dereference them.
+FA, FB, FC = 0x10000000, 0x20000000, 0x30000000
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mgemm_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported():
+    names = declared_functions()
+    assert len(names) >= 14
+    L = mg.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib._SIGS), "binding and header disagree"
+
+
+def test_version_and_status_strings():
+    assert mg.version() == 100
+    L = mg.lib()
+    assert L.mgemm_status_string(0) == b"success"
+    assert b"lda" in L.mgemm_status_string(-8)
+    assert L.mgemm_status_string(_lib.ERR_ARCH) == b"device is not gfx950"
+
+
+def call(transA="N", transB="N", M=4, N=4, K=4, alpha=1.0, A=FA, lda=4, B=FB, ldb=4,
+         beta=0.0, C=FC, ldc=4, precision=0, config=-1):
+    return mg.lib().mgemm_sgemm_ex(transA.encode(), transB.encode(), M, N, K, alpha, A, lda,
+                                   B, ldb, beta, C, ldc, None, precision, config)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(transA="X"), -1),
+    (dict(transB="q"), -2),
+    (dict(M=-1), -3),
+    (dict(N=-1), -4),
+    (dict(K=-1), -5),
+    (dict(A=None), -7),
+    (dict(lda=3), -8),
+    (dict(B=None), -9),
+    (dict(ldb=3), -10),
+    (dict(C=None), -12),
+    (dict(ldc=3), -13),
+    (dict(transA="T", lda=3, K=4), -8),          # stored rows of A^T are K
+    (dict(transB="T", ldb=3, N=4), -10),         # stored rows of B^T are N
+    (dict(transA="X", M=-1, ldc=0), -1),         # first bad argument wins
+    (dict(M=-1, lda=0), -3),
+])
+def test_argument_codes(kw, code):
+    assert call(**kw) == code
+    assert mg.lib().mgemm_last_error() != b""
+
+
+def test_null_operands_allowed_when_not_read():
+    # alpha == 0 with beta == 1: nothing to do, A and B never read.
+    assert call(A=None, B=None, alpha=0.0, beta=1.0) == 0
+    # K == 0 with beta == 1: quick return.
+    assert call(A=None, B=None, K=0, lda=4, ldb=1, beta=1.0) == 0
+    # M == 0: quick return, even with C NULL.
+    assert call(M=0, C=None, lda=1, ldc=1) == 0
+    assert call(N=0, C=None) == 0
+
+
+def test_lowercase_and_conjugate_flags():
+    assert call(transA="c", transB="t", M=0) == 0
+
+
+def test_unsupported_precision_and_config():
+    assert call(precision=7) == _lib.ERR_UNSUPPORTED
+    assert call(config=99) == _lib.ERR_UNSUPPORTED
+    assert mg.config_count("fp32") >= 2
+    info = mg.config_info("fp32", 0)
+    assert info["bm"] > 0 and info["threads"] % 64 == 0
+
+
+def test_alias_detected_before_any_launch():
+    # C overlaps A's referenced extent (returned before any HIP call).
+    assert call(C=FA + 8) == _lib.ERR_ALIAS
+    assert call(C=FB + 60) == _lib.ERR_ALIAS
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="would reach a launch on a GPU")
+def test_adjacent_buffers_are_not_an_alias():
+    # A ends exactly where C starts: legal, fails later only for lack of a GPU.
+    assert call(A=FA, C=FA + 4 * 16) == _lib.ERR_NO_DEVICE
+
+
+@pytest.mark.skipif(os.path.exists("/dev/kfd"), reason="a GPU driver is present")
+def test_valid_call_without_gpu_reports_no_device():
+    assert call() == _lib.ERR_NO_DEVICE
+    with pytest.raises(mg.MgemmError) as e:
+        mg.sgemm("N", "N", 4, 4, 4, 1.0, FA, 4, FB, 4, 0.0, FC, 4, stream=0)
+    assert e.value.status == _lib.ERR_NO_DEVICE
+
+
+def test_bucket_function_is_total():
+    L = mg.lib()
+    for m, n in ((16, 16), (64, 64), (200, 100), (512, 512), (1000, 9000)):
+        b = L.mgemm_grouped_bucket(m, n, 64)
+        assert 0 <= b <= 3
+
+
+def test_plan_functions_reject_null():
+    L = mg.lib()
+    assert L.mgemm_grouped_plan_destroy(None) == _lib.ERR_BAD_PLAN
+    assert L.mgemm_grouped_plan_launch(None, None) == _lib.ERR_BAD_PLAN
+    assert L.mgemm_grouped_plan_run(None, None) == _lib.ERR_BAD_PLAN
+    t, w = ctypes.c_int64(), ctypes.c_int64()
+    assert L.mgemm_grouped_plan_info(None, ctypes.byref(t), ctypes.byref(w)) == _lib.ERR_BAD_PLAN

@@ -1,0 +1,121 @@
+"""FP32 path on the GPU against the FP64 oracle (element by element)."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1912_04379_amd as mg
+import synth
+from gpu_util import full_check, log, logical_c, padding_untouched, run, sampled_check
+
+pytestmark = pytest.mark.gpu
+
+TRANS = [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")]
+
+
+def test_small_square_unpadded():
+    """256^3, NN, ld 256, alpha 1, beta 0, uniform inputs, seed 0."""
+    c = synth.sgemm_case(0, "N", "N", 256, 256, 256, pad=0)
+    log("f32 256^3 NN")
+    err = full_check(c, run(c))
+    log("normwise %.3e" % err)
+
+
+@pytest.mark.parametrize("ta,tb", TRANS)
+@pytest.mark.parametrize("n", [1000, 1024])
+def test_square_all_trans_full(ta, tb, n):
+    c = synth.sgemm_case(0, ta, tb, n, n, n, alpha=1.5, beta=-0.5)
+    log("f32 %d^3 %s%s" % (n, ta, tb))
+    full_check(c, run(c))
+
+
+@pytest.mark.parametrize("ta,tb", TRANS)
+@pytest.mark.parametrize("n", [2048, 3001, 4096, 4097, 8192])
+def test_square_all_trans_sampled(ta, tb, n):
+    c = synth.sgemm_case(0, ta, tb, n, n, n, alpha=1.5, beta=-0.5)
+    log("f32 %d^3 %s%s (sampled)" % (n, ta, tb))
+    sampled_check(c, run(c), count=1500)
+
+
+@pytest.mark.parametrize("ta,tb", TRANS)
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 37, 5), (37, 1, 5), (33, 65, 7),
+                                   (127, 129, 1), (130, 3, 300), (5, 300, 17),
+                                   (257, 255, 33), (64, 64, 64)])
+def test_ragged_shapes(ta, tb, shape):
+    M, N, K = shape
+    c = synth.sgemm_case(7, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=5)
+    log("f32 ragged %s %s%s" % (shape, ta, tb))
+    full_check(c, run(c))
+
+
+@pytest.mark.parametrize("cfg", range(4))
+@pytest.mark.parametrize("ta,tb", TRANS)
+def test_every_config(cfg, ta, tb):
+    c = synth.sgemm_case(3, ta, tb, 300, 270, 77, alpha=1.5, beta=-0.5, pad=3)
+    log("f32 cfg %d %s%s" % (cfg, ta, tb))
+    full_check(c, run(c, config=cfg))
+
+
+@pytest.mark.parametrize("ta,tb", TRANS)
+def test_integer_inputs_bitwise(ta, tb):
+    """Integer inputs in [-16, 16]: every partial sum is an exact integer in
+    FP32, so the GPU result equals the oracle bitwise in any order."""
+    c = synth.sgemm_case(9, ta, tb, 200, 190, 260, alpha=1.0, beta=1.0, dist="int16",
+                         dist_c="int16")
+    got = logical_c(run(c), c)
+    ref = oracle.sgemm(*(c[k] for k in ("transA", "transB", "M", "N", "K", "alpha", "A",
+                                         "lda", "B", "ldb", "beta", "C", "ldc")))
+    assert np.array_equal(got, ref)
+
+
+def test_identity_is_exact():
+    n, N = 160, 70
+    rng = np.random.default_rng(4)
+    A = np.eye(n, dtype=np.float32).ravel(order="F")
+    B = synth.matrix(rng, n, N, n + 4)
+    C = synth.matrix(rng, n, N, n, pad=synth.C_SENTINEL)
+    c = dict(transA="N", transB="N", M=n, N=N, K=n, alpha=np.float32(1), beta=np.float32(0),
+             A=A, lda=n, B=B, ldb=n + 4, C=C, ldc=n)
+    got = logical_c(run(c), c)
+    assert np.array_equal(got, B.reshape(N, n + 4)[:, :n].T.astype(np.float64))
+
+
+def test_k_zero_and_alpha_zero():
+    for K, alpha, beta in ((0, 1.0, -0.5), (40, 0.0, 2.0), (40, 0.0, 0.0)):
+        c = synth.sgemm_case(5, "N", "N", 70, 50, K, alpha=alpha, beta=beta, pad=2)
+        got = run(c)
+        want = np.float64(beta) * logical_c(c["C"], c) if beta != 0 else 0.0 * logical_c(c["C"], c)
+        assert np.array_equal(logical_c(got, c), want)
+        assert padding_untouched(got, c)
+
+
+def test_beta_zero_ignores_nan_in_c():
+    c = synth.sgemm_case(6, "T", "N", 90, 80, 70, pad=2)
+    c["C"] = np.where(c["C"] == synth.C_SENTINEL, c["C"], np.float32(np.nan)).astype(np.float32)
+    got = run(c)
+    assert np.all(np.isfinite(logical_c(got, c)))
+
+
+def test_alpha_zero_beta_one_leaves_c():
+    c = synth.sgemm_case(6, "N", "N", 30, 20, 10, alpha=0.0, beta=1.0)
+    got = run(c)
+    assert np.array_equal(got, c["C"])
+
+
+def test_side_stream_and_default_stream():
+    import torch
+    c = synth.sgemm_case(8, "N", "T", 500, 400, 300, alpha=1.5, beta=-0.5)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        got = run(c, stream=s)
+    full_check(c, got)
+    full_check(c, run(c, stream=0))
+
+
+def test_nan_in_a_row_reaches_that_row_only():
+    c = synth.sgemm_case(10, "N", "N", 100, 60, 50, pad=1)
+    A = c["A"].copy()
+    A[17 + 3 * c["lda"]] = np.nan       # op(A)[17, 3]
+    c["A"] = A
+    got = logical_c(run(c), c)
+    assert np.all(np.isnan(got[17, :]))
+    assert np.all(np.isfinite(np.delete(got, 17, axis=0)))
