@@ -1,0 +1,240 @@
+"""Benchmark: SGEMM TFLOP/s at M=N=K=8192 on one MI355X, the BF16x3 and
+scaled-FP16 forms beside it, and the FP64 oracle on the host's cores.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one C <- alpha op(A) op(B) + beta C call at M=N=K=8192, NN,
+lda=ldb=ldc=8208 (stored rows + 16, the padded-stride analogue of the
+paper's Section 4 method), alpha=1.5, beta=-0.5, A/B/C uniform on [-1, 1)
+from seed 0.  Inputs are resident in HBM before timing starts.  W untimed
+steps, then exactly K steps between two synchronisations, timed with HIP
+events on the stream the kernels run on.  One JSON line goes to stdout;
+progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SGEMM TFLOP/s @N=8192 & % of peak; bf16x3-vs-fp32 speedup at equal error"
+PEAK = {"fp32": 157.3, "bf16": 2516.6, "fp16": 2516.6}     # dense MFMA, TFLOP/s
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+KERNEL_SOURCES = {
+    "fp32": ["sgemm_f32.hip", "tile_common.hpp"],
+    "bf16x3": ["sgemm_lowp.hip", "tile_common.hpp"],
+    "fp16s": ["sgemm_lowp.hip", "tile_common.hpp"],
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash(prec):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES[prec]:
+        p = os.path.join(ROOT, "paper_1912_04379_amd", "csrc", f)
+        if os.path.exists(p):
+            h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key, prec):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None
+    when none exist or the kernel source changed since they were taken."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))[key]
+    except (OSError, KeyError, ValueError):
+        return None
+    if rec.get("source_sha") != source_hash(prec):
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def cold_time(fn, reps, stream, flush):
+    """Median time of one call after writing a 512 MB buffer (evicts L2 and
+    the MALL), as the paper flushes caches between calls."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        flush.zero_()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--size", type=int, default=8192)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="time only the FP32 path (for profiling runs)")
+    ap.add_argument("--cold-reps", type=int, default=7)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(asked for --gpus %d, WORLD_SIZE %d)" % (args.gpus, world), file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1912_04379_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    import oracle
+    import paper_1912_04379_amd as mg
+    import synth
+
+    n = args.size
+    alpha, beta = 1.5, -0.5
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+
+    log("generating inputs %d^3 ..." % n)
+    case = synth.sgemm_case(0, "N", "N", n, n, n, alpha=alpha, beta=beta, pad=16)
+    ld = case["lda"]
+    A = torch.from_numpy(case["A"]).to(dev)
+    B = torch.from_numpy(case["B"]).to(dev)
+    C0 = torch.from_numpy(case["C"]).to(dev)
+    C = C0.clone()
+    flops = 2.0 * n * n * n
+
+    def call(prec, out):
+        return lambda: mg.sgemm("N", "N", n, n, n, alpha, A, ld, B, ld, beta, out, ld,
+                                precision=prec)
+
+    # Error on sampled entries, from a fresh C0 each time (beta != 0).
+    rows, cols = synth.sample_entries(1, n, n, 2048)
+    log("oracle on %d sampled entries ..." % rows.size)
+    ref = oracle.sgemm_entries("N", "N", n, n, n, alpha, case["A"], ld, case["B"], ld, beta,
+                               case["C"], ld, rows, cols)
+
+    def error_of(prec):
+        C.copy_(C0)
+        call(prec, C)()
+        torch.cuda.synchronize()
+        got = C.view(n, ld)[torch.from_numpy(cols).to(dev), torch.from_numpy(rows).to(dev)]
+        return oracle.normwise_rel_err(got.double().cpu().numpy(), ref)
+
+    results = {}
+    forms = ["fp32"] if args.no_forms else ["fp32", "bf16x3", "fp16s"]
+    flush = torch.empty(512 * 2 ** 20 // 4, dtype=torch.float32, device=dev)
+    for prec in forms:
+        if mg.config_count(prec) == 0:
+            continue
+        err = error_of(prec)
+        log("%s: sampled normwise error %.3e; timing ..." % (prec, err))
+        ms = timed(call(prec, C), args.steps, args.warmup, stream)
+        cold = cold_time(call(prec, C), args.cold_reps, stream, flush) if args.cold_reps else None
+        results[prec] = dict(ms=ms, cold_ms=cold, tflops=flops / ms / 1e9, err=err,
+                             cfg=mg.default_config(prec, "N", "N", n, n, n))
+        log("%s: %.3f ms/call warm, %s ms cold, %.1f TFLOP/s" %
+            (prec, ms, "%.3f" % cold if cold else "-", results[prec]["tflops"]))
+
+    if args.copy_calibration:
+        src = torch.empty(2 ** 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+
+    f32 = results["fp32"]
+    line = {
+        "metric": METRIC,
+        "value": round(f32["tflops"], 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(f32["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "sgemm NN M=N=K=%d lda=ldb=ldc=%d alpha=1.5 beta=-0.5 "
+                               "uniform[-1,1) seed 0" % (n, ld),
+                   "M": n, "N": n, "K": n, "trans": "NN", "ld": ld,
+                   "tile_config": f32["cfg"]},
+        "pct_of_fp32_mfma_peak": round(100.0 * f32["tflops"] / PEAK["fp32"], 2),
+        "fp32_normwise_err": f32["err"],
+        "fp32_cold_ms": f32["cold_ms"],
+    }
+    key = "sgemm_f32_nn_%d" % n
+    traffic = measured_traffic(key, "fp32")
+    line["roofline"] = {"bound": "mfma", "achieved": round(f32["tflops"], 3),
+                        "peak": PEAK["fp32"], "unit": "TFLOP/s",
+                        "frac": round(f32["tflops"] / PEAK["fp32"], 4),
+                        "traffic": traffic}
+    if "bf16x3" in results:
+        b = results["bf16x3"]
+        line["bf16x3"] = {"tflops": round(b["tflops"], 3), "ms": round(b["ms"], 4),
+                          "cold_ms": b["cold_ms"],
+                          "speedup_vs_fp32": round(f32["ms"] / b["ms"], 3),
+                          "normwise_err": b["err"],
+                          "both_within_1e-5": bool(b["err"] <= 1e-5 and f32["err"] <= 1e-5),
+                          "mfma_frac": round(3 * b["tflops"] / PEAK["bf16"], 4)}
+    if "fp16s" in results:
+        h = results["fp16s"]
+        line["fp16s"] = {"tflops": round(h["tflops"], 3), "ms": round(h["ms"], 4),
+                         "cold_ms": h["cold_ms"],
+                         "speedup_vs_fp32": round(f32["ms"] / h["ms"], 3),
+                         "normwise_err": h["err"],
+                         "mfma_frac": round(h["tflops"] / PEAK["fp16"], 4)}
+
+    if not args.no_cpu_baseline:
+        # The oracle on columns 0..J-1 of the same product (every entry of a
+        # column is one 8192-long FP64 dot product).
+        J = max(1, min(n, 2048 * 8192 // n * 8192 // n))
+        log("cpu baseline: oracle on %d columns ..." % J)
+        t0 = time.perf_counter()
+        oracle.sgemm("N", "N", n, J, n, alpha, case["A"], ld, case["B"], ld, beta,
+                     case["C"], ld)
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {
+            "value": round(2.0 * n * n * J / dt / 1e12, 6), "unit": "TFLOP/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "FP64 oracle, columns 0..%d of the same %d^3 NN product "
+                      "(%d x %d outputs), %.1f s" % (J - 1, n, n, J, dt)}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -44,8 +44,15 @@ def lib():
         L.oracle_dgemm.argtypes = L.oracle_sgemm.argtypes
         for f in (L.oracle_sgemm, L.oracle_sgemm_entries, L.oracle_dgemm):
             f.restype = ctypes.c_int
+        L.oracle_num_threads.argtypes = []
+        L.oracle_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def num_threads():
+    """Threads the oracle's parallel loops use."""
+    return lib().oracle_num_threads()
 
 
 def _ptr(a):

@@ -41,6 +41,7 @@
  * dimension too small, sampled index out of range), -2 when host memory
  * for the FP64 copies of the operands cannot be allocated.
  */
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 
@@ -202,4 +203,10 @@ int oracle_dgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
 {
     return gemm_full(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta,
                      C0, ldc, 1, out, ldo);
+}
+
+/* Number of threads the parallel loops above use (OpenMP's maximum). */
+int oracle_num_threads(void)
+{
+    return omp_get_max_threads();
 }

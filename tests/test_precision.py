@@ -1,0 +1,159 @@
+"""BF16x3 and scaled-FP16 forms on the GPU against the FP64 oracle.
+
+Two checks per case:
+* against the exact product: normwise error within the stated tolerance
+  (BF16x3 <= 1e-5, FP16s <= 1e-3);
+* against the oracle's FP64 evaluation of the same form (same splits and
+  scalings, exact sums): the difference must be pure FP32 accumulation
+  error, gamma_n |terms| elementwise.  A dropped or doubled correction
+  term, a wrong scale or a wrong rounding mode fails this by orders of
+  magnitude.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from gpu_util import log, logical_c, padding_untouched, run, sampled_check
+
+pytestmark = pytest.mark.gpu
+
+TRANS = [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")]
+FORMS = {"bf16x3": (oracle.bf16x3, 1e-5), "fp16s": (oracle.f16_scaled, 1e-3)}
+
+
+def args_of(c):
+    return (c["transA"], c["transB"], c["M"], c["N"], c["K"], c["alpha"], c["A"], c["lda"],
+            c["B"], c["ldb"], c["beta"], c["C"], c["ldc"])
+
+
+def abs_case(c):
+    d = dict(c)
+    d["A"] = np.abs(np.where(np.isfinite(c["A"]), c["A"], 0)).astype(np.float32)
+    d["B"] = np.abs(np.where(np.isfinite(c["B"]), c["B"], 0)).astype(np.float32)
+    d["C"] = np.abs(c["C"]).astype(np.float32)
+    d["alpha"], d["beta"] = abs(c["alpha"]), abs(c["beta"])
+    return d
+
+
+def check_form(c, prec, got_buf):
+    emulate, tol = FORMS[prec]
+    got = logical_c(got_buf, c)
+    assert padding_untouched(got_buf, c), "C padding was written"
+    assert np.all(np.isfinite(got))
+    exact = oracle.sgemm(*args_of(c))
+    err = oracle.normwise_rel_err(got, exact)
+    assert err <= tol, "%s normwise error %.3e > %.0e" % (prec, err, tol)
+    emu = emulate(*args_of(c))
+    if prec == "fp16s":
+        # FP16 rounding and power-of-two scaling commute with |.|, so the
+        # form applied to |A|, |B| sums the magnitudes of its own terms.
+        mag = emulate(*args_of(abs_case(c)))
+    else:
+        # |hi| <= |x| (1 + 2^-8) and |lo| <= 2^-8 |x|: the three terms sum
+        # to at most (1 + 2^-6) |a||b| in magnitude.
+        mag = (1 + 2.0 ** -6) * oracle.abs_product(*args_of(c))
+    nterms = 3 * c["K"] + 2 if prec == "bf16x3" else c["K"] + 2
+    bound = oracle.gamma(nterms, 2.0 ** -23) * mag
+    bad = np.abs(got - emu) > bound
+    assert not bad.any(), "%s differs from its FP64 emulation beyond FP32 rounding at %s" % (
+        prec, np.argwhere(bad)[:4])
+    return err
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+@pytest.mark.parametrize("ta,tb", TRANS)
+@pytest.mark.parametrize("shape", [(256, 256, 256), (300, 270, 77), (33, 65, 7),
+                                   (1, 1, 1), (129, 5, 1000)])
+def test_forms_small(prec, ta, tb, shape):
+    M, N, K = shape
+    c = synth.sgemm_case(31, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=3)
+    log("%s %s %s%s" % (prec, shape, ta, tb))
+    check_form(c, prec, run(c, precision=prec))
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+@pytest.mark.parametrize("cfg", range(4))
+def test_forms_every_config(prec, cfg):
+    c = synth.sgemm_case(32, "T", "N", 520, 390, 200, alpha=1.5, beta=-0.5, dist="loguni")
+    log("%s cfg %d" % (prec, cfg))
+    check_form(c, prec, run(c, precision=prec, config=cfg))
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+def test_wide_range_inputs_2048(prec):
+    """Sign-random magnitudes 2**U[-8, 8], NN at 2048^3, lda = rows + 16,
+    alpha 1, beta 0: the error is the product's own."""
+    c = synth.sgemm_case(0, "N", "N", 2048, 2048, 2048, dist="loguni")
+    log("%s 2048^3 loguni" % prec)
+    err = check_form(c, prec, run(c, precision=prec))
+    log("normwise %.3e" % err)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+def test_wide_range_inputs_8192_sampled(prec):
+    c = synth.sgemm_case(0, "N", "N", 8192, 8192, 8192, dist="loguni")
+    log("%s 8192^3 loguni (sampled)" % prec)
+    err = sampled_check(c, run(c, precision=prec), count=1500, bound_fn=None,
+                        normwise=FORMS[prec][1])
+    log("sampled normwise %.3e" % err)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+@pytest.mark.parametrize("ta,tb", TRANS)
+def test_integer_inputs_bitwise(prec, ta, tb):
+    """|v| <= 16 is exact in BF16 and in scaled FP16: both forms equal the
+    oracle bitwise."""
+    c = synth.sgemm_case(33, ta, tb, 200, 170, 300, alpha=1.0, beta=1.0, dist="int16",
+                         dist_c="int16")
+    got = logical_c(run(c, precision=prec), c)
+    assert np.array_equal(got, oracle.sgemm(*args_of(c)))
+
+
+def test_bf16x3_identity_within_split_residue():
+    """op(A) = I: C = hi(B) + lo(B), within 2**-16 |B| elementwise."""
+    n, N = 96, 50
+    rng = np.random.default_rng(4)
+    A = np.eye(n, dtype=np.float32).ravel(order="F")
+    B = synth.matrix(rng, n, N, n, dist="loguni")
+    C = np.zeros(n * N, dtype=np.float32)
+    c = dict(transA="N", transB="N", M=n, N=N, K=n, alpha=np.float32(1), beta=np.float32(0),
+             A=A, lda=n, B=B, ldb=n, C=C, ldc=n)
+    got = logical_c(run(c, precision="bf16x3"), c)
+    Bl = B.reshape(N, n).T.astype(np.float64)
+    assert np.all(np.abs(got - Bl) <= 2.0 ** -16 * np.abs(Bl))
+
+
+@pytest.mark.parametrize("scale", [1e-6, 1e6])
+def test_fp16s_extreme_magnitudes(scale):
+    """Values far outside FP16's range (or below its normal range) are
+    brought into range by the panel scaling: error stays within 1e-3."""
+    c = synth.sgemm_case(34, "N", "T", 300, 200, 150)
+    c["A"] = (c["A"] * np.float32(scale)).astype(np.float32)
+    c["B"] = (c["B"] * np.float32(scale)).astype(np.float32)
+    check_form(c, "fp16s", run(c, precision="fp16s"))
+
+
+def test_fp16s_panels_with_different_scales():
+    """Each 32-row panel of op(A) gets its own scale: rows 0..31 tiny, rows
+    32..63 huge, a zero panel, and the ragged last panel."""
+    M, N, K = 100, 70, 90
+    c = synth.sgemm_case(35, "N", "N", M, N, K)
+    A = c["A"].reshape(K, c["lda"]).copy()
+    A[:, 0:32] *= np.float32(1e-5)
+    A[:, 32:64] *= np.float32(3e4)
+    A[:, 64:96] = 0
+    c["A"] = A.reshape(-1).astype(np.float32)
+    got = run(c, precision="fp16s")
+    check_form(c, "fp16s", got)
+    assert np.all(logical_c(got, c)[64:96, :] == 0)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+def test_forms_alpha_beta_rules(prec):
+    c = synth.sgemm_case(36, "N", "N", 64, 48, 40, alpha=0.0, beta=-0.5)
+    got = run(c, precision=prec)
+    assert np.array_equal(logical_c(got, c), -0.5 * logical_c(c["C"], c))
+    c = synth.sgemm_case(36, "T", "T", 64, 48, 40)
+    c["C"] = np.where(c["C"] == synth.C_SENTINEL, c["C"], np.float32(np.nan)).astype(np.float32)
+    assert np.all(np.isfinite(logical_c(run(c, precision=prec), c)))
