@@ -13,6 +13,8 @@
 //                 while the MFMAs run on the current LDS buffer (two LDS
 //                 buffers, one barrier per slab);
 //   * L2 block:   XCD-aware, band-ordered tile rasterisation.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace mgemm {
@@ -32,31 +34,43 @@ struct CfgF32 {
     static_assert(BK % 8 == 0, "BK must be a multiple of 8");
 };
 
-template <int BP, int BK, int NT, bool KC>
-__device__ inline void stage_to_lds(const SlabLoader<BP, BK, NT, KC>& ld, float* Xs,
-                                    int tid) {
+template <class Loader, int BK>
+__device__ inline void stage_to_lds(const Loader& ld, float* Xs, int tid, int nt) {
     constexpr int S = BK + 4;
 #pragma unroll
-    for (int q = 0; q < SlabLoader<BP, BK, NT, KC>::PER_THREAD; ++q) {
+    for (int q = 0; q < Loader::PER_THREAD; ++q) {
         int p, kq;
-        SlabLoader<BP, BK, NT, KC>::group_pos(tid + q * NT, p, kq);
+        Loader::group_pos(tid + q * nt, p, kq);
         *reinterpret_cast<f32x4*>(Xs + p * S + 4 * kq) = ld.v[q];
     }
 }
 
 // One BM x BN tile of C at (m0, n0).  AK / BKC: op(A) / op(B) contiguous
-// along K in memory (A 'T' / B 'N').
-template <class Cfg, bool AK, bool BKC>
+// along K in memory (A 'T' / B 'N').  BUF: buffer loads and stores (every
+// leading dimension <= MAX_BUF_LD) or plain global accesses.
+template <class Cfg, bool AK, bool BKC, bool BUF>
 __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float* smem) {
     constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, NT = Cfg::NT, S = Cfg::S;
     constexpr int FM = Cfg::FM, FN = Cfg::FN;
+    using LA = typename std::conditional<BUF, SlabLoaderB<BM, BK, NT, AK>,
+                                         SlabLoaderG<BM, BK, NT, AK>>::type;
+    using LB = typename std::conditional<BUF, SlabLoaderB<BN, BK, NT, BKC>,
+                                         SlabLoaderG<BN, BK, NT, BKC>>::type;
+    using Epi = typename std::conditional<BUF, EpilogueB, EpilogueG>::type;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, h = lane >> 5;
     const int wm = (wave % Cfg::WGM) * Cfg::WM;
     const int wn = (wave / Cfg::WGM) * Cfg::WN;
 
-    SlabLoader<BM, BK, NT, AK> la;
-    SlabLoader<BN, BK, NT, BKC> lb;
+    // op(A) is M x K: stored M x K ('N') or K x M ('T'); likewise op(B) as N x K.
+    const Panel pa{d.A, d.lda, d.M, d.K,
+                   AK ? stored_extent(d.K, d.M, d.lda) : stored_extent(d.M, d.K, d.lda), m0};
+    const Panel pb{d.B, d.ldb, d.N, d.K,
+                   BKC ? stored_extent(d.K, d.N, d.ldb) : stored_extent(d.N, d.K, d.ldb), n0};
+    LA la;
+    LB lb;
+    la.init(pa, tid);
+    lb.init(pb, tid);
 
     f32x16 acc[FM][FN];
 #pragma unroll
@@ -66,10 +80,10 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
             acc[i][j] = f32x16{};
 
     const int64_t nk = (d.K + BK - 1) / BK;
-    la.load(d.A, d.lda, d.M, d.K, m0, 0, tid);
-    lb.load(d.B, d.ldb, d.N, d.K, n0, 0, tid);
-    stage_to_lds(la, smem, tid);
-    stage_to_lds(lb, smem + BM * S, tid);
+    la.load(pa, 0, tid);
+    lb.load(pb, 0, tid);
+    stage_to_lds<LA, BK>(la, smem, tid, NT);
+    stage_to_lds<LB, BK>(lb, smem + BM * S, tid, NT);
     __syncthreads();
 
     for (int64_t kt = 0; kt < nk; ++kt) {
@@ -77,8 +91,8 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
         float* nxt = smem + ((kt + 1) & 1) * Cfg::STAGE;
         const bool more = kt + 1 < nk;
         if (more) {
-            la.load(d.A, d.lda, d.M, d.K, m0, (kt + 1) * BK, tid);
-            lb.load(d.B, d.ldb, d.N, d.K, n0, (kt + 1) * BK, tid);
+            la.load(pa, (kt + 1) * BK, tid);
+            lb.load(pb, (kt + 1) * BK, tid);
         }
         const float* As = cur;
         const float* Bs = cur + BM * S;
@@ -105,29 +119,40 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
                             b[j][e], a[i][e], acc[i][j], 0, 0, 0);
         }
         if (more) {
-            stage_to_lds(la, nxt, tid);
-            stage_to_lds(lb, nxt + BM * S, tid);
+            stage_to_lds<LA, BK>(la, nxt, tid, NT);
+            stage_to_lds<LB, BK>(lb, nxt + BM * S, tid, NT);
         }
         __syncthreads();
     }
 
+    Epi epi(d, m0, n0);
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
 #pragma unroll
             for (int r = 0; r < 16; ++r)
-                store_c(d, m0 + wm + 32 * i + l32, n0 + wn + 32 * j + mfma32_row(r, lane),
-                        acc[i][j][r], 1.0f);
+                epi.store(wm + 32 * i + l32, wn + 32 * j + mfma32_row(r, lane), acc[i][j][r]);
 }
 
-template <class Cfg, bool AK, bool BKC>
+template <class Cfg, bool AK, bool BKC, bool BUF>
 __global__ __launch_bounds__(Cfg::NT) void sgemm_f32_kernel(GemmDesc d, uint32_t tiles_m,
                                                            uint32_t tiles_n) {
     __shared__ __attribute__((aligned(16))) float smem[Cfg::SMEM_FLOATS];
     uint32_t tm, tn;
     grouped_tile<8>(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
-    tile_f32<Cfg, AK, BKC>(d, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
+    tile_f32<Cfg, AK, BKC, BUF>(d, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
+}
+
+template <class Cfg, bool AK, bool BKC>
+static void launch_trans(dim3 grid, const GemmDesc& d, uint32_t tm, uint32_t tn,
+                         hipStream_t s) {
+    if (buffer_path_ok(d))
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, AK, BKC, true>), grid, dim3(Cfg::NT), 0, s,
+                           d, tm, tn);
+    else
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, AK, BKC, false>), grid, dim3(Cfg::NT), 0, s,
+                           d, tm, tn);
 }
 
 template <class Cfg>
@@ -137,17 +162,17 @@ static hipError_t launch_cfg(bool ta, bool tb, const GemmDesc& d, hipStream_t s)
     const int64_t tiles = tiles_m * tiles_n;
     if (tiles_m > 0xffffffffLL || tiles_n > 0xffffffffLL || tiles > 0xffffffffLL)
         return hipErrorInvalidValue;
-    dim3 grid((uint32_t)tiles), block(Cfg::NT);
+    dim3 grid((uint32_t)tiles);
     const uint32_t tmm = (uint32_t)tiles_m, tnn = (uint32_t)tiles_n;
     // op(A) is K-contiguous for A 'T'; op(B) is K-contiguous for B 'N'.
     if (!ta && !tb)
-        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, false, true>), grid, block, 0, s, d, tmm, tnn);
+        launch_trans<Cfg, false, true>(grid, d, tmm, tnn, s);
     else if (!ta && tb)
-        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, false, false>), grid, block, 0, s, d, tmm, tnn);
+        launch_trans<Cfg, false, false>(grid, d, tmm, tnn, s);
     else if (ta && !tb)
-        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, true, true>), grid, block, 0, s, d, tmm, tnn);
+        launch_trans<Cfg, true, true>(grid, d, tmm, tnn, s);
     else
-        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, true, false>), grid, block, 0, s, d, tmm, tnn);
+        launch_trans<Cfg, true, false>(grid, d, tmm, tnn, s);
     return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@
 // chunk c of row p sits at chunk slot c ^ ((p >> 2) & 3), so the 16 lanes
 // that read one 16-byte chunk of 16 consecutive rows hit 16 distinct slots
 // (no bank conflicts) without padding.
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace mgemm {
@@ -74,14 +76,14 @@ __device__ inline u32x2 scale_f16x4(const f32x4& v, int e) {
 // Write one register-staged slab (BP rows) into LDS.  `hi` / `lo` are the
 // two arrays of the BF16x3 form; the FP16 form uses `hi` only, with the
 // exponent of each 32-row panel from `expo` (indexed from panel p0/32).
-template <Form F, int BP, int NT, bool KC>
-__device__ inline void stage_lowp(const SlabLoader<BP, 32, NT, KC>& ld, char* hi, char* lo,
+template <Form F, class Loader, int NT>
+__device__ inline void stage_lowp(const Loader& ld, char* hi, char* lo,
                                   const int* __restrict__ expo, int64_t panel0, int64_t panels,
                                   int tid) {
 #pragma unroll
-    for (int q = 0; q < SlabLoader<BP, 32, NT, KC>::PER_THREAD; ++q) {
+    for (int q = 0; q < Loader::PER_THREAD; ++q) {
         int p, kq;
-        SlabLoader<BP, 32, NT, KC>::group_pos(tid + q * NT, p, kq);
+        Loader::group_pos(tid + q * NT, p, kq);
         const int off = chunk_off(p, kq >> 1) + ((kq & 1) << 3);
         if constexpr (F == Form::BF16X3) {
             u32x2 h, l;
@@ -96,7 +98,7 @@ __device__ inline void stage_lowp(const SlabLoader<BP, 32, NT, KC>& ld, char* hi
     }
 }
 
-template <class Cfg, Form F, bool AK, bool BKC>
+template <class Cfg, Form F, bool AK, bool BKC, bool BUF>
 __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char* smem) {
     constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, NT = Cfg::NT;
     constexpr int FM = Cfg::FM, FN = Cfg::FN;
@@ -108,8 +110,19 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
     const int wn = (wave / Cfg::WGM) * Cfg::WN;
     const int64_t pan_a = (d.M + 31) / 32, pan_b = (d.N + 31) / 32;
 
-    SlabLoader<BM, BK, NT, AK> la;
-    SlabLoader<BN, BK, NT, BKC> lb;
+    using LA = typename std::conditional<BUF, SlabLoaderB<BM, BK, NT, AK>,
+                                         SlabLoaderG<BM, BK, NT, AK>>::type;
+    using LB = typename std::conditional<BUF, SlabLoaderB<BN, BK, NT, BKC>,
+                                         SlabLoaderG<BN, BK, NT, BKC>>::type;
+    using Epi = typename std::conditional<BUF, EpilogueB, EpilogueG>::type;
+    const Panel pa{d.A, d.lda, d.M, d.K,
+                   AK ? stored_extent(d.K, d.M, d.lda) : stored_extent(d.M, d.K, d.lda), m0};
+    const Panel pb{d.B, d.ldb, d.N, d.K,
+                   BKC ? stored_extent(d.K, d.N, d.ldb) : stored_extent(d.N, d.K, d.ldb), n0};
+    LA la;
+    LB lb;
+    la.init(pa, tid);
+    lb.init(pb, tid);
 
     f32x16 acc[FM][FN];
 #pragma unroll
@@ -123,14 +136,13 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
     auto put = [&](int s) {
         char* base = stage_ptr(s);
         char* lo = base + ARR;
-        stage_lowp<F, BM, NT, AK>(la, base, lo, d.expA, m0 / 32, pan_a, tid);
-        stage_lowp<F, BN, NT, BKC>(lb, base + BM * 64, lo + BM * 64, d.expB, n0 / 32, pan_b,
-                                   tid);
+        stage_lowp<F, LA, NT>(la, base, lo, d.expA, m0 / 32, pan_a, tid);
+        stage_lowp<F, LB, NT>(lb, base + BM * 64, lo + BM * 64, d.expB, n0 / 32, pan_b, tid);
     };
 
     const int64_t nk = (d.K + BK - 1) / BK;
-    la.load(d.A, d.lda, d.M, d.K, m0, 0, tid);
-    lb.load(d.B, d.ldb, d.N, d.K, n0, 0, tid);
+    la.load(pa, 0, tid);
+    lb.load(pb, 0, tid);
     put(0);
     __syncthreads();
 
@@ -138,8 +150,8 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
         const int cur = (int)(kt & 1);
         const bool more = kt + 1 < nk;
         if (more) {
-            la.load(d.A, d.lda, d.M, d.K, m0, (kt + 1) * BK, tid);
-            lb.load(d.B, d.ldb, d.N, d.K, n0, (kt + 1) * BK, tid);
+            la.load(pa, (kt + 1) * BK, tid);
+            lb.load(pb, (kt + 1) * BK, tid);
         }
         const char* Ah = stage_ptr(cur);
         const char* Bh = Ah + BM * 64;
@@ -197,6 +209,7 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
         __syncthreads();
     }
 
+    Epi epi(d, m0, n0);
 #pragma unroll
     for (int i = 0; i < FM; ++i)
 #pragma unroll
@@ -209,19 +222,18 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const float v = F == Form::F16S ? ldexpf(acc[i][j][r], sh) : acc[i][j][r];
-                store_c(d, m0 + wm + 32 * i + l32, n0 + wn + 32 * j + mfma32_row(r, lane), v,
-                        1.0f);
+                epi.store(wm + 32 * i + l32, wn + 32 * j + mfma32_row(r, lane), v);
             }
         }
 }
 
-template <class Cfg, Form F, bool AK, bool BKC>
+template <class Cfg, Form F, bool AK, bool BKC, bool BUF>
 __global__ __launch_bounds__(Cfg::NT) void sgemm_lowp_kernel(GemmDesc d, uint32_t tiles_m,
                                                             uint32_t tiles_n) {
     extern __shared__ __attribute__((aligned(16))) char lowp_smem[];
     uint32_t tm, tn;
     grouped_tile<8>(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
-    tile_lowp<Cfg, F, AK, BKC>(d, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, lowp_smem);
+    tile_lowp<Cfg, F, AK, BKC, BUF>(d, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, lowp_smem);
 }
 
 template <class Cfg, Form F>
@@ -229,11 +241,11 @@ constexpr int lowp_smem_bytes() {
     return 2 * (F == Form::BF16X3 ? 2 : 1) * (Cfg::BM + Cfg::BN) * Cfg::ROW_BYTES;
 }
 
-template <class Cfg, Form F, bool AK, bool BKC>
-static hipError_t launch_one(dim3 grid, const GemmDesc& d, uint32_t tm, uint32_t tn,
-                             hipStream_t s) {
+template <class Cfg, Form F, bool AK, bool BKC, bool BUF>
+static hipError_t launch_kernel(dim3 grid, const GemmDesc& d, uint32_t tm, uint32_t tn,
+                                hipStream_t s) {
     constexpr int bytes = lowp_smem_bytes<Cfg, F>();
-    auto k = sgemm_lowp_kernel<Cfg, F, AK, BKC>;
+    auto k = sgemm_lowp_kernel<Cfg, F, AK, BKC, BUF>;
     if (bytes > 65536) {
         hipError_t e = hipFuncSetAttribute((const void*)k,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -241,6 +253,13 @@ static hipError_t launch_one(dim3 grid, const GemmDesc& d, uint32_t tm, uint32_t
     }
     hipLaunchKernelGGL(k, grid, dim3(Cfg::NT), bytes, s, d, tm, tn);
     return hipGetLastError();
+}
+
+template <class Cfg, Form F, bool AK, bool BKC>
+static hipError_t launch_one(dim3 grid, const GemmDesc& d, uint32_t tm, uint32_t tn,
+                             hipStream_t s) {
+    return buffer_path_ok(d) ? launch_kernel<Cfg, F, AK, BKC, true>(grid, d, tm, tn, s)
+                             : launch_kernel<Cfg, F, AK, BKC, false>(grid, d, tm, tn, s);
 }
 
 template <class Cfg, Form F>
@@ -285,12 +304,13 @@ static hipError_t lowp_launch(int cfg, bool ta, bool tb, const GemmDesc& d, hipS
     }
 }
 
-// Largest tile that still gives every CU at least two work-groups.
+// The 256x256 tile once the chip gets at least two rounds of work-groups;
+// otherwise the tile that still gives every CU several work-groups
+// (measured at 2048^3: 64x64 beats 128x128, which leaves one tile per CU).
 static int lowp_default(int64_t M, int64_t N) {
     auto tiles = [&](int bm, int bn) { return ((M + bm - 1) / bm) * ((N + bn - 1) / bn); };
     if (tiles(256, 256) >= 512) return 0;
-    if (tiles(256, 128) >= 512) return 2;
-    if (tiles(128, 128) >= 256) return 1;
+    if (tiles(128, 128) >= 1024) return 1;
     return 3;
 }
 

@@ -72,64 +72,201 @@ __device__ inline void grouped_tile(uint32_t id, uint32_t tiles_m, uint32_t tile
 // (lanes walk along k in memory); P-contiguous panels number them
 // p-fastest (each of the 4 dword loads of a group is coalesced across
 // lanes along p).  Elements outside P x K read as 0.
+//
+// Two implementations with the same interface:
+//   SlabLoaderB  raw buffer loads.  The buffer descriptor is rebased to the
+//                slab's first element each slab (scalar work); lanes keep
+//                32-bit byte offsets computed once; a lane outside the
+//                panel uses an offset beyond the descriptor's range, which
+//                the hardware returns as 0 -- no branches.  Needs every
+//                in-slab offset below 2^31 bytes (ld <= MAX_BUF_LD).
+//   SlabLoaderG  plain 64-bit global loads with per-element predicates, for
+//                any leading dimension.
 // ---------------------------------------------------------------------------
+constexpr int64_t MAX_BUF_LD = (1LL << 21) - 64;
+constexpr uint32_t BUF_OOB = 0x80000000u;      // offset that is always out of range
+constexpr int64_t BUF_MAX_RANGE = 0x7ffffff0LL;
+
+typedef __amdgpu_buffer_rsrc_t BufRsrc;
+
+// Descriptor for `bytes` bytes at `base` (clamped below 2^31).
+__device__ inline BufRsrc make_rsrc(const void* base, int64_t bytes) {
+    const int64_t n = bytes <= 0 ? 0 : (bytes > BUF_MAX_RANGE ? BUF_MAX_RANGE : bytes);
+    // dword 3 = 0x00020000: 32-bit data format, the raw (untyped) buffer
+    // setting for gfx9-family parts.
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)n,
+                                             0x00020000);
+}
+
+__device__ inline float buf_load_f32(BufRsrc r, uint32_t off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
+__device__ inline f32x4 buf_load_f32x4(BufRsrc r, uint32_t off) {
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+__device__ inline void buf_store_f32(BufRsrc r, uint32_t off, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+}
+
+// One operand panel: stored array X (column-major, leading dimension ld,
+// `extent` referenced elements from X), panel extents P x K, first panel
+// row p0.
+struct Panel {
+    const float* X;
+    int64_t ld, P, K, extent, p0;
+};
+
 template <int BP, int BK, int NT, bool KCONTIG>
-struct SlabLoader {
+struct SlabGeom {
     static constexpr int GROUPS = BP * BK / 4;
     static constexpr int PER_THREAD = GROUPS / NT;
     static_assert(GROUPS % NT == 0, "slab must split evenly over threads");
     static_assert(BK % 4 == 0, "BK must be a multiple of 4");
 
-    f32x4 v[PER_THREAD];
-
     __device__ static inline void group_pos(int g, int& p, int& kq) {
         if (KCONTIG) { kq = g % (BK / 4); p = g / (BK / 4); }
         else         { p = g % BP;        kq = g / BP; }
     }
+};
 
-    // X: the operand base pointer; P, K: panel extents; ld: leading dim.
-    __device__ inline void load(const float* __restrict__ X, int64_t ld,
-                                int64_t P, int64_t K, int64_t p0, int64_t k0,
-                                int tid) {
+template <int BP, int BK, int NT, bool KCONTIG>
+struct SlabLoaderB : SlabGeom<BP, BK, NT, KCONTIG> {
+    using G = SlabGeom<BP, BK, NT, KCONTIG>;
+    f32x4 v[G::PER_THREAD];
+    uint32_t off[G::PER_THREAD];   // byte offset of element e = 0 of each group
+    bool pok[G::PER_THREAD];       // group's p inside the panel
+
+    __device__ inline void init(const Panel& pn, int tid) {
 #pragma unroll
-        for (int q = 0; q < PER_THREAD; ++q) {
+        for (int q = 0; q < G::PER_THREAD; ++q) {
             int p, kq;
-            group_pos(tid + q * NT, p, kq);
-            const int64_t gp = p0 + p;
+            G::group_pos(tid + q * NT, p, kq);
+            pok[q] = pn.p0 + p < pn.P;
+            off[q] = KCONTIG ? (uint32_t)(4 * (4 * kq + (int64_t)p * pn.ld))
+                             : (uint32_t)(4 * (p + (int64_t)(4 * kq) * pn.ld));
+        }
+    }
+
+    __device__ inline void load(const Panel& pn, int64_t k0, int tid) {
+        // The slab's first element and the bytes left in the array from it.
+        const int64_t first = KCONTIG ? k0 + pn.p0 * pn.ld : pn.p0 + k0 * pn.ld;
+        const BufRsrc r = make_rsrc(pn.X + first, 4 * (pn.extent - first));
+        const bool full = k0 + BK <= pn.K;
+        if (KCONTIG && full) {
+#pragma unroll
+            for (int q = 0; q < G::PER_THREAD; ++q)
+                v[q] = buf_load_f32x4(r, pok[q] ? off[q] : BUF_OOB);
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < G::PER_THREAD; ++q) {
+            int p, kq;
+            G::group_pos(tid + q * NT, p, kq);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const bool ok = pok[q] && (full || k0 + 4 * kq + e < pn.K);
+                const uint32_t step = KCONTIG ? 4u * e : (uint32_t)(4 * e * pn.ld);
+                v[q][e] = buf_load_f32(r, ok ? off[q] + step : BUF_OOB);
+            }
+        }
+    }
+};
+
+template <int BP, int BK, int NT, bool KCONTIG>
+struct SlabLoaderG : SlabGeom<BP, BK, NT, KCONTIG> {
+    using G = SlabGeom<BP, BK, NT, KCONTIG>;
+    f32x4 v[G::PER_THREAD];
+
+    __device__ inline void init(const Panel&, int) {}
+
+    __device__ inline void load(const Panel& pn, int64_t k0, int tid) {
+#pragma unroll
+        for (int q = 0; q < G::PER_THREAD; ++q) {
+            int p, kq;
+            G::group_pos(tid + q * NT, p, kq);
+            const int64_t gp = pn.p0 + p;
             const int64_t gk = k0 + 4 * kq;
-            const bool prow = gp < P;
+            const bool prow = gp < pn.P;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int64_t k = gk + e;
                 float x = 0.0f;
-                if (prow && k < K) {
-                    const int64_t off = KCONTIG ? (k + gp * ld) : (gp + k * ld);
-                    x = X[off];
-                }
+                if (prow && k < pn.K) x = pn.X[KCONTIG ? (k + gp * pn.ld) : (gp + k * pn.ld)];
                 v[q][e] = x;
             }
         }
     }
 };
 
+// Referenced elements of a stored rows x cols array with leading dim ld.
+__device__ __host__ inline int64_t stored_extent(int64_t rows, int64_t cols, int64_t ld) {
+    return rows > 0 && cols > 0 ? (cols - 1) * ld + rows : 0;
+}
+
 // ---------------------------------------------------------------------------
 // Epilogue.  The MFMA computes D[n][m] (rows of D are columns of C) so that
 // the 32 lanes of a 32x32 block hold 32 consecutive m of one column of C:
 // column-major stores are then 128-byte coalesced.  Register r of lane l in
 // a 32x32 block holds row 8*(r/4) + 4*(l/32) + (r%4) and column l%32.
+//
+// C <- alpha * acc + beta * C; beta == 0 never reads C.  EpilogueB masks
+// with out-of-range buffer offsets (a dropped store); EpilogueG with
+// predicates.
 // ---------------------------------------------------------------------------
 __device__ inline int mfma32_row(int r, int lane) {
     return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
 }
 
-__device__ inline void store_c(const GemmDesc& d, int64_t m, int64_t n, float acc,
-                               float scale) {
-    if (m < d.M && n < d.N) {
-        float* c = d.C + m + n * d.ldc;
-        float v = d.alpha * (acc * scale);
-        if (d.beta != 0.0f) v = fmaf(d.beta, *c, v);
-        *c = v;
+struct EpilogueB {
+    BufRsrc r;
+    int64_t mrem, nrem, ldc;
+    float alpha, beta;
+    __device__ inline EpilogueB(const GemmDesc& d, int64_t m0, int64_t n0) {
+        const int64_t first = m0 + n0 * d.ldc;
+        r = make_rsrc(d.C + first, 4 * (stored_extent(d.M, d.N, d.ldc) - first));
+        mrem = d.M - m0;
+        nrem = d.N - n0;
+        ldc = d.ldc;
+        alpha = d.alpha;
+        beta = d.beta;
     }
+    // (m, n) relative to the tile origin.
+    __device__ inline void store(int m, int n, float acc) {
+        const bool ok = m < mrem && n < nrem;
+        const uint32_t off = ok ? (uint32_t)(4 * (m + (int64_t)n * ldc)) : BUF_OOB;
+        float v = alpha * acc;
+        if (beta != 0.0f) v = fmaf(beta, buf_load_f32(r, off), v);
+        buf_store_f32(r, off, v);
+    }
+};
+
+struct EpilogueG {
+    float* C;
+    int64_t mrem, nrem, ldc;
+    float alpha, beta;
+    __device__ inline EpilogueG(const GemmDesc& d, int64_t m0, int64_t n0) {
+        C = d.C + m0 + n0 * d.ldc;
+        mrem = d.M - m0;
+        nrem = d.N - n0;
+        ldc = d.ldc;
+        alpha = d.alpha;
+        beta = d.beta;
+    }
+    __device__ inline void store(int m, int n, float acc) {
+        if (m < mrem && n < nrem) {
+            float* c = C + m + (int64_t)n * ldc;
+            float v = alpha * acc;
+            if (beta != 0.0f) v = fmaf(beta, *c, v);
+            *c = v;
+        }
+    }
+};
+
+// True when every leading dimension allows the buffer (32-bit offset) path.
+__host__ __device__ inline bool buffer_path_ok(const GemmDesc& d) {
+    return d.lda <= MAX_BUF_LD && d.ldb <= MAX_BUF_LD && d.ldc <= MAX_BUF_LD;
 }
 
 }  // namespace mgemm
