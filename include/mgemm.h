@@ -122,15 +122,20 @@ typedef struct mgemm_problem {
 typedef struct mgemm_plan mgemm_plan;
 
 /*
- * Build a plan for `count` problems (host array, copied): validates every
- * problem (on failure returns MGEMM_ERR_BAD_PROBLEM with *bad_index set and
- * *bad_status the BLAS-style code of the first bad argument), picks a tile
- * configuration per problem from `bucket_configs` (an array of 4 entries
- * indexed by size bucket, see mgemm_grouped_bucket; NULL = library
- * defaults), uploads the descriptor table and tile list to device memory,
- * and records one launch of the persistent grouped kernel on `stream` into
- * a HIP graph.  The C_i must not overlap each other.  Device memory owned
- * by the plan is freed by mgemm_grouped_plan_destroy.
+ * Build a plan for `count` problems (host array, copied).  Precision is
+ * MGEMM_PREC_FP32 or MGEMM_PREC_BF16X3.  Every problem is validated with
+ * the rules above; on failure the call returns MGEMM_ERR_BAD_PROBLEM with
+ * *bad_index set to the problem and *bad_status to its BLAS-style code
+ * (or MGEMM_ERR_ALIAS / MGEMM_ERR_UNSUPPORTED).  No C may overlap another
+ * problem's C, A or B.  Leading dimensions must not exceed 2^21 - 64.
+ * Problems are sorted into four size buckets (mgemm_grouped_bucket); each
+ * bucket uses one tile variant (0 .. mgemm_grouped_variant_count()-1) from
+ * `bucket_configs` (4 entries; NULL = library defaults, e.g. from
+ * mgemm_grouped_tune).  The plan uploads a descriptor table and a tile
+ * list ordered longest-first to device memory it owns, and records one
+ * launch of the persistent grouped kernel into a HIP graph (on a private
+ * stream; `stream` is unused and may be NULL).  Results are bitwise
+ * reproducible: every tile of C is written by one work-group, no atomics.
  */
 int mgemm_grouped_plan_create(const mgemm_problem *problems, int64_t count,
                               int precision, const int *bucket_configs,
@@ -147,12 +152,33 @@ int mgemm_grouped_plan_run(mgemm_plan *plan, void *stream);
 int mgemm_grouped_plan_info(const mgemm_plan *plan, int64_t *tiles,
                             int64_t *workgroups);
 
-/* Free the plan (waits for nothing: the caller synchronises first).
- * A NULL or already destroyed plan returns MGEMM_ERR_BAD_PLAN. */
+/* Free the plan and its device memory (the caller synchronises first:
+ * nothing waits for launches in flight).  A NULL or already destroyed plan
+ * returns MGEMM_ERR_BAD_PLAN. */
 int mgemm_grouped_plan_destroy(mgemm_plan *plan);
 
-/* Size bucket (0..3) of a grouped problem, by max(M, N). */
+/* Size bucket (0..3) of a grouped problem: max(M, N) <= 64, <= 128,
+ * <= 256, > 256. */
 int mgemm_grouped_bucket(int64_t M, int64_t N, int64_t K);
+
+/* Number of tile variants of the grouped kernel for a precision (0 when
+ * grouped plans do not support it), and the tile shape of one variant. */
+int mgemm_grouped_variant_count(int precision);
+int mgemm_grouped_variant_info(int precision, int variant, int *bm, int *bn,
+                               int *bk);
+
+/*
+ * Autotuner: choose the variant of every size bucket present in the batch
+ * by timing the whole grouped launch on `stream` (best of `reps` timed
+ * runs after one warm-up, HIP events), one bucket at a time, starting from
+ * the defaults.  Writes 4 entries to bucket_configs and the best time in
+ * milliseconds to *best_ms (may be NULL).  The problems are RUN: every C
+ * is overwritten with unspecified values, so tune on scratch outputs or
+ * re-initialise C afterwards.  Synchronises `stream`.
+ */
+int mgemm_grouped_tune(const mgemm_problem *problems, int64_t count,
+                       int precision, void *stream, int reps,
+                       int *bucket_configs, float *best_ms);
 
 /* ---- status ------------------------------------------------------------ */
 

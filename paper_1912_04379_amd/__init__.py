@@ -12,9 +12,18 @@ current HIP stream.  PyTorch supplies device memory and streams.
 """
 from ._lib import (MgemmError, PREC_BF16X3, PREC_FP16_SCALED, PREC_FP32, PRECISIONS,
                    check, lib)
-from .api import (config_count, config_info, default_config, matmul, sgemm, stream_handle,
-                  version)
+from .api import (config_count, config_info, default_config, matmul, matmul_args, sgemm,
+                  stream_handle, version)
 
-__all__ = ["MgemmError", "PREC_FP32", "PREC_BF16X3", "PREC_FP16_SCALED", "PRECISIONS",
-           "sgemm", "matmul", "config_count", "config_info", "default_config",
-           "version", "lib", "check", "stream_handle"]
+
+def linear(X, W, precision="fp32"):
+    """Y = X @ W with the hand-written backward (see autograd.py)."""
+    from .autograd import linear as _linear
+    return _linear(X, W, precision)
+
+
+from .grouped import GroupedPlan, tune as tune_grouped  # noqa: E402
+
+__all__ = ["GroupedPlan", "tune_grouped", "MgemmError", "PREC_FP32", "PREC_BF16X3", "PREC_FP16_SCALED", "PRECISIONS",
+           "sgemm", "matmul", "matmul_args", "linear", "config_count", "config_info",
+           "default_config", "version", "lib", "check", "stream_handle"]

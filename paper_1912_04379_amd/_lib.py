@@ -57,6 +57,11 @@ _SIGS = {
     "mgemm_grouped_plan_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),
     "mgemm_grouped_plan_destroy": (_i32, [_vp]),
     "mgemm_grouped_bucket": (_i32, [_i64, _i64, _i64]),
+    "mgemm_grouped_variant_count": (_i32, [_i32]),
+    "mgemm_grouped_variant_info": (_i32, [_i32, _i32, ctypes.POINTER(_i32),
+                                          ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "mgemm_grouped_tune": (_i32, [ctypes.POINTER(Problem), _i64, _i32, _vp, _i32,
+                                  ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)]),
     "mgemm_status_string": (ctypes.c_char_p, [_i32]),
     "mgemm_last_error": (ctypes.c_char_p, []),
     "mgemm_version": (_i32, []),

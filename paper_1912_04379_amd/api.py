@@ -58,17 +58,31 @@ def sgemm(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, *,
     return check(st)
 
 
-def colmajor_view(T):
-    """How a 2-D tensor T (r x c, torch semantics) enters a column-major
-    product as its transpose T^T: returns (trans, ld) such that op(X) = T^T
-    where X is the stored array at T.data_ptr().
+def matmul_args(x_shape, x_strides, w_shape, w_strides):
+    """Column-major SGEMM arguments for Y = X @ W with a row-major (b x o) Y.
 
-    A row-major T (stride (ld, 1)) is stored column-major as T^T (c x r):
-    op 'N'.  A column-major T (stride (1, ld)), e.g. a transposed view, is
-    stored as T itself: op 'T'.
+    Row-major Y is the column-major array Y^T (o x b, ld o), and
+    Y^T = W^T X^T: op(A) = W^T comes from W's storage, op(B) = X^T from X's.
+    Returns (transA, transB, M, N, K, lda, ldb, ldc).  Pure host logic.
     """
-    r, c = T.shape
-    s0, s1 = T.stride()
+    b, i = x_shape
+    i2, o = w_shape
+    if i != i2:
+        raise ValueError("inner dimensions differ: %d vs %d" % (i, i2))
+    tw, ldw = _view(w_shape, w_strides)
+    tx, ldx = _view(x_shape, x_strides)
+    return tw, tx, o, b, i, ldw, ldx, max(1, o)
+
+
+def _view(shape, strides):
+    """(trans, ld) such that op(stored array) = T^T for a 2-D tensor T.
+
+    A row-major T (stride (ld, 1)) is stored column-major as T^T: op 'N'.
+    A column-major T (stride (1, ld)), e.g. a transposed view, is stored as
+    T itself: op 'T'.
+    """
+    r, c = shape
+    s0, s1 = strides
     if s1 == 1 and (s0 >= max(1, c) or r <= 1):
         return "N", max(1, s0, c)
     if s0 == 1 and (s1 >= max(1, r) or c <= 1):
@@ -76,24 +90,23 @@ def colmajor_view(T):
     raise ValueError("tensor must have unit stride in one dimension")
 
 
-def matmul(X, W, *, precision="fp32", config=-1, out=None, stream=None):
-    """Y = X @ W for 2-D float32 device tensors, Y row-major (b x o).
+def colmajor_view(T):
+    """(trans, ld) of a 2-D tensor entering a column-major product as T^T."""
+    return _view(tuple(T.shape), tuple(T.stride()))
 
-    Row-major Y is column-major Y^T = W^T X^T, so this is one call
-    sgemm(opW, opX, o, b, i, 1, W, ldw, X, ldx, 0, Y, o).
-    """
+
+def matmul(X, W, *, precision="fp32", config=-1, out=None, stream=None):
+    """Y = X @ W for 2-D float32 device tensors; Y is a new (or the given
+    contiguous) row-major (b x o) tensor.  One library call."""
     import torch
-    b, i = X.shape
-    i2, o = W.shape
-    if i != i2:
-        raise ValueError("inner dimensions differ: %d vs %d" % (i, i2))
+    ta, tb, M, N, K, lda, ldb, ldc = matmul_args(tuple(X.shape), tuple(X.stride()),
+                                                 tuple(W.shape), tuple(W.stride()))
+    b, o = X.shape[0], W.shape[1]
     if out is None:
         out = torch.empty((b, o), dtype=torch.float32, device=X.device)
-    if out.shape != (b, o) or out.stride() != (o, 1) and b > 0 and o > 0:
+    elif tuple(out.shape) != (b, o) or (b > 1 and o > 0 and out.stride() != (o, 1)):
         raise ValueError("out must be a contiguous (b x o) tensor")
-    tw, ldw = colmajor_view(W)
-    tx, ldx = colmajor_view(X)
-    sgemm(tw, tx, o, b, i, 1.0, W, ldw, X, ldx, 0.0, out, max(1, o),
+    sgemm(ta, tb, M, N, K, 1.0, W, lda, X, ldb, 0.0, out, ldc,
           precision=precision, config=config, stream=stream)
     return out
 

@@ -1,0 +1,510 @@
+// grouped.hip -- many independent GEMMs in one persistent launch.
+//
+// A plan holds, in device memory, one descriptor per problem (operands,
+// sizes, trans flags, the tile variant chosen for its size bucket, its tile
+// grid) and one list of (problem, tile) references sorted by decreasing
+// cost (K x tile area): longest-processing-time-first order.  The
+// persistent kernel starts (CUs x work-groups per CU) work-groups; after an
+// XCD-aware renumbering (the work-groups of one XCD take neighbouring list
+// entries, which mostly belong to the same problem and so share its
+// operands in that XCD's L2), work-group w computes list entries w, w+G,
+// w+2G, ...  Every tile is written by exactly one work-group with no
+// atomics, so results are bitwise reproducible run to run and between the
+// graph replay and a direct launch.
+//
+// The plan records its launch into a HIP graph once; mgemm_grouped_plan_launch
+// replays it.  mgemm_grouped_tune picks the variant of each size bucket by
+// timing the whole batch (coordinate descent over buckets).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "host_common.hpp"
+#include "mgemm.h"
+#include "tile_f32.hpp"
+#include "tile_lowp.hpp"
+
+namespace mgemm {
+
+// ---- tile variants of the persistent kernel (all 256 threads) -------------
+using GF0 = CfgF32<64, 64, 16, 2, 2>;
+using GF1 = CfgF32<128, 128, 16, 2, 2>;
+using GF2 = CfgF32<128, 128, 32, 2, 2>;
+using GL0 = CfgLP<64, 64, 2, 2>;
+using GL1 = CfgLP<128, 128, 2, 2>;
+using GL2 = CfgLP<128, 64, 2, 2>;
+constexpr int NUM_VARIANTS = 3;
+constexpr int NUM_BUCKETS = 4;
+
+struct VariantShape {
+    int bm, bn, bk;
+};
+
+static VariantShape variant_shape(int precision, int v) {
+    if (precision == MGEMM_PREC_FP32) {
+        const VariantShape s[NUM_VARIANTS] = {{GF0::BM, GF0::BN, GF0::BK},
+                                              {GF1::BM, GF1::BN, GF1::BK},
+                                              {GF2::BM, GF2::BN, GF2::BK}};
+        return s[v];
+    }
+    const VariantShape s[NUM_VARIANTS] = {{GL0::BM, GL0::BN, GL0::BK},
+                                          {GL1::BM, GL1::BN, GL1::BK},
+                                          {GL2::BM, GL2::BN, GL2::BK}};
+    return s[v];
+}
+
+template <class Cfg>
+constexpr int f32_lds() { return Cfg::SMEM_FLOATS * 4; }
+template <class Cfg>
+constexpr int lp_lds() { return 2 * 2 * (Cfg::BM + Cfg::BN) * Cfg::ROW_BYTES; }
+constexpr int cmax(int a, int b) { return a > b ? a : b; }
+constexpr int GROUPED_LDS_F32 = cmax(f32_lds<GF0>(), cmax(f32_lds<GF1>(), f32_lds<GF2>()));
+constexpr int GROUPED_LDS_LP = cmax(lp_lds<GL0>(), cmax(lp_lds<GL1>(), lp_lds<GL2>()));
+
+// Default variant per size bucket (bucket = by max(M, N)).
+static const int DEFAULT_F32[NUM_BUCKETS] = {0, 0, 1, 2};
+static const int DEFAULT_LP[NUM_BUCKETS] = {0, 0, 2, 1};
+
+static int bucket_of(int64_t M, int64_t N) {
+    const int64_t s = M > N ? M : N;
+    return s <= 64 ? 0 : s <= 128 ? 1 : s <= 256 ? 2 : 3;
+}
+
+// ---- device descriptors ----------------------------------------------------
+struct GroupedProblem {
+    GemmDesc d;
+    uint32_t tiles_m, tiles_n;
+    int32_t ta, tb, variant, pad;
+};
+
+struct TileRef {
+    uint32_t problem, tile;
+};
+
+// Each variant is a separate (non-inlined) function so that its register
+// allocation is its own; the kernel needs only the largest of them.
+template <class Cfg>
+__device__ __attribute__((noinline)) void f32_tile_any(const GemmDesc& d, int ta, int tb, uint32_t tm, uint32_t tn,
+                                    char* smem) {
+    const int64_t m0 = (int64_t)tm * Cfg::BM, n0 = (int64_t)tn * Cfg::BN;
+    float* s = reinterpret_cast<float*>(smem);
+    // op(A) is K-contiguous for A 'T'; op(B) is K-contiguous for B 'N'.
+    if (!ta && !tb) tile_f32<Cfg, false, true, true>(d, m0, n0, s);
+    else if (!ta)   tile_f32<Cfg, false, false, true>(d, m0, n0, s);
+    else if (!tb)   tile_f32<Cfg, true, true, true>(d, m0, n0, s);
+    else            tile_f32<Cfg, true, false, true>(d, m0, n0, s);
+}
+
+template <class Cfg>
+__device__ __attribute__((noinline)) void lp_tile_any(const GemmDesc& d, int ta, int tb, uint32_t tm, uint32_t tn,
+                                   char* smem) {
+    const int64_t m0 = (int64_t)tm * Cfg::BM, n0 = (int64_t)tn * Cfg::BN;
+    if (!ta && !tb) tile_lowp<Cfg, Form::BF16X3, false, true, true>(d, m0, n0, smem);
+    else if (!ta)   tile_lowp<Cfg, Form::BF16X3, false, false, true>(d, m0, n0, smem);
+    else if (!tb)   tile_lowp<Cfg, Form::BF16X3, true, true, true>(d, m0, n0, smem);
+    else            tile_lowp<Cfg, Form::BF16X3, true, false, true>(d, m0, n0, smem);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256, 2) void grouped_kernel(const GroupedProblem* __restrict__ probs,
+                                                      const TileRef* __restrict__ tiles,
+                                                      uint32_t ntiles) {
+    extern __shared__ __attribute__((aligned(16))) char grouped_smem[];
+    const uint32_t w = xcd_remap(blockIdx.x, gridDim.x);
+    for (uint32_t t = w; t < ntiles; t += gridDim.x) {
+        const TileRef tr = tiles[t];
+        const GroupedProblem& gp = probs[tr.problem];
+        const GemmDesc d = gp.d;
+        const uint32_t tm = tr.tile % gp.tiles_m, tn = tr.tile / gp.tiles_m;
+        if (PREC == MGEMM_PREC_FP32) {
+            switch (gp.variant) {
+                case 0: f32_tile_any<GF0>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
+                case 1: f32_tile_any<GF1>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
+                default: f32_tile_any<GF2>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
+            }
+        } else {
+            switch (gp.variant) {
+                case 0: lp_tile_any<GL0>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
+                case 1: lp_tile_any<GL1>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
+                default: lp_tile_any<GL2>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
+            }
+        }
+        __syncthreads();  // LDS is reused by the next tile
+    }
+}
+
+static const void* kernel_of(int precision) {
+    return precision == MGEMM_PREC_FP32 ? (const void*)grouped_kernel<MGEMM_PREC_FP32>
+                                        : (const void*)grouped_kernel<MGEMM_PREC_BF16X3>;
+}
+
+static int lds_of(int precision) {
+    return precision == MGEMM_PREC_FP32 ? GROUPED_LDS_F32 : GROUPED_LDS_LP;
+}
+
+}  // namespace mgemm
+
+// ---- the plan object ---------------------------------------------------------
+struct mgemm_plan {
+    int device = 0;
+    int precision = 0;
+    int64_t nprob = 0, ntiles = 0;
+    uint32_t grid = 0;
+    mgemm::GroupedProblem* d_probs = nullptr;
+    mgemm::TileRef* d_tiles = nullptr;
+    hipStream_t capture = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace mgemm {
+
+static std::mutex g_plans_mu;
+static std::unordered_set<mgemm_plan*> g_plans;
+
+static bool plan_live(const mgemm_plan* p) {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    return p && g_plans.count(const_cast<mgemm_plan*>(p));
+}
+
+static void plan_free(mgemm_plan* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->capture) (void)hipStreamDestroy(p->capture);
+    if (p->d_probs) (void)hipFree(p->d_probs);
+    if (p->d_tiles) (void)hipFree(p->d_tiles);
+    delete p;
+}
+
+static int hip_err(hipError_t e, const char* where) {
+    (void)hipGetLastError();
+    return fail(MGEMM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+static hipError_t launch_plan_kernel(const mgemm_plan* p, hipStream_t s) {
+    if (p->ntiles == 0) return hipSuccess;
+    const uint32_t n = (uint32_t)p->ntiles;
+    if (p->precision == MGEMM_PREC_FP32)
+        hipLaunchKernelGGL(grouped_kernel<MGEMM_PREC_FP32>, dim3(p->grid), dim3(256),
+                           lds_of(p->precision), s, p->d_probs, p->d_tiles, n);
+    else
+        hipLaunchKernelGGL(grouped_kernel<MGEMM_PREC_BF16X3>, dim3(p->grid), dim3(256),
+                           lds_of(p->precision), s, p->d_probs, p->d_tiles, n);
+    return hipGetLastError();
+}
+
+struct Interval {
+    uintptr_t lo, hi;
+    int64_t owner;
+};
+
+static void extent_of(const void* ptr, int64_t rows, int64_t cols, int64_t ld, Interval& iv) {
+    iv.lo = (uintptr_t)ptr;
+    iv.hi = iv.lo + (uintptr_t)(((cols - 1) * ld + rows) * (int64_t)sizeof(float));
+}
+
+// Build (without a graph) the plan for a batch.  Shared by plan_create and
+// the tuner.
+static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
+                      const int* bucket_configs, mgemm_plan** out, int64_t* bad_index,
+                      int* bad_status) {
+    if (bad_index) *bad_index = -1;
+    if (bad_status) *bad_status = 0;
+    if (!out) return fail(MGEMM_ERR_BAD_PLAN, "out_plan is NULL");
+    *out = nullptr;
+    if (count < 0 || (count > 0 && !probs))
+        return fail(MGEMM_ERR_BAD_PROBLEM, "problem array is NULL or count < 0");
+    if (precision != MGEMM_PREC_FP32 && precision != MGEMM_PREC_BF16X3)
+        return fail(MGEMM_ERR_UNSUPPORTED, "grouped plans support FP32 and BF16x3");
+    int cfg[NUM_BUCKETS];
+    for (int b = 0; b < NUM_BUCKETS; ++b) {
+        cfg[b] = bucket_configs ? bucket_configs[b]
+                                : (precision == MGEMM_PREC_FP32 ? DEFAULT_F32[b] : DEFAULT_LP[b]);
+        if (cfg[b] < 0 || cfg[b] >= NUM_VARIANTS)
+            return fail(MGEMM_ERR_UNSUPPORTED, "bucket configuration out of range");
+    }
+    // Validate every problem (BLAS rules) and collect the live ones.
+    std::vector<GroupedProblem> live;
+    std::vector<int64_t> live_index;
+    std::vector<Interval> cs, ab;
+    for (int64_t i = 0; i < count; ++i) {
+        const mgemm_problem& q = probs[i];
+        std::string why;
+        int st = validate(q.transA, q.transB, q.M, q.N, q.K, q.alpha, q.A, q.lda, q.B, q.ldb,
+                          q.beta, q.C, q.ldc, why);
+        const int ta = trans_code(q.transA), tb = trans_code(q.transB);
+        if (st == 0 && (q.lda > MAX_BUF_LD || q.ldb > MAX_BUF_LD || q.ldc > MAX_BUF_LD)) {
+            st = MGEMM_ERR_UNSUPPORTED;
+            why = "leading dimension above the grouped kernel's limit";
+        }
+        if (st == 0 && overlaps(ta, tb, q.M, q.N, q.K, q.alpha, q.A, q.lda, q.B, q.ldb, q.C,
+                                q.ldc)) {
+            st = MGEMM_ERR_ALIAS;
+            why = "C overlaps A or B";
+        }
+        if (st) {
+            if (bad_index) *bad_index = i;
+            if (bad_status) *bad_status = st;
+            return fail(MGEMM_ERR_BAD_PROBLEM, "problem " + std::to_string(i) + ": " + why);
+        }
+        if (q.M == 0 || q.N == 0) continue;
+        const bool no_product = q.alpha == 0.0f || q.K == 0;
+        if (no_product && q.beta == 1.0f) continue;
+        GroupedProblem g{};
+        // alpha == 0: K = 0 so that A and B are never read.
+        g.d = GemmDesc{q.A, q.B, q.C, q.M, q.N, no_product ? 0 : q.K, q.lda, q.ldb, q.ldc,
+                       q.alpha, q.beta, nullptr, nullptr};
+        g.ta = ta;
+        g.tb = tb;
+        g.variant = cfg[bucket_of(q.M, q.N)];
+        const VariantShape vs = variant_shape(precision, g.variant);
+        g.tiles_m = (uint32_t)((q.M + vs.bm - 1) / vs.bm);
+        g.tiles_n = (uint32_t)((q.N + vs.bn - 1) / vs.bn);
+        live.push_back(g);
+        live_index.push_back(i);
+        Interval iv;
+        extent_of(q.C, q.M, q.N, q.ldc, iv);
+        iv.owner = i;
+        cs.push_back(iv);
+        if (!no_product) {
+            extent_of(q.A, ta ? q.K : q.M, ta ? q.M : q.K, q.lda, iv);
+            ab.push_back(iv);
+            extent_of(q.B, tb ? q.N : q.K, tb ? q.K : q.N, q.ldb, iv);
+            ab.push_back(iv);
+        }
+    }
+    // No C may overlap another C, or any A or B of the batch.
+    std::sort(cs.begin(), cs.end(), [](const Interval& a, const Interval& b) { return a.lo < b.lo; });
+    for (size_t k = 1; k < cs.size(); ++k)
+        if (cs[k].lo < cs[k - 1].hi) {
+            if (bad_index) *bad_index = cs[k].owner;
+            if (bad_status) *bad_status = MGEMM_ERR_ALIAS;
+            return fail(MGEMM_ERR_BAD_PROBLEM, "problem " + std::to_string(cs[k].owner) +
+                                                   ": C overlaps another problem's C");
+        }
+    for (const Interval& x : ab) {
+        auto it = std::lower_bound(cs.begin(), cs.end(), x.hi,
+                                   [](const Interval& c, uintptr_t v) { return c.lo < v; });
+        if (it != cs.begin() && std::prev(it)->hi > x.lo) {
+            if (bad_index) *bad_index = std::prev(it)->owner;
+            if (bad_status) *bad_status = MGEMM_ERR_ALIAS;
+            return fail(MGEMM_ERR_BAD_PROBLEM,
+                        "problem " + std::to_string(std::prev(it)->owner) +
+                            ": C overlaps an operand of the batch");
+        }
+    }
+    // Tile list, longest first (cost ~ K x tile area; ties keep problem order).
+    std::vector<TileRef> tl;
+    std::vector<double> cost;
+    for (size_t i = 0; i < live.size(); ++i) {
+        const VariantShape vs = variant_shape(precision, live[i].variant);
+        const double c = (double)(live[i].d.K + 32) * vs.bm * vs.bn;
+        const uint64_t n = (uint64_t)live[i].tiles_m * live[i].tiles_n;
+        if (n > 0xffffffffULL) return fail(MGEMM_ERR_UNSUPPORTED, "too many tiles");
+        for (uint32_t t = 0; t < (uint32_t)n; ++t) {
+            tl.push_back(TileRef{(uint32_t)i, t});
+            cost.push_back(c);
+        }
+    }
+    if (tl.size() > 0xffffffffULL) return fail(MGEMM_ERR_UNSUPPORTED, "too many tiles");
+    std::vector<size_t> order(tl.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<TileRef> sorted(tl.size());
+    for (size_t k = 0; k < order.size(); ++k) sorted[k] = tl[order[k]];
+
+    int st = check_device(nullptr);
+    if (st) return st;
+    mgemm_plan* p = new mgemm_plan();
+    hipError_t e = hipGetDevice(&p->device);
+    p->precision = precision;
+    p->nprob = (int64_t)live.size();
+    p->ntiles = (int64_t)sorted.size();
+    if (e == hipSuccess && !live.empty())
+        e = hipMalloc((void**)&p->d_probs, live.size() * sizeof(GroupedProblem));
+    if (e == hipSuccess && !sorted.empty())
+        e = hipMalloc((void**)&p->d_tiles, sorted.size() * sizeof(TileRef));
+    if (e != hipSuccess) {
+        plan_free(p);
+        (void)hipGetLastError();
+        return fail(MGEMM_ERR_ALLOC, "device memory for the plan's tables");
+    }
+    if (!live.empty())
+        e = hipMemcpy(p->d_probs, live.data(), live.size() * sizeof(GroupedProblem),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !sorted.empty())
+        e = hipMemcpy(p->d_tiles, sorted.data(), sorted.size() * sizeof(TileRef),
+                      hipMemcpyHostToDevice);
+    const void* k = kernel_of(precision);
+    const int lds = lds_of(precision);
+    if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    int per_cu = 0, cus = 0;
+    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                                                   p->device);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_err(e, "grouped plan set-up");
+    }
+    const int64_t slots = (int64_t)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+    p->grid = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(slots, p->ntiles));
+    *out = p;
+    return MGEMM_OK;
+}
+
+static void plan_register(mgemm_plan* p) {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    g_plans.insert(p);
+}
+
+static bool plan_unregister(mgemm_plan* p) {
+    std::lock_guard<std::mutex> lk(g_plans_mu);
+    return g_plans.erase(p) > 0;
+}
+
+}  // namespace mgemm
+
+using namespace mgemm;
+
+extern "C" {
+
+int mgemm_grouped_bucket(int64_t M, int64_t N, int64_t K) {
+    (void)K;
+    return bucket_of(M, N);
+}
+
+int mgemm_grouped_variant_count(int precision) {
+    return precision == MGEMM_PREC_FP32 || precision == MGEMM_PREC_BF16X3 ? NUM_VARIANTS : 0;
+}
+
+int mgemm_grouped_variant_info(int precision, int variant, int* bm, int* bn, int* bk) {
+    if (mgemm_grouped_variant_count(precision) == 0 || variant < 0 || variant >= NUM_VARIANTS)
+        return fail(MGEMM_ERR_UNSUPPORTED, "unknown grouped variant");
+    const VariantShape s = variant_shape(precision, variant);
+    if (bm) *bm = s.bm;
+    if (bn) *bn = s.bn;
+    if (bk) *bk = s.bk;
+    return MGEMM_OK;
+}
+
+int mgemm_grouped_plan_create(const mgemm_problem* problems, int64_t count, int precision,
+                              const int* bucket_configs, void* stream, mgemm_plan** out_plan,
+                              int64_t* bad_index, int* bad_status) {
+    (void)stream;
+    mgemm_plan* p = nullptr;
+    int st = build_plan(problems, count, precision, bucket_configs, out_plan ? &p : nullptr,
+                        bad_index, bad_status);
+    if (st) return st;
+    // Record the launch once into a graph, on a private non-blocking stream
+    // of default priority (the legacy default stream cannot be captured).
+    hipError_t e = hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(p->capture, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t le = launch_plan_kernel(p, p->capture);
+        e = hipStreamEndCapture(p->capture, &p->graph);
+        if (e == hipSuccess) e = le;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_err(e, "grouped plan graph capture");
+    }
+    plan_register(p);
+    *out_plan = p;
+    return MGEMM_OK;
+}
+
+int mgemm_grouped_plan_launch(mgemm_plan* plan, void* stream) {
+    if (!plan_live(plan)) return fail(MGEMM_ERR_BAD_PLAN, "plan is NULL or destroyed");
+    if (plan->ntiles == 0) return MGEMM_OK;
+    hipError_t e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+    return e == hipSuccess ? MGEMM_OK : hip_err(e, "hipGraphLaunch");
+}
+
+int mgemm_grouped_plan_run(mgemm_plan* plan, void* stream) {
+    if (!plan_live(plan)) return fail(MGEMM_ERR_BAD_PLAN, "plan is NULL or destroyed");
+    hipError_t e = launch_plan_kernel(plan, (hipStream_t)stream);
+    return e == hipSuccess ? MGEMM_OK : hip_err(e, "grouped kernel launch");
+}
+
+int mgemm_grouped_plan_info(const mgemm_plan* plan, int64_t* tiles, int64_t* workgroups) {
+    if (!plan_live(plan)) return fail(MGEMM_ERR_BAD_PLAN, "plan is NULL or destroyed");
+    if (tiles) *tiles = plan->ntiles;
+    if (workgroups) *workgroups = plan->grid;
+    return MGEMM_OK;
+}
+
+int mgemm_grouped_plan_destroy(mgemm_plan* plan) {
+    if (!plan || !plan_unregister(plan))
+        return fail(MGEMM_ERR_BAD_PLAN, "plan is NULL or already destroyed");
+    plan_free(plan);
+    return MGEMM_OK;
+}
+
+int mgemm_grouped_tune(const mgemm_problem* problems, int64_t count, int precision, void* stream,
+                       int reps, int* bucket_configs, float* best_ms) {
+    if (!bucket_configs) return fail(MGEMM_ERR_UNSUPPORTED, "bucket_configs is NULL");
+    if (reps < 1) reps = 1;
+    hipStream_t s = (hipStream_t)stream;
+    for (int b = 0; b < NUM_BUCKETS; ++b)
+        bucket_configs[b] = precision == MGEMM_PREC_FP32 ? DEFAULT_F32[b] : DEFAULT_LP[b];
+    bool used[NUM_BUCKETS] = {false, false, false, false};
+    for (int64_t i = 0; i < count && problems; ++i)
+        used[bucket_of(problems[i].M, problems[i].N)] = true;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_err(hipGetLastError(), "hipEventCreate");
+    }
+    // Time the whole batch with the given bucket assignment (best of reps).
+    auto time_of = [&](const int* cfg, float& ms) -> int {
+        mgemm_plan* p = nullptr;
+        int st = build_plan(problems, count, precision, cfg, &p, nullptr, nullptr);
+        if (st) return st;
+        hipError_t e = launch_plan_kernel(p, s);   // warm-up
+        float best = 1e30f;
+        for (int r = 0; r < reps && e == hipSuccess; ++r) {
+            e = hipEventRecord(e0, s);
+            if (e == hipSuccess) e = launch_plan_kernel(p, s);
+            if (e == hipSuccess) e = hipEventRecord(e1, s);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float t = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+            if (e == hipSuccess && t < best) best = t;
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        plan_free(p);
+        if (e != hipSuccess) return hip_err(e, "grouped tuning run");
+        ms = best;
+        return MGEMM_OK;
+    };
+    float cur = 0.0f;
+    int st = time_of(bucket_configs, cur);
+    for (int b = 0; b < NUM_BUCKETS && st == MGEMM_OK; ++b) {
+        if (!used[b]) continue;
+        const int keep = bucket_configs[b];
+        int best_v = keep;
+        for (int v = 0; v < NUM_VARIANTS && st == MGEMM_OK; ++v) {
+            if (v == keep) continue;
+            bucket_configs[b] = v;
+            float t = 0.0f;
+            st = time_of(bucket_configs, t);
+            if (st == MGEMM_OK && t < cur) {
+                cur = t;
+                best_v = v;
+            }
+        }
+        bucket_configs[b] = best_v;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == MGEMM_OK && best_ms) *best_ms = cur;
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,169 @@
+"""Dense layer Y = X W with the hand-written backward dX = G W^T, dW = X^T G.
+
+CPU: the library's row-major -> column-major argument mapping
+(``matmul_args``) is fed to the FP64 oracle, which must then reproduce
+X @ W, and the backward's two mapped products must equal central finite
+differences of L = sum((X W) o G) (exact up to rounding: L is bilinear).
+GPU: forward and backward through the C ABI against the oracle gradient.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1912_04379_amd.api import matmul_args
+
+
+def np_strides(a):
+    return tuple(s // a.itemsize for s in a.strides)
+
+
+def storage(a):
+    """Flat buffer that a (possibly transposed) view of a contiguous array
+    lives in."""
+    base = a if a.base is None else a.base
+    return np.ascontiguousarray(base).ravel()
+
+
+def mapped_product(X, W, gemm):
+    """Y = X @ W evaluated by `gemm` on the arguments the library passes."""
+    ta, tb, M, N, K, lda, ldb, ldc = matmul_args(X.shape, np_strides(X), W.shape, np_strides(W))
+    Yt = gemm(ta, tb, M, N, K, 1.0, storage(W), lda, storage(X), ldb, 0.0, None, ldc)
+    return Yt.T          # column-major Y^T -> row-major Y
+
+
+@pytest.mark.parametrize("xt", [False, True])
+@pytest.mark.parametrize("wt", [False, True])
+def test_mapping_reproduces_matmul(xt, wt):
+    rng = np.random.default_rng(0)
+    b, i, o = 37, 23, 29
+    X = rng.uniform(-1, 1, (i, b) if xt else (b, i)).astype(np.float32)
+    W = rng.uniform(-1, 1, (o, i) if wt else (i, o)).astype(np.float32)
+    X = X.T if xt else X
+    W = W.T if wt else W
+    got = mapped_product(X, W, oracle.sgemm)
+    want = X.astype(np.float64) @ W.astype(np.float64)
+    assert oracle.normwise_rel_err(got, want) <= 1e-13
+
+
+def test_backward_mapping_matches_finite_differences():
+    """64 x 48 x 32 in FP64: dX = G W^T and dW = X^T G as the backward forms
+    them (transposed views -> trans flags) against central differences."""
+    X, W, G = (v.astype(np.float64) for v in synth.dense_layer(0, 64, 48, 32))
+    dX = mapped_product(G, W.T, oracle.dgemm)
+    dW = mapped_product(X.T, G, oracle.dgemm)
+    rng = np.random.default_rng(3)
+    h = 1e-3
+    for _ in range(20):
+        r, c = rng.integers(0, 64), rng.integers(0, 48)
+        Xp, Xm = X.copy(), X.copy()
+        Xp[r, c] += h
+        Xm[r, c] -= h
+        fd = (oracle.dense_loss(Xp, W, G) - oracle.dense_loss(Xm, W, G)) / (2 * h)
+        assert abs(fd - dX[r, c]) <= 1e-9 * max(1.0, abs(fd))
+        r, c = rng.integers(0, 48), rng.integers(0, 32)
+        Wp, Wm = W.copy(), W.copy()
+        Wp[r, c] += h
+        Wm[r, c] -= h
+        fd = (oracle.dense_loss(X, Wp, G) - oracle.dense_loss(X, Wm, G)) / (2 * h)
+        assert abs(fd - dW[r, c]) <= 1e-9 * max(1.0, abs(fd))
+
+
+def test_mapping_matches_the_north_star_calls():
+    """The three calls of the 8192 x 1024 x 4096 layer."""
+    # Y = X W: X (8192 x 1024), W (1024 x 4096), both contiguous.
+    assert matmul_args((8192, 1024), (1024, 1), (1024, 4096), (4096, 1)) == \
+        ("N", "N", 4096, 8192, 1024, 4096, 1024, 4096)
+    # dX = G W^T: G (8192 x 4096), W^T a transposed view (strides (1, 4096)).
+    assert matmul_args((8192, 4096), (4096, 1), (4096, 1024), (1, 4096)) == \
+        ("T", "N", 1024, 8192, 4096, 4096, 4096, 1024)
+    # dW = X^T G: X^T a transposed view (strides (1, 1024)).
+    assert matmul_args((1024, 8192), (1, 1024), (8192, 4096), (4096, 1)) == \
+        ("N", "T", 4096, 1024, 8192, 4096, 1024, 4096)
+
+
+# ---------------------------------------------------------------------------
+
+def sampled_rowmajor(A, B, rows, cols):
+    """(A @ B)[rows, cols] for row-major float32 host arrays, from the
+    oracle: P^T = B^T A^T with B, A read as column-major storage."""
+    p, k = A.shape
+    q = B.shape[1]
+    A = np.ascontiguousarray(A)
+    B = np.ascontiguousarray(B)
+    return oracle.sgemm_entries("N", "N", q, p, k, 1.0, B.ravel(), q, A.ravel(), k, 0.0,
+                                None, q, cols, rows)
+
+
+@pytest.mark.gpu
+def test_small_layer_forward_backward():
+    import torch
+    import paper_1912_04379_amd as mg
+    X, W, G = synth.dense_layer(1, 64, 48, 32)
+    Xd = torch.from_numpy(X).cuda().requires_grad_()
+    Wd = torch.from_numpy(W).cuda().requires_grad_()
+    Gd = torch.from_numpy(G).cuda()
+    Y = mg.linear(Xd, Wd)
+    (Y * Gd).sum().backward()
+    dX, dW = oracle.dense_grads(X, W, G)
+    Yref = X.astype(np.float64) @ W.astype(np.float64)
+    assert oracle.normwise_rel_err(Y.detach().cpu().numpy(), Yref) <= 1e-6
+    assert oracle.normwise_rel_err(Xd.grad.cpu().numpy(), dX) <= 1e-6
+    assert oracle.normwise_rel_err(Wd.grad.cpu().numpy(), dW) <= 1e-6
+
+
+@pytest.mark.gpu
+def test_gradient_of_noncontiguous_upstream():
+    """G arrives as a transposed view: the backward still maps it."""
+    import torch
+    import paper_1912_04379_amd as mg
+    X, W, G = synth.dense_layer(2, 50, 40, 30)
+    Xd = torch.from_numpy(X).cuda().requires_grad_()
+    Wd = torch.from_numpy(W).cuda().requires_grad_()
+    Gt = torch.from_numpy(np.ascontiguousarray(G.T)).cuda()
+    Y = mg.linear(Xd, Wd)
+    Y.backward(Gt.t())
+    dX, dW = oracle.dense_grads(X, W, G)
+    assert oracle.normwise_rel_err(Xd.grad.cpu().numpy(), dX) <= 1e-6
+    assert oracle.normwise_rel_err(Wd.grad.cpu().numpy(), dW) <= 1e-6
+
+
+@pytest.mark.gpu
+def test_only_weight_gradient():
+    import torch
+    import paper_1912_04379_amd as mg
+    X, W, G = synth.dense_layer(3, 33, 17, 9)
+    Xd = torch.from_numpy(X).cuda()
+    Wd = torch.from_numpy(W).cuda().requires_grad_()
+    mg.linear(Xd, Wd).backward(torch.from_numpy(G).cuda())
+    _, dW = oracle.dense_grads(X, W, G)
+    assert Xd.grad is None
+    assert oracle.normwise_rel_err(Wd.grad.cpu().numpy(), dW) <= 1e-6
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_full_size_layer_against_oracle_gradient(prec):
+    """X 8192 x 1024, W 1024 x 4096, G 8192 x 4096, uniform [-1, 1), seed 0:
+    Y, dX, dW on sampled entries within 1e-5 normwise of the FP64 oracle."""
+    import torch
+    import paper_1912_04379_amd as mg
+    print("dense layer 8192x1024x4096", prec, flush=True)
+    X, W, G = synth.dense_layer(0, 8192, 1024, 4096)
+    Xd = torch.from_numpy(X).cuda().requires_grad_()
+    Wd = torch.from_numpy(W).cuda().requires_grad_()
+    Gd = torch.from_numpy(G).cuda()
+    Y = mg.linear(Xd, Wd, precision=prec)
+    Y.backward(Gd)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(9)
+    for name, got, A, B in (("Y", Y.detach(), X, W),
+                            ("dX", Xd.grad, G, np.ascontiguousarray(W.T)),
+                            ("dW", Wd.grad, np.ascontiguousarray(X.T), G)):
+        r = rng.integers(0, got.shape[0], 1500)
+        c = rng.integers(0, got.shape[1], 1500)
+        ref = sampled_rowmajor(A, B, r, c)
+        g = got[torch.from_numpy(r).cuda(), torch.from_numpy(c).cuda()].double().cpu().numpy()
+        err = oracle.normwise_rel_err(g, ref)
+        print("%s %s sampled normwise %.3e" % (prec, name, err), flush=True)
+        assert err <= 1e-5

@@ -1,0 +1,239 @@
+"""Grouped persistent launch: many uneven GEMMs in one kernel, replayed
+from a HIP graph, with per-bucket tile variants from the tuner."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1912_04379_amd as mg
+import synth
+from paper_1912_04379_amd import _lib
+from paper_1912_04379_amd import grouped as gp
+
+FA, FB, FC = 0x10000000, 0x20000000, 0x30000000
+
+
+def fake(ta="N", M=8, N=8, K=8, A=FA, B=FB, C=FC, alpha=1.0, beta=0.0, lda=None):
+    return dict(transA=ta, transB="N", M=M, N=N, K=K, alpha=alpha, beta=beta, A=A,
+                lda=lda if lda is not None else (K if ta == "T" else M), B=B, ldb=K, C=C, ldc=M)
+
+
+def create(problems, precision=0, configs=None):
+    arr = gp._problem_array(problems)
+    cfg = (ctypes.c_int * 4)(*configs) if configs else None
+    plan = ctypes.c_void_p()
+    bad, bst = ctypes.c_int64(), ctypes.c_int()
+    st = mg.lib().mgemm_grouped_plan_create(arr, len(problems), precision, cfg, None,
+                                            ctypes.byref(plan), ctypes.byref(bad),
+                                            ctypes.byref(bst))
+    return st, bad.value, bst.value
+
+
+# ---- CPU: validation happens before any device work -------------------------
+
+def test_bad_problem_is_reported_with_its_index():
+    probs = [fake(), fake(A=FA + 4096, C=FC + 4096), fake(M=-3, C=FC + 8192)]
+    st, bad, bst = create(probs)
+    assert st == _lib.ERR_BAD_PROBLEM and bad == 2 and bst == -3
+    probs[2] = fake(C=FC + 8192, lda=2)            # lda < M
+    st, bad, bst = create(probs)
+    assert (st, bad, bst) == (_lib.ERR_BAD_PROBLEM, 2, -8)
+
+
+def test_overlapping_outputs_are_rejected():
+    st, bad, bst = create([fake(), fake(A=FA + 4096, C=FC + 128)])
+    assert st == _lib.ERR_BAD_PROBLEM and bst == _lib.ERR_ALIAS
+    # one problem's C over another problem's A
+    st, bad, bst = create([fake(), fake(A=FA + 4096, C=FA + 64)])
+    assert st == _lib.ERR_BAD_PROBLEM and bst == _lib.ERR_ALIAS
+
+
+def test_unsupported_precision_and_variant():
+    assert create([fake()], precision=2)[0] == _lib.ERR_UNSUPPORTED
+    assert create([fake()], configs=[0, 0, 9, 0])[0] == _lib.ERR_UNSUPPORTED
+    assert gp.variant_count("fp32") == 3 and gp.variant_count("fp16s") == 0
+    assert gp.variant_info("bf16x3", 1)["bm"] > 0
+
+
+def test_buckets():
+    assert [gp.bucket(m, n) for m, n in ((16, 64), (65, 10), (200, 256), (257, 16))] == \
+        [0, 1, 2, 3]
+
+
+def test_destroy_null_plan():
+    assert mg.lib().mgemm_grouped_plan_destroy(None) == _lib.ERR_BAD_PLAN
+
+
+# ---- GPU --------------------------------------------------------------------
+
+def make_batch(count=512, seed=0, lo=16, hi=512):
+    """Problems and host data; every matrix sits 256-byte aligned in one
+    device arena."""
+    import torch
+    shapes = synth.grouped_problems(seed, count, lo, hi)
+    data = synth.grouped_data(shapes, seed=seed + 1)
+    sizes = []
+    for d in data:
+        sizes += [d["A"].size, d["B"].size, d["C"].size]
+    offs, tot = [], 0
+    for s in sizes:
+        offs.append(tot)
+        tot += (s + 63) // 64 * 64
+    host = np.zeros(tot, dtype=np.float32)
+    k = 0
+    for d in data:
+        for key in ("A", "B", "C"):
+            host[offs[k]:offs[k] + d[key].size] = d[key]
+            k += 1
+    arena = torch.from_numpy(host).cuda()
+    base = arena.data_ptr()
+    problems = []
+    k = 0
+    for s, d in zip(shapes, data):
+        p = dict(s, alpha=1.0, beta=1.0, lda=d["lda"], ldb=d["ldb"], ldc=d["ldc"])
+        p["A"], p["B"], p["C"] = base + 4 * offs[k], base + 4 * offs[k + 1], base + 4 * offs[k + 2]
+        p["_c_off"], p["_c_size"] = offs[k + 2], d["C"].size
+        k += 3
+        problems.append(p)
+    return problems, data, arena, host
+
+
+def c_of(arena_host, p):
+    return arena_host[p["_c_off"]:p["_c_off"] + p["_c_size"]]
+
+
+def check_batch(problems, data, out_host, precision, tol):
+    worst = 0.0
+    for p, d in zip(problems, data):
+        args = (p["transA"], p["transB"], p["M"], p["N"], p["K"], p["alpha"], d["A"], d["lda"],
+                d["B"], d["ldb"], p["beta"], d["C"], d["ldc"])
+        ref = oracle.sgemm(*args)
+        got = c_of(out_host, p).reshape(p["N"], p["ldc"])[:, :p["M"]].T.astype(np.float64)
+        err = oracle.normwise_rel_err(got, ref)
+        worst = max(worst, err)
+        assert err <= tol, "problem %s: %.3e" % ((p["M"], p["N"], p["K"], p["transA"]), err)
+        if precision == "fp32":
+            bound = oracle.gamma(p["K"] + 2, 2.0 ** -23) * oracle.abs_product(*args)
+            assert np.all(np.abs(got - ref) <= bound)
+    return worst
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16x3", 1e-5)])
+def test_512_uneven_problems_against_oracle(precision, tol):
+    import torch
+    print("grouped 512 problems", precision, flush=True)
+    problems, data, arena, host = make_batch()
+    with mg.GroupedPlan(problems, precision) as plan:
+        info = plan.info()
+        assert info["tiles"] > 512 and info["workgroups"] > 0
+        plan.launch()
+        torch.cuda.synchronize()
+    worst = check_batch(problems, data, arena.cpu().numpy(), precision, tol)
+    print("worst normwise error %.3e" % worst, flush=True)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_graph_replay_equals_direct_launch_bitwise(precision):
+    """Several replays, with eager work and synchronisations in between,
+    each from the same initial C: every replay equals the direct launch."""
+    import torch
+    problems, data, arena, host = make_batch(count=96, seed=5)
+    init = torch.from_numpy(host).cuda()
+    with mg.GroupedPlan(problems, precision) as plan:
+        plan.run()
+        torch.cuda.synchronize()
+        direct = arena.clone()
+        for r in range(4):
+            arena.copy_(init)
+            scratch = torch.randn(1 << 20, device="cuda")
+            scratch.mul_(2.0).sum().item()          # unrelated eager work
+            plan.launch()
+            torch.cuda.synchronize()
+            assert torch.equal(arena, direct), "replay %d differs" % r
+
+
+@pytest.mark.gpu
+def test_grouped_equals_single_calls_with_same_tile():
+    """Variant 1 (128x128x16) is the single-call configuration 0: the same
+    tile code, so the results are bitwise equal."""
+    import torch
+    problems, data, arena, host = make_batch(count=40, seed=7)
+    init = torch.from_numpy(host).cuda()
+    assert gp.variant_info("fp32", 1) == {"bm": 128, "bn": 128, "bk": 16}
+    assert mg.config_info("fp32", 0)["bk"] == 16
+    with mg.GroupedPlan(problems, "fp32", bucket_configs=[1, 1, 1, 1]) as plan:
+        plan.launch()
+        torch.cuda.synchronize()
+    grouped = arena.clone()
+    arena.copy_(init)
+    for p in problems:
+        mg.sgemm(p["transA"], p["transB"], p["M"], p["N"], p["K"], p["alpha"], p["A"], p["lda"],
+                 p["B"], p["ldb"], p["beta"], p["C"], p["ldc"], config=0)
+    torch.cuda.synchronize()
+    assert torch.equal(arena, grouped)
+
+
+@pytest.mark.gpu
+def test_edge_problems_in_a_batch():
+    """alpha = 0 (C = beta C, A holds NaN and is not read), beta = 0 with
+    NaN in C, K = 0, an empty problem, and 1 x 1 x 1."""
+    import torch
+    rng = np.random.default_rng(3)
+    specs = [(50, 40, 30, 0.0, 2.0), (70, 33, 20, 1.0, 0.0), (20, 20, 0, 1.5, -1.0),
+             (0, 10, 10, 1.0, 1.0), (1, 1, 1, 1.0, 1.0), (300, 129, 65, -1.0, 0.5)]
+    probs, keep, hosts = [], [], []
+    for (M, N, K, al, be) in specs:
+        A = synth.matrix(rng, M, K, max(1, M)) if K else np.zeros(1, np.float32)
+        if al == 0.0:
+            A = np.full_like(A, np.nan)
+        B = synth.matrix(rng, K, N, max(1, K)) if K else np.zeros(1, np.float32)
+        C = synth.matrix(rng, M, N, max(1, M)) if M else np.zeros(1, np.float32)
+        if be == 0.0:
+            C = np.full_like(C, np.nan)
+        t = [torch.from_numpy(x.copy()).cuda() for x in (A, B, C)]
+        keep.append(t)
+        hosts.append((A, B, C))
+        probs.append(dict(transA="N", transB="N", M=M, N=N, K=K, alpha=al, beta=be, A=t[0],
+                          lda=max(1, M), B=t[1], ldb=max(1, K), C=t[2], ldc=max(1, M)))
+    with mg.GroupedPlan(probs, "fp32") as plan:
+        plan.launch()
+        torch.cuda.synchronize()
+    for p, (A, B, C), t in zip(probs, hosts, keep):
+        M, N = p["M"], p["N"]
+        if M == 0:
+            continue
+        ref = oracle.sgemm("N", "N", M, N, p["K"], p["alpha"], A, p["lda"], B, p["ldb"],
+                           p["beta"], C, p["ldc"])
+        got = t[2].cpu().numpy().reshape(N, p["ldc"])[:, :M].T.astype(np.float64)
+        assert np.all(np.isfinite(got))
+        assert oracle.normwise_rel_err(got, ref) <= 1e-6
+
+
+@pytest.mark.gpu
+def test_tuner_returns_valid_configs_and_plan_stays_correct(tmp_path):
+    import torch
+    problems, data, arena, host = make_batch(count=64, seed=11)
+    init = torch.from_numpy(host).cuda()
+    cache = str(tmp_path / "tune.json")
+    cfg, ms = mg.tune_grouped(problems, "fp32", reps=2, cache=cache)
+    assert len(cfg) == 4 and all(0 <= c < 3 for c in cfg) and ms > 0
+    cfg2, ms2 = mg.tune_grouped(problems, "fp32", cache=cache)      # cache hit
+    assert cfg2 == cfg and ms2 is None
+    arena.copy_(init)
+    with mg.GroupedPlan(problems, "fp32", bucket_configs=cfg) as plan:
+        plan.launch()
+        torch.cuda.synchronize()
+    check_batch(problems, data, arena.cpu().numpy(), "fp32", 1e-5)
+
+
+@pytest.mark.gpu
+def test_plan_destroyed_twice_is_detected():
+    problems, data, arena, host = make_batch(count=4, seed=2)
+    plan = mg.GroupedPlan(problems, "fp32")
+    handle = plan._plan
+    plan.close()
+    assert mg.lib().mgemm_grouped_plan_destroy(handle) == _lib.ERR_BAD_PLAN
+    assert mg.lib().mgemm_grouped_plan_launch(handle, None) == _lib.ERR_BAD_PLAN
