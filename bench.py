@@ -26,9 +26,9 @@ PEAK = {"fp32": 157.3, "bf16": 2516.6, "fp16": 2516.6}     # dense MFMA, TFLOP/s
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SOURCES = {
-    "fp32": ["sgemm_f32.hip", "tile_common.hpp"],
-    "bf16x3": ["sgemm_lowp.hip", "tile_common.hpp"],
-    "fp16s": ["sgemm_lowp.hip", "tile_common.hpp"],
+    "fp32": ["sgemm_f32.hip", "tile_f32.hpp", "tile_common.hpp"],
+    "bf16x3": ["sgemm_lowp.hip", "tile_lowp.hpp", "tile_common.hpp"],
+    "fp16s": ["sgemm_lowp.hip", "tile_lowp.hpp", "tile_common.hpp"],
 }
 
 
@@ -100,6 +100,8 @@ def main():
     ap.add_argument("--no-forms", action="store_true",
                     help="time only the FP32 path (for profiling runs)")
     ap.add_argument("--cold-reps", type=int, default=7)
+    ap.add_argument("--no-grouped", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -219,21 +221,116 @@ def main():
                          "normwise_err": h["err"],
                          "mfma_frac": round(h["tflops"] / PEAK["fp16"], 4)}
 
+    if not args.no_grouped:
+        line["grouped"] = bench_grouped(args, mg, torch)
+    if not args.no_dense:
+        line["dense_layer"] = bench_dense(args, mg, torch)
+
     if not args.no_cpu_baseline:
-        # The oracle on columns 0..J-1 of the same product (every entry of a
-        # column is one 8192-long FP64 dot product).
-        J = max(1, min(n, 2048 * 8192 // n * 8192 // n))
-        log("cpu baseline: oracle on %d columns ..." % J)
+        line["cpu_baseline"] = cpu_baseline(oracle, case, n, alpha, beta, ld)
+    print(json.dumps(line), flush=True)
+
+
+def cpu_baseline(oracle, case, n, alpha, beta, ld, target_s=12.0):
+    """The FP64 oracle, as it is, on columns 0..J-1 of the same product:
+    a 128-column pilot sets J for about `target_s` seconds of work, then
+    the J-column run is timed (every output is one n-long FP64 dot)."""
+    def run(J):
         t0 = time.perf_counter()
         oracle.sgemm("N", "N", n, J, n, alpha, case["A"], ld, case["B"], ld, beta,
                      case["C"], ld)
-        dt = time.perf_counter() - t0
-        line["cpu_baseline"] = {
-            "value": round(2.0 * n * n * J / dt / 1e12, 6), "unit": "TFLOP/s",
+        return time.perf_counter() - t0
+    pilot = min(n, 128)
+    t_pilot = run(pilot)
+    J = int(max(pilot, min(n, pilot * target_s / max(t_pilot, 1e-3))))
+    log("cpu baseline: oracle on %d columns ..." % J)
+    dt = run(J)
+    return {"value": round(2.0 * n * n * J / dt / 1e12, 6), "unit": "TFLOP/s",
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "FP64 oracle, columns 0..%d of the same %d^3 NN product "
                       "(%d x %d outputs), %.1f s" % (J - 1, n, n, J, dt)}
-    print(json.dumps(line), flush=True)
+
+
+def bench_grouped(args, mg, torch):
+    """512 independent GEMMs, M, N, K uniform on {16..512}, transA N/T, alpha
+    = beta = 1: a tuned plan replayed from its HIP graph against one library
+    launch per GEMM."""
+    import ctypes
+    import numpy as np
+    import synth
+    shapes = synth.grouped_problems(0, 512, 16, 512)
+    data = synth.grouped_data(shapes, seed=1)
+    sizes = [d[k].size for d in data for k in ("A", "B", "C")]
+    offs, tot = [], 0
+    for sz in sizes:
+        offs.append(tot)
+        tot += (sz + 63) // 64 * 64
+    host = np.zeros(tot, dtype=np.float32)
+    for k, (d, key) in enumerate((d, key) for d in data for key in ("A", "B", "C")):
+        host[offs[k]:offs[k] + d[key].size] = d[key]
+    init = torch.from_numpy(host).cuda()
+    arena = init.clone()
+    base = arena.data_ptr()
+    probs = []
+    for i, (sh, d) in enumerate(zip(shapes, data)):
+        probs.append(dict(sh, alpha=1.0, beta=1.0, A=base + 4 * offs[3 * i], lda=d["lda"],
+                          B=base + 4 * offs[3 * i + 1], ldb=d["ldb"],
+                          C=base + 4 * offs[3 * i + 2], ldc=d["ldc"]))
+    flops = sum(2.0 * p["M"] * p["N"] * p["K"] for p in probs)
+    stream = torch.cuda.current_stream()
+    L = mg.lib()
+    h = stream.cuda_stream
+    out = {"workload": "512 GEMMs, M,N,K ~ U{16..512}, transA N/T, alpha=beta=1, seed 0",
+           "gflop_per_step": round(flops / 1e9, 3)}
+    for prec in ("fp32", "bf16x3"):
+        cfg, _ = mg.tune_grouped(probs, prec, reps=3)
+        arena.copy_(init)
+        plan = mg.GroupedPlan(probs, prec, bucket_configs=cfg)
+        ms_graph = timed(lambda: plan.launch(stream), args.steps, args.warmup, stream)
+        pcode = mg.PRECISIONS[prec]
+        calls = [(p["transA"].encode(), p["transB"].encode(), p["M"], p["N"], p["K"],
+                  ctypes.c_float(p["alpha"]), p["A"], p["lda"], p["B"], p["ldb"],
+                  ctypes.c_float(p["beta"]), p["C"], p["ldc"], h, pcode, -1) for p in probs]
+
+        def eager():
+            for c in calls:
+                L.mgemm_sgemm_ex(*c)
+        ms_eager = timed(eager, max(3, args.steps // 4), 2, stream)
+        info = plan.info()
+        plan.close()
+        out[prec] = {"bucket_configs": cfg, "tiles": info["tiles"],
+                     "workgroups": info["workgroups"],
+                     "graph_ms": round(ms_graph, 4), "tflops": round(flops / ms_graph / 1e9, 3),
+                     "eager_ms": round(ms_eager, 4),
+                     "eager_tflops": round(flops / ms_eager / 1e9, 3),
+                     "speedup_vs_eager": round(ms_eager / ms_graph, 3)}
+        log("grouped %s: graph %.3f ms (%.1f TFLOP/s), one launch per GEMM %.3f ms" %
+            (prec, ms_graph, flops / ms_graph / 1e9, ms_eager))
+    return out
+
+
+def bench_dense(args, mg, torch):
+    """Dense layer Y = X W (X 8192 x 1024, W 1024 x 4096) forward + hand-written
+    backward (dX = G W^T, dW = X^T G): three GEMMs per step."""
+    import synth
+    X, W, G = synth.dense_layer(0, 8192, 1024, 4096)
+    Xd = torch.from_numpy(X).cuda().requires_grad_()
+    Wd = torch.from_numpy(W).cuda().requires_grad_()
+    Gd = torch.from_numpy(G).cuda()
+    flops = 3 * 2.0 * 8192 * 1024 * 4096
+    out = {"workload": "X 8192x1024, W 1024x4096, fwd + bwd (3 GEMMs)"}
+    stream = torch.cuda.current_stream()
+    for prec in ("fp32", "bf16x3"):
+        def step():
+            Xd.grad = None
+            Wd.grad = None
+            mg.linear(Xd, Wd, precision=prec).backward(Gd)
+        ms = timed(step, max(5, args.steps // 2), 2, stream)
+        out[prec] = {"ms": round(ms, 4), "tflops": round(flops / ms / 1e9, 3)}
+        log("dense layer %s: %.3f ms per fwd+bwd (%.1f TFLOP/s)" % (prec, ms, flops / ms / 1e9))
+    return out
+
+
 
 
 if __name__ == "__main__":

@@ -354,3 +354,9 @@ def test_dense_grads_match_numpy():
     X64, W64, G64 = (v.astype(np.float64) for v in (X, W, G))
     assert oracle.normwise_rel_err(dX, G64 @ W64.T) <= 1e-13
     assert oracle.normwise_rel_err(dW, X64.T @ G64) <= 1e-13
+
+
+def test_dense_loss_matches_numpy():
+    X, W, G = (v.astype(np.float64) for v in synth.dense_layer(4, 20, 12, 16))
+    want = float(np.sum((X @ W) * G))
+    assert abs(oracle.dense_loss(X, W, G) - want) <= 1e-12 * max(1.0, abs(want))
