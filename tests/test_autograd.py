@@ -69,7 +69,7 @@ def test_backward_mapping_matches_finite_differences():
         assert abs(fd - dW[r, c]) <= 1e-9 * max(1.0, abs(fd))
 
 
-def test_mapping_matches_the_north_star_calls():
+def test_mapping_matches_the_dense_layer_calls():
     """The three calls of the 8192 x 1024 x 4096 layer."""
     # Y = X W: X (8192 x 1024), W (1024 x 4096), both contiguous.
     assert matmul_args((8192, 1024), (1024, 1), (1024, 4096), (4096, 1)) == \
