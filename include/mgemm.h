@@ -100,9 +100,34 @@ int mgemm_config_count(int precision);
 int mgemm_config_info(int precision, int config, int *bm, int *bn, int *bk,
                       int *threads);
 
-/* The configuration mgemm_sgemm_ex(..., config = -1) would use. */
+/* The configuration mgemm_sgemm_ex(..., config = -1) would use: a choice
+ * recorded for exactly this (precision, trans pair, M, N, K), else the
+ * built-in size heuristic.  -1 for a bad trans flag. */
 int mgemm_default_config(int precision, char transA, char transB,
                          int64_t M, int64_t N, int64_t K);
+
+/*
+ * Autotuner for single calls: runs the product once per configuration as a
+ * warm-up and `reps` times timed (HIP events on `stream`), keeps the fastest
+ * (best time over reps) and records it as the choice for this exact
+ * (precision, trans pair, M, N, K), so later calls with config = -1 use it.
+ * Arguments as for mgemm_sgemm_ex; C is overwritten (with beta != 0 it is
+ * updated once per run), so tune on scratch output.  Synchronises `stream`.
+ * *best_config and *best_ms (either may be NULL) receive the result.
+ */
+int mgemm_tune_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
+                     float alpha, const float *A, int64_t lda,
+                     const float *B, int64_t ldb,
+                     float beta, float *C, int64_t ldc, void *stream,
+                     int precision, int reps, int *best_config, float *best_ms);
+
+/* Record a choice without timing (e.g. replayed from a saved tuning run);
+ * returns MGEMM_ERR_UNSUPPORTED for an unknown precision or configuration. */
+int mgemm_record_choice(int precision, char transA, char transB,
+                        int64_t M, int64_t N, int64_t K, int config);
+
+/* Forget every recorded choice. */
+int mgemm_clear_choices(void);
 
 /* ---- many independent products in one persistent launch ---------------- */
 

@@ -12,8 +12,8 @@ current HIP stream.  PyTorch supplies device memory and streams.
 """
 from ._lib import (MgemmError, PREC_BF16X3, PREC_FP16_SCALED, PREC_FP32, PRECISIONS,
                    check, lib)
-from .api import (config_count, config_info, default_config, matmul, matmul_args, sgemm,
-                  stream_handle, version)
+from .api import (clear_choices, config_count, config_info, default_config, matmul,
+                  matmul_args, record_choice, sgemm, stream_handle, tune_sgemm, version)
 
 
 def linear(X, W, precision="fp32"):
@@ -26,4 +26,5 @@ from .grouped import GroupedPlan, tune as tune_grouped  # noqa: E402
 
 __all__ = ["GroupedPlan", "tune_grouped", "MgemmError", "PREC_FP32", "PREC_BF16X3", "PREC_FP16_SCALED", "PRECISIONS",
            "sgemm", "matmul", "matmul_args", "linear", "config_count", "config_info",
-           "default_config", "version", "lib", "check", "stream_handle"]
+           "default_config", "version", "lib", "check", "stream_handle", "tune_sgemm",
+           "record_choice", "clear_choices"]

@@ -49,6 +49,11 @@ _SIGS = {
     "mgemm_config_info": (_i32, [_i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                  ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "mgemm_default_config": (_i32, [_i32, _ch, _ch, _i64, _i64, _i64]),
+    "mgemm_tune_sgemm": (_i32, [_ch, _ch, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32,
+                                _vp, _i64, _vp, _i32, _i32, ctypes.POINTER(_i32),
+                                ctypes.POINTER(ctypes.c_float)]),
+    "mgemm_record_choice": (_i32, [_i32, _ch, _ch, _i64, _i64, _i64, _i32]),
+    "mgemm_clear_choices": (_i32, []),
     "mgemm_grouped_plan_create": (_i32, [ctypes.POINTER(Problem), _i64, _i32,
                                          ctypes.POINTER(_i32), _vp, ctypes.POINTER(_vp),
                                          ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),

@@ -126,5 +126,30 @@ def default_config(precision, transA, transB, M, N, K):
                                       M, N, K)
 
 
+def tune_sgemm(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, *,
+               precision="fp32", reps=3, stream=None):
+    """Time every tile configuration for this product (C is overwritten) and
+    record the fastest as the library's choice for it.  Returns
+    (config, milliseconds)."""
+    for t, n in ((A, "A"), (B, "B"), (C, "C")):
+        _check_tensor(t, n)
+    cfg = ctypes.c_int(-1)
+    ms = ctypes.c_float(0.0)
+    check(lib().mgemm_tune_sgemm(transA.encode(), transB.encode(), M, N, K, alpha, _ptr(A), lda,
+                                 _ptr(B), ldb, beta, _ptr(C), ldc, stream_handle(stream),
+                                 _prec(precision), reps, ctypes.byref(cfg), ctypes.byref(ms)))
+    return cfg.value, ms.value
+
+
+def record_choice(precision, transA, transB, M, N, K, config):
+    """Make `config` the choice for this exact product (no timing)."""
+    check(lib().mgemm_record_choice(_prec(precision), transA.encode(), transB.encode(), M, N,
+                                    K, config))
+
+
+def clear_choices():
+    check(lib().mgemm_clear_choices())
+
+
 def version():
     return lib().mgemm_version()

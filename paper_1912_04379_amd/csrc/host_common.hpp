@@ -29,4 +29,7 @@ int check_device(int* out_dev);
 // Number of tile configurations of a precision.
 int config_count(int precision);
 
+// Configuration recorded by the tuner for exactly this product, or -1.
+int recorded_choice(int precision, int ta, int tb, int64_t M, int64_t N, int64_t K);
+
 }  // namespace mgemm

@@ -15,7 +15,7 @@ struct TileConfigInfo {
 // FP32 MFMA path.
 int f32_config_count();
 TileConfigInfo f32_config_info(int cfg);
-int f32_default_config(int64_t M, int64_t N, int64_t K);
+int f32_default_config(bool transA, bool transB, int64_t M, int64_t N, int64_t K);
 hipError_t launch_f32(int cfg, bool transA, bool transB, const GemmDesc& d,
                       hipStream_t stream);
 
@@ -30,10 +30,25 @@ hipError_t launch_bf16x3(int cfg, bool transA, bool transB, const GemmDesc& d,
 int f16s_config_count();
 TileConfigInfo f16s_config_info(int cfg);
 int f16s_default_config(int64_t M, int64_t N, int64_t K);
+// FP16 exponent pre-pass; `partial` is scratch of f16_partial_floats().
+int64_t f16_partial_floats(int64_t M, int64_t N, int64_t K);
 hipError_t launch_f16_exponents(bool transA, bool transB, const GemmDesc& d,
-                                int* expA, int* expB, hipStream_t stream);
+                                int* expA, int* expB, float* partial, hipStream_t stream);
 hipError_t launch_f16s(int cfg, bool transA, bool transB, const GemmDesc& d,
                        hipStream_t stream);
+
+// Pre-packed 16-bit path (direct-to-LDS engine).  Configurations 0..5 of
+// this family are exposed as configurations 4..9 of the BF16x3 and FP16
+// forms (3 is FP16 only).  The caller provides `workspace` of
+// packed_workspace_bytes(); for the FP16 form d.expA / d.expB must already
+// hold the panel exponents.
+constexpr int LOWP_INSTAGE_CONFIGS = 4;
+int packed_config_count();
+TileConfigInfo packed_config_info(int cfg);
+int64_t packed_workspace_bytes(bool bf16x3, int cfg, int64_t M, int64_t N, int64_t K);
+bool packed_supported(bool bf16x3, int cfg, int64_t M, int64_t N, int64_t K);
+hipError_t launch_packed(bool bf16x3, int cfg, bool transA, bool transB, const GemmDesc& d,
+                         char* workspace, hipStream_t stream);
 
 // C <- beta*C (beta == 0 writes zeros without reading C).
 hipError_t launch_scale_c(const GemmDesc& d, hipStream_t stream);

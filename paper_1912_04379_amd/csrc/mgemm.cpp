@@ -114,9 +114,11 @@ int config_count(int precision) {
     }
 }
 
-static int default_config(int precision, int64_t M, int64_t N, int64_t K) {
+static int default_config(int precision, int ta, int tb, int64_t M, int64_t N, int64_t K) {
+    const int tuned = recorded_choice(precision, ta, tb, M, N, K);
+    if (tuned >= 0) return tuned;
     switch (precision) {
-        case MGEMM_PREC_FP32: return f32_default_config(M, N, K);
+        case MGEMM_PREC_FP32: return f32_default_config(ta, tb, M, N, K);
         case MGEMM_PREC_BF16X3: return bf16x3_default_config(M, N, K);
         case MGEMM_PREC_FP16_SCALED: return f16s_default_config(M, N, K);
         default: return -1;
@@ -150,31 +152,52 @@ static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K,
         e = launch_scale_c(d, s);
         return e == hipSuccess ? MGEMM_OK : hip_fail(e, "scale kernel launch");
     }
-    const int cfg = config >= 0 ? config : default_config(precision, M, N, K);
-    switch (precision) {
-        case MGEMM_PREC_FP32:
-            e = launch_f32(cfg, ta, tb, d, s);
-            break;
-        case MGEMM_PREC_BF16X3:
-            e = launch_bf16x3(cfg, ta, tb, d, s);
-            break;
-        default: {
-            // Stream-ordered workspace for the panel exponents.
-            const int64_t pa = (M + 31) / 32, pb = (N + 31) / 32;
-            int* ex = nullptr;
-            e = hipMallocAsync((void**)&ex, (size_t)(pa + pb) * sizeof(int), s);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                return fail(MGEMM_ERR_ALLOC, "workspace for FP16 panel exponents");
-            }
-            d.expA = ex;
-            d.expB = ex + pa;
-            e = launch_f16_exponents(ta, tb, d, ex, ex + pa, s);
-            if (e == hipSuccess) e = launch_f16s(cfg, ta, tb, d, s);
-            hipError_t e2 = hipFreeAsync(ex, s);
-            if (e == hipSuccess) e = e2;
-            break;
+    int cfg = config >= 0 ? config : default_config(precision, ta, tb, M, N, K);
+    if (precision == MGEMM_PREC_FP32) {
+        e = launch_f32(cfg, ta, tb, d, s);
+        return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
+    }
+    const bool bf = precision == MGEMM_PREC_BF16X3;
+    bool packed = cfg >= LOWP_INSTAGE_CONFIGS;
+    if (packed && !packed_supported(bf, cfg - LOWP_INSTAGE_CONFIGS, M, N, K)) {
+        // Not available for this form, or lane offsets would not fit in 31
+        // bits: stage in place with the same tile instead.
+        packed = false;
+        cfg = 0;
+    }
+    // Stream-ordered workspace: FP16 panel exponents (+ pass-1 partial
+    // maxima) and/or packed operands.
+    const int64_t pa = (M + 31) / 32, pb = (N + 31) / 32;
+    const int64_t part_bytes = bf ? 0 : (f16_partial_floats(M, N, K) * 4 + 255) / 256 * 256;
+    const int64_t exp_bytes =
+        bf ? 0 : ((pa + pb) * (int64_t)sizeof(int) + 255) / 256 * 256 + part_bytes;
+    const int64_t pack_bytes =
+        packed ? packed_workspace_bytes(bf, cfg - LOWP_INSTAGE_CONFIGS, M, N, K) : 0;
+    char* ws = nullptr;
+    if (exp_bytes + pack_bytes > 0) {
+        e = hipMallocAsync((void**)&ws, (size_t)(exp_bytes + pack_bytes), s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MGEMM_ERR_ALLOC, "stream-ordered workspace");
         }
+    }
+    e = hipSuccess;
+    if (!bf) {
+        d.expA = reinterpret_cast<int*>(ws);
+        d.expB = reinterpret_cast<int*>(ws) + pa;
+        e = launch_f16_exponents(ta, tb, d, reinterpret_cast<int*>(ws),
+                                 reinterpret_cast<int*>(ws) + pa,
+                                 reinterpret_cast<float*>(ws + exp_bytes - part_bytes), s);
+    }
+    if (e == hipSuccess) {
+        if (packed)
+            e = launch_packed(bf, cfg - LOWP_INSTAGE_CONFIGS, ta, tb, d, ws + exp_bytes, s);
+        else
+            e = bf ? launch_bf16x3(cfg, ta, tb, d, s) : launch_f16s(cfg, ta, tb, d, s);
+    }
+    if (ws) {
+        hipError_t e2 = hipFreeAsync(ws, s);
+        if (e == hipSuccess) e = e2;
     }
     return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
 }
@@ -216,9 +239,9 @@ int mgemm_config_info(int precision, int config, int* bm, int* bn, int* bk, int*
 
 int mgemm_default_config(int precision, char transA, char transB, int64_t M, int64_t N,
                          int64_t K) {
-    (void)transA;
-    (void)transB;
-    return default_config(precision, M, N, K);
+    const int ta = trans_code(transA), tb = trans_code(transB);
+    if (ta < 0 || tb < 0) return -1;
+    return default_config(precision, ta, tb, M, N, K);
 }
 
 const char* mgemm_status_string(int status) {

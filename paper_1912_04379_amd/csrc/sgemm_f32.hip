@@ -7,7 +7,7 @@
 namespace mgemm {
 
 template <class Cfg, bool AK, bool BKC, bool BUF>
-__global__ __launch_bounds__(Cfg::NT) void sgemm_f32_kernel(GemmDesc d, uint32_t tiles_m,
+__global__ __launch_bounds__(Cfg::NT, Cfg::WPE) void sgemm_f32_kernel(GemmDesc d, uint32_t tiles_m,
                                                            uint32_t tiles_n) {
     __shared__ __attribute__((aligned(16))) float smem[Cfg::SMEM_FLOATS];
     uint32_t tm, tn;
@@ -19,11 +19,11 @@ template <class Cfg, bool AK, bool BKC>
 static void launch_trans(dim3 grid, const GemmDesc& d, uint32_t tm, uint32_t tn,
                          hipStream_t s) {
     if (buffer_path_ok(d))
-        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, AK, BKC, true>), grid, dim3(Cfg::NT), 0, s,
-                           d, tm, tn);
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, AK, BKC, true>), grid, dim3(Cfg::NT),
+                           Cfg::PAD_BYTES, s, d, tm, tn);
     else
-        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, AK, BKC, false>), grid, dim3(Cfg::NT), 0, s,
-                           d, tm, tn);
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, AK, BKC, false>), grid, dim3(Cfg::NT),
+                           Cfg::PAD_BYTES, s, d, tm, tn);
 }
 
 template <class Cfg>
@@ -51,11 +51,15 @@ using F32Cfg0 = CfgF32<128, 128, 16, 2, 2>;  // 4 waves of 64x64
 using F32Cfg1 = CfgF32<64, 64, 16, 2, 2>;    // 4 waves of 32x32 (small problems)
 using F32Cfg2 = CfgF32<128, 128, 32, 2, 2>;  // deeper slab
 using F32Cfg3 = CfgF32<256, 128, 16, 2, 2>;  // 4 waves of 128x64
+using F32Cfg4 = CfgF32<128, 128, 16, 2, 2, 2, 2>;  // as 0, at most 2 work-groups per CU
+using F32Cfg5 = CfgF32<256, 128, 16, 2, 2, 2>;  // as 3, held to 2 waves per SIMD
+using F32Cfg6 = CfgF32<128, 256, 16, 2, 2, 2>;  // 4 waves of 64x128, 2 waves per SIMD
+using F32Cfg7 = CfgF32<128, 128, 32, 2, 2, 2, 2>;  // as 2, at most 2 work-groups per CU
 
 template <class Cfg>
 static TileConfigInfo info_of() { return {Cfg::BM, Cfg::BN, Cfg::BK, Cfg::NT}; }
 
-int f32_config_count() { return 4; }
+int f32_config_count() { return 8; }
 
 TileConfigInfo f32_config_info(int cfg) {
     switch (cfg) {
@@ -63,14 +67,24 @@ TileConfigInfo f32_config_info(int cfg) {
         case 1: return info_of<F32Cfg1>();
         case 2: return info_of<F32Cfg2>();
         case 3: return info_of<F32Cfg3>();
+        case 4: return info_of<F32Cfg4>();
+        case 5: return info_of<F32Cfg5>();
+        case 6: return info_of<F32Cfg6>();
+        case 7: return info_of<F32Cfg7>();
         default: return {0, 0, 0, 0};
     }
 }
 
-int f32_default_config(int64_t M, int64_t N, int64_t K) {
+int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
     (void)K;
     const int64_t big_tiles = ((M + 127) / 128) * ((N + 127) / 128);
-    return big_tiles >= 512 ? 0 : 1;
+    if (big_tiles < 512) return 1;
+    // Measured at 8192^3: 256x128 at 2 waves per SIMD is best for TN and NT
+    // (one operand or both k-contiguous with the other p-contiguous in the
+    // transposing direction); 128x128 for NN and TT.
+    const int64_t wide_tiles = ((M + 255) / 256) * ((N + 127) / 128);
+    if (ta != tb && wide_tiles >= 512) return 5;
+    return 0;
 }
 
 hipError_t launch_f32(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
@@ -79,6 +93,10 @@ hipError_t launch_f32(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t 
         case 1: return launch_cfg<F32Cfg1>(ta, tb, d, s);
         case 2: return launch_cfg<F32Cfg2>(ta, tb, d, s);
         case 3: return launch_cfg<F32Cfg3>(ta, tb, d, s);
+        case 4: return launch_cfg<F32Cfg4>(ta, tb, d, s);
+        case 5: return launch_cfg<F32Cfg5>(ta, tb, d, s);
+        case 6: return launch_cfg<F32Cfg6>(ta, tb, d, s);
+        case 7: return launch_cfg<F32Cfg7>(ta, tb, d, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -93,20 +93,33 @@ static int lowp_default(int64_t M, int64_t N) {
     return 3;
 }
 
-int bf16x3_config_count() { return 4; }
-TileConfigInfo bf16x3_config_info(int cfg) { return lowp_info(cfg); }
+static TileConfigInfo lowp_any_info(int cfg) {
+    return cfg < LOWP_INSTAGE_CONFIGS ? lowp_info(cfg)
+                                      : packed_config_info(cfg - LOWP_INSTAGE_CONFIGS);
+}
+
+int bf16x3_config_count() { return LOWP_INSTAGE_CONFIGS + packed_config_count(); }
+TileConfigInfo bf16x3_config_info(int cfg) { return lowp_any_info(cfg); }
+// Large products: pre-pack both operands and stream them into a 4-deep LDS
+// ring (the packing costs one extra read and write of A and B, ~10% at
+// 8192^3, and is repaid by the main loop).  Otherwise split while staging.
+static bool packed_pays(int64_t M, int64_t N, int64_t K) {
+    const int64_t tiles = ((M + 255) / 256) * ((N + 255) / 256);
+    return tiles >= 256 && K >= 512;
+}
+
 int bf16x3_default_config(int64_t M, int64_t N, int64_t K) {
-    (void)K;
+    if (packed_pays(M, N, K)) return LOWP_INSTAGE_CONFIGS + 1;   // 256x256, 4 x 16-k stages
     return lowp_default(M, N);
 }
 hipError_t launch_bf16x3(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
     return lowp_launch<Form::BF16X3>(cfg, ta, tb, d, s);
 }
 
-int f16s_config_count() { return 4; }
-TileConfigInfo f16s_config_info(int cfg) { return lowp_info(cfg); }
+int f16s_config_count() { return LOWP_INSTAGE_CONFIGS + packed_config_count(); }
+TileConfigInfo f16s_config_info(int cfg) { return lowp_any_info(cfg); }
 int f16s_default_config(int64_t M, int64_t N, int64_t K) {
-    (void)K;
+    if (packed_pays(M, N, K)) return LOWP_INSTAGE_CONFIGS + 3;   // 256x256, 4 x 32-k stages
     return lowp_default(M, N);
 }
 hipError_t launch_f16s(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
@@ -114,18 +127,32 @@ hipError_t launch_f16s(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t
 }
 
 // ---------------------------------------------------------------------------
-// FP16 pre-pass: one work-group per 32-wide panel.  Work-groups
-// [0, panels_a) take 32-row panels of op(A), the rest 32-column panels of
-// op(B).  amax = max |x| over the panel's P x K block (NaN if any element
-// is NaN); e = 15 - p where amax = f 2^p, f in [0.5, 1) (so amax 2^e is in
-// [2^14, 2^15)); e = 0 for amax == 0 or non-finite amax.
+// FP16 pre-pass.  The exponent of a 32-wide panel is e = 15 - p where
+// amax = f 2^p, f in [0.5, 1), is the panel's largest magnitude (so amax 2^e
+// lies in [2^14, 2^15)); e = 0 when amax is 0 or not finite or the panel
+// holds a NaN.  Panels of op(A) are 32 rows, panels of op(B) 32 columns,
+// both over the whole K.
+//
+// Pass 1: one work-group per (panel, 2048-deep range of k) writes the range's
+// amax (NaN if the range holds a NaN) to `partial`.  P-contiguous panels:
+// thread t reads row t % 32 of columns t / 32, t / 32 + 8, ... (each wave
+// instruction reads two 128-byte columns).  K-contiguous panels: the 256
+// threads walk each of the 32 rows along k.
+// Pass 2: one thread per panel reduces its ranges and writes e.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void f16_exponent_kernel(GemmDesc d, int ta, int tb,
-                                                           int64_t panels_a, int* expA,
-                                                           int* expB) {
-    __shared__ float red[4];
-    __shared__ int nan_seen;
-    const int64_t pid = blockIdx.x;
+constexpr int64_t EXP_KRANGE = 2048;
+
+int64_t f16_partial_floats(int64_t M, int64_t N, int64_t K) {
+    const int64_t nkr = K > 0 ? (K + EXP_KRANGE - 1) / EXP_KRANGE : 1;
+    return ((M + 31) / 32 + (N + 31) / 32) * nkr;
+}
+
+__global__ __launch_bounds__(256) void f16_amax_kernel(GemmDesc d, int ta, int tb,
+                                                       int64_t panels_a, int64_t nkr,
+                                                       float* __restrict__ partial) {
+    __shared__ float red_max[4];
+    __shared__ int red_nan[4];
+    const int64_t pid = blockIdx.x / nkr, kr = blockIdx.x % nkr;
     const bool is_a = pid < panels_a;
     const int64_t panel = is_a ? pid : pid - panels_a;
     const float* X = is_a ? d.A : d.B;
@@ -133,43 +160,78 @@ __global__ __launch_bounds__(256) void f16_exponent_kernel(GemmDesc d, int ta, i
     const int64_t P = is_a ? d.M : d.N;
     // op(A) rows are contiguous for A 'N'; op(B) columns are contiguous for B 'T'.
     const bool pcontig = is_a ? !ta : tb;
-    const int64_t p0 = panel * 32;
-    const int64_t rows = P - p0 < 32 ? P - p0 : 32;
-    const int64_t total = rows * d.K;
-    if (threadIdx.x == 0) nan_seen = 0;
-    __syncthreads();
+    const int64_t p0 = panel * 32, rows = P - p0 < 32 ? P - p0 : 32;
+    const int64_t k0 = kr * EXP_KRANGE, k1 = k0 + EXP_KRANGE < d.K ? k0 + EXP_KRANGE : d.K;
+    const int t = threadIdx.x;
     float amax = 0.0f;
-    bool nan = false;
-    for (int64_t e = threadIdx.x; e < total; e += 256) {
-        int64_t r, k;
-        if (pcontig) { r = e % rows; k = e / rows; }
-        else         { k = e % d.K; r = e / d.K; }
-        const float x = X[pcontig ? (p0 + r) + k * ld : k + (p0 + r) * ld];
-        nan |= x != x;
-        amax = fmaxf(amax, fabsf(x));
+    int nan = 0;
+    if (pcontig) {
+        const int r = t & 31;
+        if (r < rows)
+            for (int64_t k = k0 + (t >> 5); k < k1; k += 8) {
+                const float x = X[(p0 + r) + k * ld];
+                nan |= x != x;
+                amax = fmaxf(amax, fabsf(x));
+            }
+    } else {
+        for (int64_t r = 0; r < rows; ++r)
+            for (int64_t k = k0 + t; k < k1; k += 256) {
+                const float x = X[k + (p0 + r) * ld];
+                nan |= x != x;
+                amax = fmaxf(amax, fabsf(x));
+            }
     }
-    for (int o = 32; o > 0; o >>= 1) amax = fmaxf(amax, __shfl_xor(amax, o));
-    if (nan) nan_seen = 1;
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    for (int o = 32; o > 0; o >>= 1) {
+        amax = fmaxf(amax, __shfl_xor(amax, o));
+        nan |= __shfl_xor(nan, o);
+    }
+    if ((t & 63) == 0) {
+        red_max[t >> 6] = amax;
+        red_nan[t >> 6] = nan;
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        const float m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-        int e = 0;
-        if (!nan_seen && m > 0.0f && isfinite(m)) {
-            int p;
-            frexpf(m, &p);
-            e = 15 - p;
-        }
-        (is_a ? expA : expB)[panel] = e;
+    if (t == 0) {
+        const float m = fmaxf(fmaxf(red_max[0], red_max[1]), fmaxf(red_max[2], red_max[3]));
+        const int any_nan = red_nan[0] | red_nan[1] | red_nan[2] | red_nan[3];
+        partial[blockIdx.x] = any_nan ? __builtin_nanf("") : m;
     }
 }
 
+__global__ __launch_bounds__(256) void f16_exponent_kernel(int64_t panels_a, int64_t panels,
+                                                           int64_t nkr,
+                                                           const float* __restrict__ partial,
+                                                           int* __restrict__ expA,
+                                                           int* __restrict__ expB) {
+    const int64_t pid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (pid >= panels) return;
+    float m = 0.0f;
+    bool nan = false;
+    for (int64_t kr = 0; kr < nkr; ++kr) {
+        const float v = partial[pid * nkr + kr];
+        nan |= v != v;
+        m = fmaxf(m, v);
+    }
+    int e = 0;
+    if (!nan && m > 0.0f && isfinite(m)) {
+        int p;
+        frexpf(m, &p);
+        e = 15 - p;
+    }
+    if (pid < panels_a) expA[pid] = e;
+    else expB[pid - panels_a] = e;
+}
+
 hipError_t launch_f16_exponents(bool ta, bool tb, const GemmDesc& d, int* expA, int* expB,
-                                hipStream_t s) {
+                                float* partial, hipStream_t s) {
     const int64_t pa = (d.M + 31) / 32, pb = (d.N + 31) / 32;
-    if (pa + pb > 0x7fffffffLL) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(f16_exponent_kernel, dim3((uint32_t)(pa + pb)), dim3(256), 0, s, d,
-                       (int)ta, (int)tb, pa, expA, expB);
+    const int64_t nkr = d.K > 0 ? (d.K + EXP_KRANGE - 1) / EXP_KRANGE : 1;
+    const int64_t nwg = (pa + pb) * nkr;
+    if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
+    if (nwg == 0) return hipSuccess;
+    hipLaunchKernelGGL(f16_amax_kernel, dim3((uint32_t)nwg), dim3(256), 0, s, d, (int)ta,
+                       (int)tb, pa, nkr, partial);
+    hipLaunchKernelGGL(f16_exponent_kernel, dim3((uint32_t)((pa + pb + 255) / 256)), dim3(256), 0,
+                       s, pa, pa + pb, nkr, partial, expA, expB);
     return hipGetLastError();
 }
 

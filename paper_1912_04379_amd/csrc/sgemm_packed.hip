@@ -1,0 +1,196 @@
+// sgemm_packed.hip -- the BF16x3 and scaled-FP16 forms through pre-packed
+// operands: pack kernels (FP32 op(X) -> zero-padded 32 x 32 blocks of 16-bit
+// values, k contiguous) and the launchers of the direct-to-LDS tile engine
+// in tile_packed.hpp.
+#include "kernels.hpp"
+#include "tile_packed.hpp"
+
+namespace mgemm {
+
+// ---------------------------------------------------------------------------
+// Pack: one work-group (256 threads) per 32-row x 32-k region of op(X);
+// thread t owns 4 consecutive k of one row.  K-contiguous sources (A 'T',
+// B 'N') number the threads k-fastest (8 threads read one 128-byte row
+// segment); P-contiguous sources number them p-fastest (each of the 4 loads
+// reads 32 consecutive rows of one column).  The region lands in one 32 x 32
+// block (KW = 32) or two 32 x 16 blocks (KW = 16), each row-major with k
+// contiguous.  Elements outside P x K are written as zeros.
+// ---------------------------------------------------------------------------
+template <Form F, bool KC, int KW>
+__global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ X, int64_t ld,
+                                                   int64_t P, int64_t K, int64_t kb,
+                                                   int64_t kregions, int64_t nregions,
+                                                   char* __restrict__ hi, char* __restrict__ lo,
+                                                   const int* __restrict__ expo) {
+    constexpr int RB = 2 * KW;
+    const int t = threadIdx.x;
+    const int r = KC ? t >> 3 : t & 31;
+    const int kq = KC ? t & 7 : t >> 5;
+    for (int64_t g = blockIdx.x; g < nregions; g += gridDim.x) {
+        const int64_t pb = g / kregions, kr = g - pb * kregions;
+        const int64_t p = pb * 32 + r, k = kr * 32 + 4 * kq;
+        const int64_t blk = k / KW;
+        if (blk >= kb) continue;                       // past the last KW block
+        f32x4 v;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            float x = 0.0f;
+            if (p < P && k + e < K) x = X[KC ? (k + e) + p * ld : p + (k + e) * ld];
+            v[e] = x;
+        }
+        const int64_t off = ((pb * kb + blk) * 32 + r) * RB + (k % KW) * 2;
+        if constexpr (F == Form::BF16X3) {
+            u32x2 h2, l2;
+            split_bf16x4(v, h2, l2);
+            *reinterpret_cast<u32x2*>(hi + off) = h2;
+            *reinterpret_cast<u32x2*>(lo + off) = l2;
+        } else {
+            *reinterpret_cast<u32x2*>(hi + off) = scale_f16x4(v, expo[pb]);
+        }
+    }
+}
+
+template <Form F, int KW>
+static hipError_t launch_pack(bool kcontig, const float* X, int64_t ld, int64_t P, int64_t K,
+                              char* hi, char* lo, const int* expo, hipStream_t s) {
+    const int64_t pb = (P + 31) / 32, kb = (K + KW - 1) / KW, kreg = (K + 31) / 32;
+    const int64_t n = pb * kreg;
+    if (n == 0) return hipSuccess;
+    const uint32_t grid = (uint32_t)(n < 65536 ? n : 65536);
+    if (kcontig)
+        hipLaunchKernelGGL((pack_kernel<F, true, KW>), dim3(grid), dim3(256), 0, s, X, ld, P, K,
+                           kb, kreg, n, hi, lo, expo);
+    else
+        hipLaunchKernelGGL((pack_kernel<F, false, KW>), dim3(grid), dim3(256), 0, s, X, ld, P,
+                           K, kb, kreg, n, hi, lo, expo);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Main kernel and configurations.
+// ---------------------------------------------------------------------------
+template <class Cfg, Form F, bool BUF>
+__global__ __launch_bounds__(Cfg::NT, Cfg::WPE) void packed_kernel(GemmDesc d, PackedArgs pk,
+                                                        uint32_t tiles_m, uint32_t tiles_n) {
+    extern __shared__ __attribute__((aligned(16))) char packed_smem[];
+    uint32_t tm, tn;
+    grouped_tile<8>(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
+    tile_packed<Cfg, F, BUF>(d, pk, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, packed_smem);
+}
+
+// KW = 32: the in-staging engine's LDS layout (configuration 0 matches its
+// 256 x 256 tile bitwise); KW = 16: half-depth stages, so a 4-deep ring of
+// the 256 x 256 BF16x3 tile fits in 128 KB of LDS.
+using PKCfg0 = CfgPK<256, 256, 2, 4, 2, 32>;   // 8 waves of 128x64, 2 stages of 32 k
+using PKCfg1 = CfgPK<256, 256, 2, 4, 4, 16>;   // 8 waves of 128x64, 4 stages of 16 k
+using PKCfg2 = CfgPK<128, 128, 2, 2, 3, 32>;   // 4 waves of 64x64, 3 stages of 32 k
+using PKCfg3 = CfgPK<256, 256, 2, 4, 4, 32>;   // FP16 only: 4 stages of 32 k (128 KB)
+// Two work-groups per CU (72 KB of LDS each for BF16x3): their barriers are
+// independent, so one keeps the MFMA pipes busy while the other waits.
+using PKCfg4 = CfgPK<256, 128, 2, 2, 3, 16>;   // 4 waves of 128x64, 3 stages of 16 k
+using PKCfg5 = CfgPK<128, 256, 2, 2, 3, 16>;   // 4 waves of 64x128, 3 stages of 16 k
+
+template <class Cfg, Form F>
+static hipError_t launch_main(const GemmDesc& d, const PackedArgs& pk, hipStream_t s) {
+    const int64_t tiles_m = (d.M + Cfg::BM - 1) / Cfg::BM;
+    const int64_t tiles_n = (d.N + Cfg::BN - 1) / Cfg::BN;
+    if (tiles_m * tiles_n > 0xffffffffLL) return hipErrorInvalidValue;
+    constexpr int bytes = PackedStage<Cfg, F>::SMEM;
+    auto k = buffer_path_ok(d) ? packed_kernel<Cfg, F, true> : packed_kernel<Cfg, F, false>;
+    hipError_t e = hipFuncSetAttribute((const void*)k,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3((uint32_t)(tiles_m * tiles_n)), dim3(Cfg::NT), bytes, s, d, pk,
+                       (uint32_t)tiles_m, (uint32_t)tiles_n);
+    return hipGetLastError();
+}
+
+int packed_config_count() { return 6; }
+
+TileConfigInfo packed_config_info(int cfg) {
+    switch (cfg) {
+        case 0: return {PKCfg0::BM, PKCfg0::BN, PKCfg0::BK, PKCfg0::NT};
+        case 1: return {PKCfg1::BM, PKCfg1::BN, PKCfg1::BK, PKCfg1::NT};
+        case 2: return {PKCfg2::BM, PKCfg2::BN, PKCfg2::BK, PKCfg2::NT};
+        case 3: return {PKCfg3::BM, PKCfg3::BN, PKCfg3::BK, PKCfg3::NT};
+        case 4: return {PKCfg4::BM, PKCfg4::BN, PKCfg4::BK, PKCfg4::NT};
+        case 5: return {PKCfg5::BM, PKCfg5::BN, PKCfg5::BK, PKCfg5::NT};
+        default: return {0, 0, 0, 0};
+    }
+}
+
+static int packed_kw(int cfg) { return cfg == 1 || cfg == 4 || cfg == 5 ? 16 : 32; }
+
+// Bytes of device workspace for the packed operands.
+int64_t packed_workspace_bytes(bool bf16x3, int cfg, int64_t M, int64_t N, int64_t K) {
+    const int kw = packed_kw(cfg);
+    const int64_t kb = (K + kw - 1) / kw, blk = 64LL * kw;
+    const int64_t a = ((M + 31) / 32) * kb * blk, b = ((N + 31) / 32) * kb * blk;
+    return (bf16x3 ? 2 : 1) * (a + b);
+}
+
+// True when the configuration exists for the form and every lane offset of
+// the main loop fits in 31 bits (8 row blocks x the K extent of a block row).
+bool packed_supported(bool bf16x3, int cfg, int64_t M, int64_t N, int64_t K) {
+    (void)M;
+    (void)N;
+    if (cfg < 0 || cfg >= packed_config_count() || (bf16x3 && cfg == 3)) return false;
+    const int kw = packed_kw(cfg);
+    return 8 * ((K + kw - 1) / kw) * 64LL * kw < (1LL << 31);
+}
+
+hipError_t launch_packed(bool bf16x3, int cfg, bool ta, bool tb, const GemmDesc& d,
+                         char* workspace, hipStream_t s) {
+    const int kw = packed_kw(cfg);
+    const int64_t kb = (d.K + kw - 1) / kw, blk = 64LL * kw;
+    const int64_t pba = (d.M + 31) / 32, pbb = (d.N + 31) / 32;
+    const int64_t a = pba * kb * blk, b = pbb * kb * blk;
+    PackedArgs pk{};
+    pk.kb = kb;
+    pk.pb_a = pba;
+    pk.pb_b = pbb;
+    char* a_hi = workspace;
+    char* b_hi = workspace + a;
+    char* a_lo = bf16x3 ? workspace + a + b : nullptr;
+    char* b_lo = bf16x3 ? workspace + 2 * a + b : nullptr;
+    pk.a_hi = a_hi;
+    pk.b_hi = b_hi;
+    pk.a_lo = a_lo;
+    pk.b_lo = b_lo;
+    // op(A) is K-contiguous for A 'T'; op(B) is K-contiguous for B 'N'.
+    hipError_t e;
+    if (bf16x3 && kw == 32) {
+        e = launch_pack<Form::BF16X3, 32>(ta, d.A, d.lda, d.M, d.K, a_hi, a_lo, nullptr, s);
+        if (e == hipSuccess)
+            e = launch_pack<Form::BF16X3, 32>(!tb, d.B, d.ldb, d.N, d.K, b_hi, b_lo, nullptr, s);
+    } else if (bf16x3) {
+        e = launch_pack<Form::BF16X3, 16>(ta, d.A, d.lda, d.M, d.K, a_hi, a_lo, nullptr, s);
+        if (e == hipSuccess)
+            e = launch_pack<Form::BF16X3, 16>(!tb, d.B, d.ldb, d.N, d.K, b_hi, b_lo, nullptr, s);
+    } else if (kw == 32) {
+        e = launch_pack<Form::F16S, 32>(ta, d.A, d.lda, d.M, d.K, a_hi, nullptr, d.expA, s);
+        if (e == hipSuccess)
+            e = launch_pack<Form::F16S, 32>(!tb, d.B, d.ldb, d.N, d.K, b_hi, nullptr, d.expB, s);
+    } else {
+        e = launch_pack<Form::F16S, 16>(ta, d.A, d.lda, d.M, d.K, a_hi, nullptr, d.expA, s);
+        if (e == hipSuccess)
+            e = launch_pack<Form::F16S, 16>(!tb, d.B, d.ldb, d.N, d.K, b_hi, nullptr, d.expB, s);
+    }
+    if (e != hipSuccess) return e;
+    switch (cfg) {
+        case 0: return bf16x3 ? launch_main<PKCfg0, Form::BF16X3>(d, pk, s)
+                              : launch_main<PKCfg0, Form::F16S>(d, pk, s);
+        case 1: return bf16x3 ? launch_main<PKCfg1, Form::BF16X3>(d, pk, s)
+                              : launch_main<PKCfg1, Form::F16S>(d, pk, s);
+        case 2: return bf16x3 ? launch_main<PKCfg2, Form::BF16X3>(d, pk, s)
+                              : launch_main<PKCfg2, Form::F16S>(d, pk, s);
+        case 3: return bf16x3 ? hipErrorInvalidValue : launch_main<PKCfg3, Form::F16S>(d, pk, s);
+        case 4: return bf16x3 ? launch_main<PKCfg4, Form::BF16X3>(d, pk, s)
+                              : launch_main<PKCfg4, Form::F16S>(d, pk, s);
+        case 5: return bf16x3 ? launch_main<PKCfg5, Form::BF16X3>(d, pk, s)
+                              : launch_main<PKCfg5, Form::F16S>(d, pk, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mgemm

@@ -20,9 +20,13 @@
 
 namespace mgemm {
 
-template <int BM_, int BN_, int BK_, int WGM_, int WGN_>
+// WPE: waves per SIMD the kernel is compiled for (0 = the compiler's choice;
+// otherwise registers are held to 512 / WPE per lane).  OCC: at most this
+// many work-groups per CU (0 = no cap), enforced by reserving LDS at launch
+// (a whole number of rounds of work-groups avoids a part-empty last round).
+template <int BM_, int BN_, int BK_, int WGM_, int WGN_, int WPE_ = 0, int OCC_ = 0>
 struct CfgF32 {
-    static constexpr int BM = BM_, BN = BN_, BK = BK_;
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, WPE = WPE_, OCC = OCC_;
     static constexpr int WGM = WGM_, WGN = WGN_;
     static constexpr int NT = 64 * WGM * WGN;
     static constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -31,6 +35,12 @@ struct CfgF32 {
                                       // aligned rows, conflict-free b128 reads
     static constexpr int STAGE = (BM + BN) * S;
     static constexpr int SMEM_FLOATS = 2 * STAGE;
+    // Dynamic LDS reserved (unused) so that OCC + 1 work-groups do not fit
+    // in a CU's 160 KB.
+    static constexpr int LDS_CU = 160 * 1024;
+    static constexpr int CAP_BYTES = OCC > 0 ? LDS_CU / (OCC + 1) + 1024 : 0;
+    static constexpr int PAD_BYTES =
+        CAP_BYTES > SMEM_FLOATS * 4 ? CAP_BYTES - SMEM_FLOATS * 4 : 0;
     static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile must be 32-aligned");
     static_assert(BK % 8 == 0, "BK must be a multiple of 8");
 };

@@ -178,18 +178,27 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
                     bh[j] = *reinterpret_cast<const bf16x8*>(Bh + o);
                     bl[j] = *reinterpret_cast<const bf16x8*>(Bl + o);
                 }
+                // rows of D = n (op(B)), columns of D = m (op(A)).  Every
+                // accumulator takes lo*hi, then hi*lo, then hi*hi; the loops
+                // run term-major so that consecutive MFMAs are independent.
 #pragma unroll
                 for (int i = 0; i < FM; ++i)
 #pragma unroll
-                    for (int j = 0; j < FN; ++j) {
-                        // rows of D = n (op(B)), columns of D = m (op(A))
+                    for (int j = 0; j < FN; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl[j], ah[i],
                                                                             acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[j], al[i],
                                                                             acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[j], ah[i],
                                                                             acc[i][j], 0, 0, 0);
-                    }
             } else {
                 f16x8 aq[FM], bq[FN];
 #pragma unroll

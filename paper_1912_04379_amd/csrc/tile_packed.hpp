@@ -1,0 +1,242 @@
+// tile_packed.hpp -- 16-bit MFMA tile engine fed straight from pre-packed
+// operands into a multi-stage LDS ring (gfx950 buffer_load_dwordx4 ... lds).
+//
+// Packed operand layout (written by the pack kernels in sgemm_packed.hip):
+// op(X), P x K, as 16-bit values in blocks of 32 rows x KW k (KW = 32 or 16;
+// one 2*KW-byte row per p, k contiguous); block (pb, kb) starts at byte
+// (pb * KB + kb) * 64 * KW with KB = ceil(K / KW).  Rows >= P and k >= K
+// hold zeros, so the main loop needs no masking.  The BF16x3 form has two such
+// arrays per operand (hi, lo); the FP16 form one (x * 2^e of its 32-row
+// panel, e from the exponent pre-pass).
+//
+// Main loop.  A work-group owns a BM x BN tile of C.  Its K loop walks
+// KW-deep slabs; slab s of every array goes to LDS stage s mod NS by direct
+// memory-to-LDS loads issued NS-1 slabs ahead (no registers, no VALU).
+// Each slab iteration is: wait for this slab's own loads (s_waitcnt vmcnt
+// with the later slabs still in flight), barrier, issue the loads of slab
+// s+NS-1 into the stage that the previous iteration finished reading, then
+// KW/16 MFMA k-steps on stage s.  In LDS a row of KW values is split into
+// 16-byte chunks of 8 k; chunk c of row p sits at slot c ^ swz(p), with
+// swz(p) = (p >> 2) & 3 for 64-byte rows (the in-staging engine's layout)
+// and (p >> 3) & 1 for 32-byte rows, so that the 16 lanes reading one chunk
+// of 16 consecutive rows hit 16 distinct 16-byte slots (no bank conflicts).
+// Lane i of a load fetches the chunk whose swizzled slot is i: a permutation
+// inside one block, so the loads stay fully coalesced.
+#pragma once
+#include <type_traits>
+
+#include "tile_lowp.hpp"
+
+namespace mgemm {
+
+// Device view of the packed operands of one product.
+struct PackedArgs {
+    const char* a_hi;
+    const char* a_lo;   // BF16x3 only
+    const char* b_hi;
+    const char* b_lo;   // BF16x3 only
+    int64_t kb;         // 32-wide k blocks
+    int64_t pb_a, pb_b; // 32-row blocks of op(A) and op(B)
+};
+
+// WPE: waves per SIMD the kernel is compiled for (registers <= 512 / WPE);
+// 2 with 4-wave work-groups means two work-groups share each CU.
+template <int BM_, int BN_, int WGM_, int WGN_, int NS_, int KW_, int WPE_ = 2>
+struct CfgPK {
+    static constexpr int BM = BM_, BN = BN_, BK = KW_, NS = NS_, KW = KW_, WPE = WPE_;
+    static constexpr int WGM = WGM_, WGN = WGN_;
+    static constexpr int NT = 64 * WGM * WGN, NWAVES = WGM * WGN;
+    static constexpr int WM = BM / WGM, WN = BN / WGN;
+    static constexpr int FM = WM / 32, FN = WN / 32;
+    static constexpr int ROW_BYTES = 2 * KW;            // one row of a block
+    static constexpr int CPR = KW / 8;                  // 16-byte chunks per row
+    static constexpr int BLOCK = 32 * ROW_BYTES;        // one 32-row block
+    static_assert(KW == 16 || KW == 32, "k-width of a packed block");
+    static_assert(WM % 32 == 0 && WN % 32 == 0, "wave tile must be 32-aligned");
+    static_assert(BM % 32 == 0 && BN % 32 == 0, "tiles are whole 32-row blocks");
+};
+
+// Swizzled slot of logical chunk c of row p (an involution in c).
+template <int KW>
+__device__ inline int pk_slot(int p, int c) {
+    return KW == 32 ? c ^ ((p >> 2) & 3) : c ^ ((p >> 3) & 1);
+}
+
+template <class Cfg, Form F>
+struct PackedStage {
+    static constexpr int ARRAYS = F == Form::BF16X3 ? 2 : 1;
+    static constexpr int ARR = (Cfg::BM + Cfg::BN) * Cfg::ROW_BYTES;   // one array
+    static constexpr int BYTES = ARRAYS * ARR;
+    static constexpr int CHUNKS = BYTES / 1024;                 // 1 KB per wave-wide load
+    static constexpr int PER_WAVE = CHUNKS / Cfg::NWAVES;
+    static_assert(CHUNKS % Cfg::NWAVES == 0, "stage must split evenly over waves");
+    static constexpr int SMEM = Cfg::NS * BYTES;
+};
+
+#define MGEMM_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
+// Wait until at most N of this wave's vector-memory operations are in
+// flight, then barrier.  The memory clobber keeps the compiler from moving
+// LDS reads of the next stage above it.
+template <int N>
+__device__ inline void wait_vm_and_barrier() {
+    static_assert(N >= 0 && N < 64, "vmcnt range");
+    asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
+}
+
+template <class Cfg, Form F, bool BUF>
+__device__ inline void tile_packed(const GemmDesc& d, const PackedArgs& pk, int64_t m0,
+                                   int64_t n0, char* smem) {
+    using St = PackedStage<Cfg, F>;
+    constexpr int BM = Cfg::BM, NS = Cfg::NS, FM = Cfg::FM, FN = Cfg::FN;
+    constexpr int PW = St::PER_WAVE, KW = Cfg::KW, RB = Cfg::ROW_BYTES, CPR = Cfg::CPR;
+    constexpr int RPC = 1024 / RB;                      // rows per 1 KB load
+    using Epi = typename std::conditional<BUF, EpilogueB, EpilogueG>::type;
+    const int tid = threadIdx.x, lane = tid & 63;
+    // tid >> 6 is the same on every lane of a wave; say so, so that the
+    // buffer descriptors and LDS destinations derived from it stay scalar.
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int l32 = lane & 31, h = lane >> 5;
+    const int wm = (wave % Cfg::WGM) * Cfg::WM;
+    const int wn = (wave / Cfg::WGM) * Cfg::WN;
+    const int64_t pan_a = (d.M + 31) / 32, pan_b = (d.N + 31) / 32;
+
+    // ---- which 1 KB pieces of a stage this wave loads ----------------------
+    // Stage layout: [hi: A rows | B rows][lo: A rows | B rows]; piece j covers
+    // RPC rows of one array.  Per piece: array (0 a_hi, 1 b_hi, 2 a_lo,
+    // 3 b_lo) and the lane's byte offset from the slab's first block.
+    int arr[PW];
+    uint32_t goff[PW];
+#pragma unroll
+    for (int t = 0; t < PW; ++t) {
+        const int j = wave * PW + t;
+        const int within = j % ((BM + Cfg::BN) / RPC);  // row group inside one array
+        const bool is_a = within < BM / RPC;
+        const int rg = is_a ? within : within - BM / RPC;
+        arr[t] = (j >= (BM + Cfg::BN) / RPC ? 2 : 0) + (is_a ? 0 : 1);
+        const int p = rg * RPC + lane / CPR;            // tile-relative row
+        const int c = pk_slot<KW>(p, lane % CPR);       // logical chunk of this slot
+        goff[t] = (uint32_t)((int64_t)(p >> 5) * pk.kb * Cfg::BLOCK + (p & 31) * RB + c * 16);
+    }
+    const int64_t blk_a = (m0 / 32) * pk.kb, blk_b = (n0 / 32) * pk.kb;
+    const int64_t bytes_a = pk.pb_a * pk.kb * Cfg::BLOCK, bytes_b = pk.pb_b * pk.kb * Cfg::BLOCK;
+
+    auto issue = [&](int64_t s) {
+        char* stage = smem + (int)(s % NS) * St::BYTES;
+        const int64_t off_a = (blk_a + s) * Cfg::BLOCK, off_b = (blk_b + s) * Cfg::BLOCK;
+        // Slabs past the end of K get an empty range: every lane reads 0.
+        const bool live = s < pk.kb;
+        const BufRsrc ra_hi = make_rsrc(pk.a_hi + off_a, live ? bytes_a - off_a : 0);
+        const BufRsrc rb_hi = make_rsrc(pk.b_hi + off_b, live ? bytes_b - off_b : 0);
+        BufRsrc ra_lo = ra_hi, rb_lo = rb_hi;
+        if constexpr (F == Form::BF16X3) {
+            ra_lo = make_rsrc(pk.a_lo + off_a, live ? bytes_a - off_a : 0);
+            rb_lo = make_rsrc(pk.b_lo + off_b, live ? bytes_b - off_b : 0);
+        }
+#pragma unroll
+        for (int t = 0; t < PW; ++t) {
+            const BufRsrc r = arr[t] == 0 ? ra_hi : arr[t] == 1 ? rb_hi : arr[t] == 2 ? ra_lo : rb_lo;
+            char* dst = stage + (wave * PW + t) * 1024;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(r, MGEMM_LDS(dst), 16, goff[t], 0, 0, 0);
+        }
+    };
+
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = f32x16{};
+
+    const int64_t nk = pk.kb;
+#pragma unroll
+    for (int s = 0; s < NS - 1; ++s) issue(s);
+
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        // Loads of slabs kt+1 .. kt+NS-2 may stay in flight.
+        wait_vm_and_barrier<(NS - 2) * PW>();
+        issue(kt + NS - 1);   // into the stage read in iteration kt-1
+        const char* Ah = smem + (int)(kt % NS) * St::BYTES;
+        const char* Bh = Ah + BM * RB;
+        const char* Al = Ah + St::ARR;
+        const char* Bl = Al + BM * RB;
+        // Byte offset of logical chunk c of row p inside one array.
+        auto co = [](int p, int c) { return p * RB + (pk_slot<KW>(p, c) << 4); };
+#pragma unroll
+        for (int ks = 0; ks < KW / 16; ++ks) {
+            const int c = 2 * ks + h;
+            if constexpr (F == Form::BF16X3) {
+                bf16x8 ah[FM], al[FM], bh[FN], bl[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const int o = co(wm + 32 * i + l32, c);
+                    ah[i] = *reinterpret_cast<const bf16x8*>(Ah + o);
+                    al[i] = *reinterpret_cast<const bf16x8*>(Al + o);
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    const int o = co(wn + 32 * j + l32, c);
+                    bh[j] = *reinterpret_cast<const bf16x8*>(Bh + o);
+                    bl[j] = *reinterpret_cast<const bf16x8*>(Bl + o);
+                }
+                // rows of D = n (op(B)), columns of D = m (op(A)).  Every
+                // accumulator takes lo*hi, then hi*lo, then hi*hi; the loops
+                // run term-major so that consecutive MFMAs are independent.
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bl[j], ah[i],
+                                                                            acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[j], al[i],
+                                                                            acc[i][j], 0, 0, 0);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bh[j], ah[i],
+                                                                            acc[i][j], 0, 0, 0);
+            } else {
+                f16x8 aq[FM], bq[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+                    aq[i] = *reinterpret_cast<const f16x8*>(Ah + co(wm + 32 * i + l32, c));
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    bq[j] = *reinterpret_cast<const f16x8*>(Bh + co(wn + 32 * j + l32, c));
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(bq[j], aq[i],
+                                                                           acc[i][j], 0, 0, 0);
+            }
+        }
+    }
+    // Drain the (empty) loads issued past the end before the work-group ends
+    // or the LDS is reused.
+    wait_vm_and_barrier<0>();
+
+    Epi epi(d, m0, n0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            int sh = 0;
+            if constexpr (F == Form::F16S) {
+                const int64_t pa = (m0 + wm + 32 * i) / 32, pb = (n0 + wn + 32 * j) / 32;
+                sh = -((pa < pan_a ? d.expA[pa] : 0) + (pb < pan_b ? d.expB[pb] : 0));
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float v = F == Form::F16S ? ldexpf(acc[i][j][r], sh) : acc[i][j][r];
+                epi.store(wm + 32 * i + l32, wn + 32 * j + mfma32_row(r, lane), v);
+            }
+        }
+}
+
+}  // namespace mgemm

@@ -123,3 +123,19 @@ def test_plan_functions_reject_null():
     assert L.mgemm_grouped_plan_run(None, None) == _lib.ERR_BAD_PLAN
     t, w = ctypes.c_int64(), ctypes.c_int64()
     assert L.mgemm_grouped_plan_info(None, ctypes.byref(t), ctypes.byref(w)) == _lib.ERR_BAD_PLAN
+
+
+def test_recorded_choice_overrides_the_heuristic():
+    L = mg.lib()
+    base = mg.default_config("fp32", "N", "N", 777, 555, 333)
+    tn_base = mg.default_config("fp32", "T", "N", 777, 555, 333)
+    other = (base + 1) % mg.config_count("fp32")
+    mg.record_choice("fp32", "N", "N", 777, 555, 333, other)
+    try:
+        assert mg.default_config("fp32", "N", "N", 777, 555, 333) == other
+        assert mg.default_config("fp32", "T", "N", 777, 555, 333) == tn_base   # exact key only
+    finally:
+        mg.clear_choices()
+    assert mg.default_config("fp32", "N", "N", 777, 555, 333) == base
+    assert L.mgemm_record_choice(0, b"N", b"N", 1, 1, 1, 99) == _lib.ERR_UNSUPPORTED
+    assert L.mgemm_record_choice(0, b"Q", b"N", 1, 1, 1, 0) == -1

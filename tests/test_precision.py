@@ -73,7 +73,7 @@ def test_forms_small(prec, ta, tb, shape):
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
-@pytest.mark.parametrize("cfg", range(4))
+@pytest.mark.parametrize("cfg", range(10))
 def test_forms_every_config(prec, cfg):
     c = synth.sgemm_case(32, "T", "N", 520, 390, 200, alpha=1.5, beta=-0.5, dist="loguni")
     log("%s cfg %d" % (prec, cfg))
@@ -157,3 +157,27 @@ def test_forms_alpha_beta_rules(prec):
     c = synth.sgemm_case(36, "T", "T", 64, 48, 40)
     c["C"] = np.where(c["C"] == synth.C_SENTINEL, c["C"], np.float32(np.nan)).astype(np.float32)
     assert np.all(np.isfinite(logical_c(run(c, precision=prec), c)))
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+@pytest.mark.parametrize("ta,tb", TRANS)
+def test_packed_equals_in_staging_bitwise(prec, ta, tb):
+    """Configuration 4 (operands pre-packed, streamed into LDS by direct
+    loads) and configuration 0 (split while staging) use the same 256 x 256
+    tile, the same splits and the same MFMA operand order: equal bitwise."""
+    c = synth.sgemm_case(40, ta, tb, 600, 520, 333, alpha=1.5, beta=-0.5, pad=5)
+    log("%s packed vs in-staging %s%s" % (prec, ta, tb))
+    a = run(c, precision=prec, config=0)
+    b = run(c, precision=prec, config=4)
+    assert np.array_equal(a, b)
+    check_form(c, prec, b)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+@pytest.mark.parametrize("cfg", [4, 5, 6, 7, 8, 9])
+def test_packed_ragged_and_tiny(prec, cfg):
+    for shape in ((1, 1, 1), (33, 65, 7), (300, 129, 1000), (257, 255, 31)):
+        M, N, K = shape
+        c = synth.sgemm_case(41, "T", "N", M, N, K, alpha=1.5, beta=-0.5, pad=3)
+        log("%s packed cfg %d %s" % (prec, cfg, shape))
+        check_form(c, prec, run(c, precision=prec, config=cfg))

@@ -47,7 +47,7 @@ def test_ragged_shapes(ta, tb, shape):
     full_check(c, run(c))
 
 
-@pytest.mark.parametrize("cfg", range(4))
+@pytest.mark.parametrize("cfg", range(8))
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_every_config(cfg, ta, tb):
     c = synth.sgemm_case(3, ta, tb, 300, 270, 77, alpha=1.5, beta=-0.5, pad=3)
@@ -119,3 +119,23 @@ def test_nan_in_a_row_reaches_that_row_only():
     got = logical_c(run(c), c)
     assert np.all(np.isnan(got[17, :]))
     assert np.all(np.isfinite(np.delete(got, 17, axis=0)))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_tuner_records_a_valid_choice(prec):
+    import torch
+    c = synth.sgemm_case(12, "T", "N", 600, 500, 400, alpha=1.5, beta=-0.5)
+    A, B = (torch.from_numpy(c[k]).cuda() for k in ("A", "B"))
+    scratch = torch.from_numpy(c["C"]).cuda()
+    try:
+        cfg, ms = mg.tune_sgemm("T", "N", 600, 500, 400, 1.5, A, c["lda"], B, c["ldb"], -0.5,
+                                scratch, c["ldc"], precision=prec, reps=2)
+        assert 0 <= cfg < mg.config_count(prec) and ms > 0
+        assert mg.default_config(prec, "T", "N", 600, 500, 400) == cfg
+        tol = 1e-5
+        got = run(c, precision=prec)            # config -1 now uses the tuned choice
+        ref = oracle.sgemm(*(c[k] for k in ("transA", "transB", "M", "N", "K", "alpha", "A",
+                                             "lda", "B", "ldb", "beta", "C", "ldc")))
+        assert oracle.normwise_rel_err(logical_c(got, c), ref) <= tol
+    finally:
+        mg.clear_choices()
