@@ -79,11 +79,11 @@ int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
     (void)K;
     const int64_t big_tiles = ((M + 127) / 128) * ((N + 127) / 128);
     if (big_tiles < 512) return 1;
-    // Measured at 8192^3: 256x128 at 2 waves per SIMD is best for TN and NT
-    // (one operand or both k-contiguous with the other p-contiguous in the
-    // transposing direction); 128x128 for NN and TT.
+    // Measured at 8192^3 (MI355X): NN 256x128 at 2 waves per SIMD; TN and NT
+    // 128x128 with 32-deep slabs; TT 128x128 with 16-deep slabs.
     const int64_t wide_tiles = ((M + 255) / 256) * ((N + 127) / 128);
-    if (ta != tb && wide_tiles >= 512) return 5;
+    if (!ta && !tb) return wide_tiles >= 512 ? 5 : 0;
+    if (ta != tb) return 2;
     return 0;
 }
 

@@ -135,42 +135,51 @@ template <int BP, int BK, int NT, bool KCONTIG>
 struct SlabLoaderB : SlabGeom<BP, BK, NT, KCONTIG> {
     using G = SlabGeom<BP, BK, NT, KCONTIG>;
     f32x4 v[G::PER_THREAD];
-    uint32_t off[G::PER_THREAD];   // byte offset of element e = 0 of each group
-    bool pok[G::PER_THREAD];       // group's p inside the panel
+    // Byte offset of element e = 0 of each group from the slab's first
+    // element, or BUF_OOB for a group outside the panel.  BUF_OOB plus any
+    // in-slab step (< 2^31 - 2^30) stays at or above 2^31, beyond every
+    // descriptor's range, so masked groups never need a second select.
+    uint32_t off[G::PER_THREAD];
+    int kbase[G::PER_THREAD];      // k of element 0 relative to the slab
 
     __device__ inline void init(const Panel& pn, int tid) {
 #pragma unroll
         for (int q = 0; q < G::PER_THREAD; ++q) {
             int p, kq;
             G::group_pos(tid + q * NT, p, kq);
-            pok[q] = pn.p0 + p < pn.P;
-            off[q] = KCONTIG ? (uint32_t)(4 * (4 * kq + (int64_t)p * pn.ld))
-                             : (uint32_t)(4 * (p + (int64_t)(4 * kq) * pn.ld));
+            kbase[q] = 4 * kq;
+            const uint32_t o = KCONTIG ? (uint32_t)(4 * (4 * kq + (int64_t)p * pn.ld))
+                                       : (uint32_t)(4 * (p + (int64_t)(4 * kq) * pn.ld));
+            off[q] = pn.p0 + p < pn.P ? o : BUF_OOB;
         }
     }
 
     __device__ inline void load(const Panel& pn, int64_t k0, int tid) {
+        (void)tid;
         // The slab's first element and the bytes left in the array from it.
         const int64_t first = KCONTIG ? k0 + pn.p0 * pn.ld : pn.p0 + k0 * pn.ld;
         const BufRsrc r = make_rsrc(pn.X + first, 4 * (pn.extent - first));
-        const bool full = k0 + BK <= pn.K;
-        if (KCONTIG && full) {
+        const uint32_t kstep = KCONTIG ? 4u : (uint32_t)(4 * pn.ld);   // bytes per k
+        if (k0 + BK <= pn.K) {
+            // Whole slab inside K: only the panel edge is masked (in off).
 #pragma unroll
-            for (int q = 0; q < G::PER_THREAD; ++q)
-                v[q] = buf_load_f32x4(r, pok[q] ? off[q] : BUF_OOB);
+            for (int q = 0; q < G::PER_THREAD; ++q) {
+                if constexpr (KCONTIG) {
+                    v[q] = buf_load_f32x4(r, off[q]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[q][e] = buf_load_f32(r, off[q] + e * kstep);
+                }
+            }
             return;
         }
+        // Last, partial slab: also mask k >= K.
+        const int krem = (int)(pn.K - k0);
 #pragma unroll
-        for (int q = 0; q < G::PER_THREAD; ++q) {
-            int p, kq;
-            G::group_pos(tid + q * NT, p, kq);
+        for (int q = 0; q < G::PER_THREAD; ++q)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const bool ok = pok[q] && (full || k0 + 4 * kq + e < pn.K);
-                const uint32_t step = KCONTIG ? 4u * e : (uint32_t)(4 * e * pn.ld);
-                v[q][e] = buf_load_f32(r, ok ? off[q] + step : BUF_OOB);
-            }
-        }
+            for (int e = 0; e < 4; ++e)
+                v[q][e] = buf_load_f32(r, kbase[q] + e < krem ? off[q] + e * kstep : BUF_OOB);
     }
 };
 
