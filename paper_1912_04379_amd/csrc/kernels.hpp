@@ -37,8 +37,8 @@ hipError_t launch_f16_exponents(bool transA, bool transB, const GemmDesc& d,
 hipError_t launch_f16s(int cfg, bool transA, bool transB, const GemmDesc& d,
                        hipStream_t stream);
 
-// Pre-packed 16-bit path (direct-to-LDS engine).  Configurations 0..5 of
-// this family are exposed as configurations 4..9 of the BF16x3 and FP16
+// Pre-packed 16-bit path (direct-to-LDS engine).  Configurations 0..6 of
+// this family are exposed as configurations 4..10 of the BF16x3 and FP16
 // forms (3 is FP16 only).  The caller provides `workspace` of
 // packed_workspace_bytes(); for the FP16 form d.expA / d.expB must already
 // hold the panel exponents.

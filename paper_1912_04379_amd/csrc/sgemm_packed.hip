@@ -75,7 +75,12 @@ __global__ __launch_bounds__(Cfg::NT, Cfg::WPE) void packed_kernel(GemmDesc d, P
     extern __shared__ __attribute__((aligned(16))) char packed_smem[];
     uint32_t tm, tn;
     grouped_tile<8>(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
-    tile_packed<Cfg, F, BUF>(d, pk, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, packed_smem);
+    if constexpr (Cfg::PIPELINED)
+        tile_packed_pp<Cfg, F, BUF>(d, pk, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN,
+                                    packed_smem);
+    else
+        tile_packed<Cfg, F, BUF>(d, pk, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN,
+                                 packed_smem);
 }
 
 // KW = 32: the in-staging engine's LDS layout (configuration 0 matches its
@@ -89,6 +94,8 @@ using PKCfg3 = CfgPK<256, 256, 2, 4, 4, 32>;   // FP16 only: 4 stages of 32 k (1
 // independent, so one keeps the MFMA pipes busy while the other waits.
 using PKCfg4 = CfgPK<256, 128, 2, 2, 3, 16>;   // 4 waves of 128x64, 3 stages of 16 k
 using PKCfg5 = CfgPK<128, 256, 2, 2, 3, 16>;   // 4 waves of 64x128, 3 stages of 16 k
+// As 1 with fragment double buffering (tile_packed_pp).
+using PKCfg6 = CfgPK<256, 256, 2, 4, 4, 16, 2, true>;
 
 template <class Cfg, Form F>
 static hipError_t launch_main(const GemmDesc& d, const PackedArgs& pk, hipStream_t s) {
@@ -105,7 +112,7 @@ static hipError_t launch_main(const GemmDesc& d, const PackedArgs& pk, hipStream
     return hipGetLastError();
 }
 
-int packed_config_count() { return 6; }
+int packed_config_count() { return 7; }
 
 TileConfigInfo packed_config_info(int cfg) {
     switch (cfg) {
@@ -115,11 +122,12 @@ TileConfigInfo packed_config_info(int cfg) {
         case 3: return {PKCfg3::BM, PKCfg3::BN, PKCfg3::BK, PKCfg3::NT};
         case 4: return {PKCfg4::BM, PKCfg4::BN, PKCfg4::BK, PKCfg4::NT};
         case 5: return {PKCfg5::BM, PKCfg5::BN, PKCfg5::BK, PKCfg5::NT};
+        case 6: return {PKCfg6::BM, PKCfg6::BN, PKCfg6::BK, PKCfg6::NT};
         default: return {0, 0, 0, 0};
     }
 }
 
-static int packed_kw(int cfg) { return cfg == 1 || cfg == 4 || cfg == 5 ? 16 : 32; }
+static int packed_kw(int cfg) { return cfg == 1 || cfg >= 4 ? 16 : 32; }
 
 // Bytes of device workspace for the packed operands.
 int64_t packed_workspace_bytes(bool bf16x3, int cfg, int64_t M, int64_t N, int64_t K) {
@@ -189,6 +197,8 @@ hipError_t launch_packed(bool bf16x3, int cfg, bool ta, bool tb, const GemmDesc&
                               : launch_main<PKCfg4, Form::F16S>(d, pk, s);
         case 5: return bf16x3 ? launch_main<PKCfg5, Form::BF16X3>(d, pk, s)
                               : launch_main<PKCfg5, Form::F16S>(d, pk, s);
+        case 6: return bf16x3 ? launch_main<PKCfg6, Form::BF16X3>(d, pk, s)
+                              : launch_main<PKCfg6, Form::F16S>(d, pk, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -41,9 +41,12 @@ struct PackedArgs {
 
 // WPE: waves per SIMD the kernel is compiled for (registers <= 512 / WPE);
 // 2 with 4-wave work-groups means two work-groups share each CU.
-template <int BM_, int BN_, int WGM_, int WGN_, int NS_, int KW_, int WPE_ = 2>
+// PIPELINED: the fragment-double-buffered main loop (tile_packed_pp).
+template <int BM_, int BN_, int WGM_, int WGN_, int NS_, int KW_, int WPE_ = 2,
+          bool PIPELINED_ = false>
 struct CfgPK {
     static constexpr int BM = BM_, BN = BN_, BK = KW_, NS = NS_, KW = KW_, WPE = WPE_;
+    static constexpr bool PIPELINED = PIPELINED_;
     static constexpr int WGM = WGM_, WGN = WGN_;
     static constexpr int NT = 64 * WGM * WGN, NWAVES = WGM * WGN;
     static constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -219,6 +222,179 @@ __device__ inline void tile_packed(const GemmDesc& d, const PackedArgs& pk, int6
     }
     // Drain the (empty) loads issued past the end before the work-group ends
     // or the LDS is reused.
+    wait_vm_and_barrier<0>();
+
+    Epi epi(d, m0, n0);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            int sh = 0;
+            if constexpr (F == Form::F16S) {
+                const int64_t pa = (m0 + wm + 32 * i) / 32, pb = (n0 + wn + 32 * j) / 32;
+                sh = -((pa < pan_a ? d.expA[pa] : 0) + (pb < pan_b ? d.expB[pb] : 0));
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float v = F == Form::F16S ? ldexpf(acc[i][j][r], sh) : acc[i][j][r];
+                epi.store(wm + 32 * i + l32, wn + 32 * j + mfma32_row(r, lane), v);
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Software-pipelined variant: one wave per SIMD with a large wave tile and
+// two register sets of MFMA fragments.  Iteration kt:
+//   1. first half of stage kt's MFMAs (fragments already in registers);
+//   2. wait for stage kt+1's loads, barrier (every wave has now read stage
+//      kt's fragments, so its LDS buffer is free);
+//   3. issue the loads of stage kt+NS into that buffer;
+//   4. read stage kt+1's fragments into the other register set, overlapped
+//      with the second half of stage kt's MFMAs.
+// Every accumulator still takes lo*hi, hi*lo, hi*hi per 16-deep k step in k
+// order, so results equal the other packed configurations bitwise.
+// ---------------------------------------------------------------------------
+template <class Cfg, Form F>
+struct PPFrags {
+    static constexpr int FM = Cfg::FM, FN = Cfg::FN;
+    bf16x8 ah[FM], al[FM], bh[FN], bl[FN];     // BF16x3
+    f16x8 aq[FM], bq[FN];                       // FP16
+};
+
+template <class Cfg, Form F, bool BUF>
+__device__ inline void tile_packed_pp(const GemmDesc& d, const PackedArgs& pk, int64_t m0,
+                                      int64_t n0, char* smem) {
+    using St = PackedStage<Cfg, F>;
+    constexpr int BM = Cfg::BM, NS = Cfg::NS, FM = Cfg::FM, FN = Cfg::FN;
+    constexpr int PW = St::PER_WAVE, KW = Cfg::KW, RB = Cfg::ROW_BYTES, CPR = Cfg::CPR;
+    constexpr int RPC = 1024 / RB;
+    static_assert(KW == 16, "one 16-deep MFMA step per stage");
+    static_assert(NS >= 3, "at least three stages");
+    using Epi = typename std::conditional<BUF, EpilogueB, EpilogueG>::type;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int l32 = lane & 31, h = lane >> 5;
+    const int wm = (wave % Cfg::WGM) * Cfg::WM;
+    const int wn = (wave / Cfg::WGM) * Cfg::WN;
+    const int64_t pan_a = (d.M + 31) / 32, pan_b = (d.N + 31) / 32;
+
+    int arr[PW];
+    uint32_t goff[PW];
+#pragma unroll
+    for (int t = 0; t < PW; ++t) {
+        const int j = wave * PW + t;
+        const int within = j % ((BM + Cfg::BN) / RPC);
+        const bool is_a = within < BM / RPC;
+        const int rg = is_a ? within : within - BM / RPC;
+        arr[t] = (j >= (BM + Cfg::BN) / RPC ? 2 : 0) + (is_a ? 0 : 1);
+        const int p = rg * RPC + lane / CPR;
+        const int c = pk_slot<KW>(p, lane % CPR);
+        goff[t] = (uint32_t)((int64_t)(p >> 5) * pk.kb * Cfg::BLOCK + (p & 31) * RB + c * 16);
+    }
+    const int64_t blk_a = (m0 / 32) * pk.kb, blk_b = (n0 / 32) * pk.kb;
+    const int64_t bytes_a = pk.pb_a * pk.kb * Cfg::BLOCK, bytes_b = pk.pb_b * pk.kb * Cfg::BLOCK;
+
+    auto issue = [&](int64_t s) {
+        char* stage = smem + (int)(s % NS) * St::BYTES;
+        const int64_t off_a = (blk_a + s) * Cfg::BLOCK, off_b = (blk_b + s) * Cfg::BLOCK;
+        const bool live = s < pk.kb;
+        const BufRsrc ra_hi = make_rsrc(pk.a_hi + off_a, live ? bytes_a - off_a : 0);
+        const BufRsrc rb_hi = make_rsrc(pk.b_hi + off_b, live ? bytes_b - off_b : 0);
+        BufRsrc ra_lo = ra_hi, rb_lo = rb_hi;
+        if constexpr (F == Form::BF16X3) {
+            ra_lo = make_rsrc(pk.a_lo + off_a, live ? bytes_a - off_a : 0);
+            rb_lo = make_rsrc(pk.b_lo + off_b, live ? bytes_b - off_b : 0);
+        }
+#pragma unroll
+        for (int t = 0; t < PW; ++t) {
+            const BufRsrc r = arr[t] == 0 ? ra_hi : arr[t] == 1 ? rb_hi : arr[t] == 2 ? ra_lo : rb_lo;
+            char* dst = stage + (wave * PW + t) * 1024;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(r, MGEMM_LDS(dst), 16, goff[t], 0, 0, 0);
+        }
+    };
+    auto co = [](int p, int c) { return p * RB + (pk_slot<KW>(p, c) << 4); };
+    auto read = [&](int64_t s, PPFrags<Cfg, F>& f) {
+        const char* Ah = smem + (int)(s % NS) * St::BYTES;
+        const char* Bh = Ah + BM * RB;
+        const char* Al = Ah + St::ARR;
+        const char* Bl = Al + BM * RB;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            const int o = co(wm + 32 * i + l32, h);
+            if constexpr (F == Form::BF16X3) {
+                f.ah[i] = *reinterpret_cast<const bf16x8*>(Ah + o);
+                f.al[i] = *reinterpret_cast<const bf16x8*>(Al + o);
+            } else {
+                f.aq[i] = *reinterpret_cast<const f16x8*>(Ah + o);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < FN; ++j) {
+            const int o = co(wn + 32 * j + l32, h);
+            if constexpr (F == Form::BF16X3) {
+                f.bh[j] = *reinterpret_cast<const bf16x8*>(Bh + o);
+                f.bl[j] = *reinterpret_cast<const bf16x8*>(Bl + o);
+            } else {
+                f.bq[j] = *reinterpret_cast<const f16x8*>(Bh + o);
+            }
+        }
+    };
+
+    f32x16 acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = f32x16{};
+
+    // MFMA number q (0 .. NQ-1) of one k step: term-major over (term, i, j).
+    constexpr int TERMS = F == Form::BF16X3 ? 3 : 1;
+    constexpr int NQ = TERMS * FM * FN;
+    auto mfma_range = [&](const PPFrags<Cfg, F>& f, auto lo_c, auto hi_c) {
+        constexpr int LO = decltype(lo_c)::value, HI = decltype(hi_c)::value;
+#pragma unroll
+        for (int q = LO; q < HI; ++q) {
+            const int term = q / (FM * FN), i = (q / FN) % FM, j = q % FN;
+            if constexpr (F == Form::BF16X3) {
+                if (term == 0)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bl[j], f.ah[i], acc[i][j], 0, 0, 0);
+                else if (term == 1)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bh[j], f.al[i], acc[i][j], 0, 0, 0);
+                else
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bh[j], f.ah[i], acc[i][j], 0, 0, 0);
+            } else {
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.bq[j], f.aq[i], acc[i][j], 0, 0, 0);
+            }
+        }
+    };
+    using Half = std::integral_constant<int, NQ / 2>;
+    using Zero = std::integral_constant<int, 0>;
+    using All = std::integral_constant<int, NQ>;
+
+    const int64_t nk = pk.kb;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) issue(s);
+    PPFrags<Cfg, F> fr[2];
+    wait_vm_and_barrier<(NS - 1) * PW>();     // stage 0 has landed
+    read(0, fr[0]);
+
+    for (int64_t kt = 0; kt < nk; kt += 2) {
+        // Two iterations per trip so that the register set is a constant.
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int64_t k = kt + u;
+            if (k >= nk) break;
+            PPFrags<Cfg, F>& cur = fr[u];
+            PPFrags<Cfg, F>& nxt = fr[u ^ 1];
+            mfma_range(cur, Zero{}, Half{});
+            __builtin_amdgcn_sched_barrier(0);
+            wait_vm_and_barrier<(NS - 2) * PW>();   // stage k+1 has landed
+            issue(k + NS);                          // into stage k's buffer
+            if (k + 1 < nk) read(k + 1, nxt);
+            __builtin_amdgcn_sched_barrier(0);
+            mfma_range(cur, Half{}, All{});
+        }
+    }
     wait_vm_and_barrier<0>();
 
     Epi epi(d, m0, n0);

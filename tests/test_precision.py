@@ -73,7 +73,7 @@ def test_forms_small(prec, ta, tb, shape):
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
-@pytest.mark.parametrize("cfg", range(10))
+@pytest.mark.parametrize("cfg", range(11))
 def test_forms_every_config(prec, cfg):
     c = synth.sgemm_case(32, "T", "N", 520, 390, 200, alpha=1.5, beta=-0.5, dist="loguni")
     log("%s cfg %d" % (prec, cfg))
@@ -171,10 +171,13 @@ def test_packed_equals_in_staging_bitwise(prec, ta, tb):
     b = run(c, precision=prec, config=4)
     assert np.array_equal(a, b)
     check_form(c, prec, b)
+    # 16-deep stages (5) and the fragment-pipelined loop (10) keep the order
+    assert np.array_equal(a, run(c, precision=prec, config=5))
+    assert np.array_equal(a, run(c, precision=prec, config=10))
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
-@pytest.mark.parametrize("cfg", [4, 5, 6, 7, 8, 9])
+@pytest.mark.parametrize("cfg", [4, 5, 6, 7, 8, 9, 10])
 def test_packed_ragged_and_tiny(prec, cfg):
     for shape in ((1, 1, 1), (33, 65, 7), (300, 129, 1000), (257, 255, 31)):
         M, N, K = shape
