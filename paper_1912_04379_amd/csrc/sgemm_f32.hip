@@ -15,35 +15,28 @@ __global__ __launch_bounds__(Cfg::NT, Cfg::WPE) void sgemm_f32_kernel(GemmDesc d
     tile_f32<Cfg, AK, BKC, BUF>(d, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
 }
 
-template <class Cfg, bool AK, bool BKC>
-static void launch_trans(dim3 grid, const GemmDesc& d, uint32_t tm, uint32_t tn,
-                         hipStream_t s) {
-    if (buffer_path_ok(d))
-        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, AK, BKC, true>), grid, dim3(Cfg::NT),
-                           Cfg::PAD_BYTES, s, d, tm, tn);
-    else
-        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, AK, BKC, false>), grid, dim3(Cfg::NT),
-                           Cfg::PAD_BYTES, s, d, tm, tn);
-}
-
-template <class Cfg>
+template <class Cfg, bool BUF>
 static hipError_t launch_cfg(bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
     const int64_t tiles_m = (d.M + Cfg::BM - 1) / Cfg::BM;
     const int64_t tiles_n = (d.N + Cfg::BN - 1) / Cfg::BN;
     const int64_t tiles = tiles_m * tiles_n;
     if (tiles_m > 0xffffffffLL || tiles_n > 0xffffffffLL || tiles > 0xffffffffLL)
         return hipErrorInvalidValue;
-    dim3 grid((uint32_t)tiles);
-    const uint32_t tmm = (uint32_t)tiles_m, tnn = (uint32_t)tiles_n;
+    const dim3 grid((uint32_t)tiles), block(Cfg::NT);
+    const uint32_t tm = (uint32_t)tiles_m, tn = (uint32_t)tiles_n;
     // op(A) is K-contiguous for A 'T'; op(B) is K-contiguous for B 'N'.
     if (!ta && !tb)
-        launch_trans<Cfg, false, true>(grid, d, tmm, tnn, s);
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, false, true, BUF>), grid, block,
+                           Cfg::PAD_BYTES, s, d, tm, tn);
     else if (!ta && tb)
-        launch_trans<Cfg, false, false>(grid, d, tmm, tnn, s);
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, false, false, BUF>), grid, block,
+                           Cfg::PAD_BYTES, s, d, tm, tn);
     else if (ta && !tb)
-        launch_trans<Cfg, true, true>(grid, d, tmm, tnn, s);
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, true, true, BUF>), grid, block,
+                           Cfg::PAD_BYTES, s, d, tm, tn);
     else
-        launch_trans<Cfg, true, false>(grid, d, tmm, tnn, s);
+        hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, true, false, BUF>), grid, block,
+                           Cfg::PAD_BYTES, s, d, tm, tn);
     return hipGetLastError();
 }
 
@@ -79,25 +72,32 @@ int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
     (void)K;
     const int64_t big_tiles = ((M + 127) / 128) * ((N + 127) / 128);
     if (big_tiles < 512) return 1;
-    // Measured at 8192^3 (MI355X): NN 256x128 at 2 waves per SIMD; TN and NT
-    // 128x128 with 32-deep slabs; TT 128x128 with 16-deep slabs.
+    // Measured at 8192^3 (MI355X): 256x128 tiles for NN, TN and NT, 128x256
+    // for TT (both at 2 waves per SIMD), when they still give two rounds of
+    // work-groups per CU; 128x128 otherwise.
     const int64_t wide_tiles = ((M + 255) / 256) * ((N + 127) / 128);
-    if (!ta && !tb) return wide_tiles >= 512 ? 5 : 0;
-    if (ta != tb) return 2;
-    return 0;
+    const int64_t tall_tiles = ((M + 127) / 128) * ((N + 255) / 256);
+    if (ta && tb) return tall_tiles >= 512 ? 6 : 0;
+    return wide_tiles >= 512 ? 5 : 0;
 }
 
 hipError_t launch_f32(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
+    if (cfg < 0 || cfg >= f32_config_count()) return hipErrorInvalidValue;
+    // A leading dimension beyond 32-bit buffer offsets takes the 64-bit
+    // address path, built for the 64x64 and 128x128 tiles only (larger
+    // tiles would spill registers there).
+    if (!buffer_path_ok(d))
+        return cfg == 1 ? launch_cfg<F32Cfg1, false>(ta, tb, d, s)
+                        : launch_cfg<F32Cfg0, false>(ta, tb, d, s);
     switch (cfg) {
-        case 0: return launch_cfg<F32Cfg0>(ta, tb, d, s);
-        case 1: return launch_cfg<F32Cfg1>(ta, tb, d, s);
-        case 2: return launch_cfg<F32Cfg2>(ta, tb, d, s);
-        case 3: return launch_cfg<F32Cfg3>(ta, tb, d, s);
-        case 4: return launch_cfg<F32Cfg4>(ta, tb, d, s);
-        case 5: return launch_cfg<F32Cfg5>(ta, tb, d, s);
-        case 6: return launch_cfg<F32Cfg6>(ta, tb, d, s);
-        case 7: return launch_cfg<F32Cfg7>(ta, tb, d, s);
-        default: return hipErrorInvalidValue;
+        case 0: return launch_cfg<F32Cfg0, true>(ta, tb, d, s);
+        case 1: return launch_cfg<F32Cfg1, true>(ta, tb, d, s);
+        case 2: return launch_cfg<F32Cfg2, true>(ta, tb, d, s);
+        case 3: return launch_cfg<F32Cfg3, true>(ta, tb, d, s);
+        case 4: return launch_cfg<F32Cfg4, true>(ta, tb, d, s);
+        case 5: return launch_cfg<F32Cfg5, true>(ta, tb, d, s);
+        case 6: return launch_cfg<F32Cfg6, true>(ta, tb, d, s);
+        default: return launch_cfg<F32Cfg7, true>(ta, tb, d, s);
     }
 }
 

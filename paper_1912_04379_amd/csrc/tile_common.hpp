@@ -154,14 +154,15 @@ struct SlabLoaderB : SlabGeom<BP, BK, NT, KCONTIG> {
         }
     }
 
-    __device__ inline void load(const Panel& pn, int64_t k0, int tid) {
-        (void)tid;
+    // FULL: the slab lies inside K (k0 + BK <= K), only the panel edge is
+    // masked (in off).  Otherwise k >= K is masked too.
+    template <bool FULL>
+    __device__ inline void load(const Panel& pn, int64_t k0) {
         // The slab's first element and the bytes left in the array from it.
         const int64_t first = KCONTIG ? k0 + pn.p0 * pn.ld : pn.p0 + k0 * pn.ld;
         const BufRsrc r = make_rsrc(pn.X + first, 4 * (pn.extent - first));
         const uint32_t kstep = KCONTIG ? 4u : (uint32_t)(4 * pn.ld);   // bytes per k
-        if (k0 + BK <= pn.K) {
-            // Whole slab inside K: only the panel edge is masked (in off).
+        if constexpr (FULL) {
 #pragma unroll
             for (int q = 0; q < G::PER_THREAD; ++q) {
                 if constexpr (KCONTIG) {
@@ -171,15 +172,21 @@ struct SlabLoaderB : SlabGeom<BP, BK, NT, KCONTIG> {
                     for (int e = 0; e < 4; ++e) v[q][e] = buf_load_f32(r, off[q] + e * kstep);
                 }
             }
-            return;
+        } else {
+            const int krem = (int)(pn.K - k0);
+#pragma unroll
+            for (int q = 0; q < G::PER_THREAD; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    v[q][e] = buf_load_f32(r, kbase[q] + e < krem ? off[q] + e * kstep : BUF_OOB);
         }
-        // Last, partial slab: also mask k >= K.
-        const int krem = (int)(pn.K - k0);
-#pragma unroll
-        for (int q = 0; q < G::PER_THREAD; ++q)
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-                v[q][e] = buf_load_f32(r, kbase[q] + e < krem ? off[q] + e * kstep : BUF_OOB);
+    }
+
+    // Either form, chosen at run time.
+    __device__ inline void load(const Panel& pn, int64_t k0, int tid) {
+        (void)tid;
+        if (k0 + BK <= pn.K) load<true>(pn, k0);
+        else load<false>(pn, k0);
     }
 };
 
@@ -188,13 +195,16 @@ struct SlabLoaderG : SlabGeom<BP, BK, NT, KCONTIG> {
     using G = SlabGeom<BP, BK, NT, KCONTIG>;
     f32x4 v[G::PER_THREAD];
 
-    __device__ inline void init(const Panel&, int) {}
+    int tid_;
 
-    __device__ inline void load(const Panel& pn, int64_t k0, int tid) {
+    __device__ inline void init(const Panel&, int tid) { tid_ = tid; }
+
+    template <bool FULL>
+    __device__ inline void load(const Panel& pn, int64_t k0) {
 #pragma unroll
         for (int q = 0; q < G::PER_THREAD; ++q) {
             int p, kq;
-            G::group_pos(tid + q * NT, p, kq);
+            G::group_pos(tid_ + q * NT, p, kq);
             const int64_t gp = pn.p0 + p;
             const int64_t gk = k0 + 4 * kq;
             const bool prow = gp < pn.P;
@@ -202,12 +212,30 @@ struct SlabLoaderG : SlabGeom<BP, BK, NT, KCONTIG> {
             for (int e = 0; e < 4; ++e) {
                 const int64_t k = gk + e;
                 float x = 0.0f;
-                if (prow && k < pn.K) x = pn.X[KCONTIG ? (k + gp * pn.ld) : (gp + k * pn.ld)];
+                if (prow && (FULL || k < pn.K))
+                    x = pn.X[KCONTIG ? (k + gp * pn.ld) : (gp + k * pn.ld)];
                 v[q][e] = x;
             }
         }
     }
+
+    __device__ inline void load(const Panel& pn, int64_t k0, int tid) {
+        (void)tid;
+        if (k0 + BK <= pn.K) load<true>(pn, k0);
+        else load<false>(pn, k0);
+    }
 };
+
+// Work-group barrier that waits for this wave's LDS accesses only: global
+// loads stay in flight across it (__syncthreads would wait for them too).
+// The wait goes through the builtin (encoding: lgkmcnt 0, vmcnt and expcnt
+// at their maximum) so that the compiler's own wait insertion knows the
+// LDS / scalar-load counter is drained; the "memory" clobber on the
+// barrier keeps memory accesses from moving across it.
+__device__ inline void lds_barrier() {
+    __builtin_amdgcn_s_waitcnt(0xc07f);
+    asm volatile("s_barrier" ::: "memory");
+}
 
 // Referenced elements of a stored rows x cols array with leading dim ld.
 __device__ __host__ inline int64_t stored_extent(int64_t rows, int64_t cols, int64_t ld) {

@@ -24,9 +24,11 @@ namespace mgemm {
 // otherwise registers are held to 512 / WPE per lane).  OCC: at most this
 // many work-groups per CU (0 = no cap), enforced by reserving LDS at launch
 // (a whole number of rounds of work-groups avoids a part-empty last round).
-template <int BM_, int BN_, int BK_, int WGM_, int WGN_, int WPE_ = 0, int OCC_ = 0>
+template <int BM_, int BN_, int BK_, int WGM_, int WGN_, int WPE_ = 0, int OCC_ = 0,
+          bool IL_ = true>
 struct CfgF32 {
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WPE = WPE_, OCC = OCC_;
+    static constexpr bool IL = IL_;   // interleave LDS writes / loads with MFMAs
     static constexpr int WGM = WGM_, WGN = WGN_;
     static constexpr int NT = 64 * WGM * WGN;
     static constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -56,17 +58,65 @@ __device__ inline void stage_to_lds(const Loader& ld, float* Xs, int tid, int nt
     }
 }
 
+// Operand fragments of one MFMA k-chunk c (8 consecutive k of the slab,
+// 4 per half-wave): lanes with h = 0 hold k = 4c + e, lanes with h = 1 hold
+// k = BK/2 + 4c + e (e = 0..3).  Every k of the slab is used once; the
+// order of k inside one slab is free.
+template <class Cfg>
+struct FragF32 {
+    f32x4 a[Cfg::FM], b[Cfg::FN];
+
+    __device__ inline void read(const float* As, const float* Bs, int wm, int wn, int l32,
+                                int h, int c) {
+        constexpr int S = Cfg::S;
+        const int ko = h * (Cfg::BK / 2) + 4 * c;
+#pragma unroll
+        for (int i = 0; i < Cfg::FM; ++i)
+            a[i] = *reinterpret_cast<const f32x4*>(As + (wm + 32 * i + l32) * S + ko);
+#pragma unroll
+        for (int j = 0; j < Cfg::FN; ++j)
+            b[j] = *reinterpret_cast<const f32x4*>(Bs + (wn + 32 * j + l32) * S + ko);
+    }
+
+    __device__ inline void mfma(f32x16 (&acc)[Cfg::FM][Cfg::FN]) const {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int i = 0; i < Cfg::FM; ++i)
+#pragma unroll
+                for (int j = 0; j < Cfg::FN; ++j)
+                    // rows of D = n (from op(B)), columns of D = m (op(A))
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(b[j][e], a[i][e],
+                                                                     acc[i][j], 0, 0, 0);
+    }
+};
+
+// What one K-loop step does besides its MFMAs: stage the next slab into
+// the other LDS buffer (and then load the slab after it, a whole slab of
+// MFMAs ahead: in full, partially, or not at all), or nothing (last slab).
+enum class Step { STAGE_LOAD_FULL, STAGE_LOAD_PART, STAGE, LAST };
+
 // One BM x BN tile of C at (m0, n0).  AK / BKC: op(A) / op(B) contiguous
 // along K in memory (A 'T' / B 'N').  BUF: buffer loads and stores (every
 // leading dimension <= MAX_BUF_LD) or plain global accesses.
+//
+// Software pipeline, per slab kt (LDS buffer kt & 1; NC = BK/8 k-chunks):
+//   MFMAs of chunks 0..NC-2, each while the next chunk's fragments load;
+//   write slab kt+1 (in registers) to the other buffer; issue the global
+//   loads of slab kt+2; barrier on LDS only; read chunk 0 of slab kt+1;
+//   MFMAs of chunk NC-1 (which hide that read and the barrier skew).
+// The loop is split into straight-line pieces (full-slab loads, the one
+// partial slab, no load, last slab) so that no step joins two load
+// sequences: a join makes the compiler wait for every load in flight.
 template <class Cfg, bool AK, bool BKC, bool BUF>
 __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float* smem) {
-    constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, NT = Cfg::NT, S = Cfg::S;
-    constexpr int FM = Cfg::FM, FN = Cfg::FN;
+    constexpr int BM = Cfg::BM, BK = Cfg::BK, NT = Cfg::NT, S = Cfg::S;
+    constexpr int FM = Cfg::FM, FN = Cfg::FN, NC = BK / 8;
+    static_assert(NC >= 2, "the pipeline needs two k-chunks per slab");
     using LA = typename std::conditional<BUF, SlabLoaderB<BM, BK, NT, AK>,
                                          SlabLoaderG<BM, BK, NT, AK>>::type;
-    using LB = typename std::conditional<BUF, SlabLoaderB<BN, BK, NT, BKC>,
-                                         SlabLoaderG<BN, BK, NT, BKC>>::type;
+    using LB = typename std::conditional<BUF, SlabLoaderB<Cfg::BN, BK, NT, BKC>,
+                                         SlabLoaderG<Cfg::BN, BK, NT, BKC>>::type;
     using Epi = typename std::conditional<BUF, EpilogueB, EpilogueG>::type;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, h = lane >> 5;
@@ -90,51 +140,101 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
         for (int j = 0; j < FN; ++j)
             acc[i][j] = f32x16{};
 
-    const int64_t nk = (d.K + BK - 1) / BK;
-    la.load(pa, 0, tid);
-    lb.load(pb, 0, tid);
+    const int64_t nk = (d.K + BK - 1) / BK;   // >= 1: K == 0 never reaches here
+    const int64_t nfull = d.K / BK;
+    auto load = [&](int64_t slab, bool full) {
+        if (full) {
+            la.template load<true>(pa, slab * BK);
+            lb.template load<true>(pb, slab * BK);
+        } else {
+            la.template load<false>(pa, slab * BK);
+            lb.template load<false>(pb, slab * BK);
+        }
+    };
+    load(0, nfull > 0);
     stage_to_lds<LA, BK>(la, smem, tid, NT);
     stage_to_lds<LB, BK>(lb, smem + BM * S, tid, NT);
-    __syncthreads();
+    if (nk > 1) load(1, nfull > 1);
+    lds_barrier();
 
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        float* cur = smem + (kt & 1) * Cfg::STAGE;
+    FragF32<Cfg> f[2];
+    f[0].read(smem, smem + BM * S, wm, wn, l32, h, 0);
+
+    // Instruction counts of one step, for the interleaving below.
+    constexpr int N_MFMA = 4 * FM * FN;                    // per k-chunk
+    constexpr int N_READ = FM + FN;                        // per k-chunk
+    constexpr int N_WRITE = LA::PER_THREAD + LB::PER_THREAD;
+    constexpr int N_VMEM = (AK ? 1 : 4) * LA::PER_THREAD + (BKC ? 1 : 4) * LB::PER_THREAD;
+    // Small wave tiles have too few MFMAs per chunk to interleave with.
+    constexpr bool IL = Cfg::IL && N_WRITE + (N_VMEM + 1) / 2 <= N_MFMA;
+
+    int64_t kt = 0;
+    auto step = [&](auto kind_tag) {
+        constexpr Step kind = decltype(kind_tag)::value;
+        const float* cur = smem + (kt & 1) * Cfg::STAGE;
         float* nxt = smem + ((kt + 1) & 1) * Cfg::STAGE;
-        const bool more = kt + 1 < nk;
-        if (more) {
-            la.load(pa, (kt + 1) * BK, tid);
-            lb.load(pb, (kt + 1) * BK, tid);
+#pragma unroll
+        for (int c = 0; c + 2 < NC; ++c) {
+            f[(c + 1) & 1].read(cur, cur + BM * S, wm, wn, l32, h, c + 1);
+            f[c & 1].mfma(acc);
         }
-        const float* As = cur;
-        const float* Bs = cur + BM * S;
-        // MFMA step (c, e): lanes with h = 0 supply k = 4c + e, lanes with
-        // h = 1 supply k = BK/2 + 4c + e; every k of the slab is used once.
-#pragma unroll
-        for (int c = 0; c < BK / 8; ++c) {
-            f32x4 a[FM], b[FN];
-            const int ko = h * (BK / 2) + 4 * c;
-#pragma unroll
-            for (int i = 0; i < FM; ++i)
-                a[i] = *reinterpret_cast<const f32x4*>(As + (wm + 32 * i + l32) * S + ko);
-#pragma unroll
-            for (int j = 0; j < FN; ++j)
-                b[j] = *reinterpret_cast<const f32x4*>(Bs + (wn + 32 * j + l32) * S + ko);
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int i = 0; i < FM; ++i)
-#pragma unroll
-                    for (int j = 0; j < FN; ++j)
-                        // rows of D = n (from op(B)), columns of D = m (op(A))
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(
-                            b[j][e], a[i][e], acc[i][j], 0, 0, 0);
-        }
-        if (more) {
+        if constexpr (kind == Step::LAST) {
+            if constexpr (NC > 1) {
+                f[(NC - 1) & 1].read(cur, cur + BM * S, wm, wn, l32, h, NC - 1);
+                f[NC & 1].mfma(acc);
+            }
+            f[(NC - 1) & 1].mfma(acc);
+        } else {
+            __builtin_amdgcn_sched_barrier(0);
+            // Chunk NC-2's MFMAs, with the read of chunk NC-1, the writes of
+            // slab kt+1 to LDS and the loads of slab kt+2 issued between
+            // them (their issue then costs no MFMA time).
+            if constexpr (NC > 1)
+                f[(NC - 1) & 1].read(cur, cur + BM * S, wm, wn, l32, h, NC - 1);
             stage_to_lds<LA, BK>(la, nxt, tid, NT);
             stage_to_lds<LB, BK>(lb, nxt + BM * S, tid, NT);
+            if constexpr (kind == Step::STAGE_LOAD_FULL) {
+                la.template load<true>(pa, (kt + 2) * BK);
+                lb.template load<true>(pb, (kt + 2) * BK);
+            } else if constexpr (kind == Step::STAGE_LOAD_PART) {
+                la.template load<false>(pa, (kt + 2) * BK);
+                lb.template load<false>(pb, (kt + 2) * BK);
+            }
+            if constexpr (NC > 1) {
+                f[NC & 1].mfma(acc);
+                if constexpr (IL) {
+                    __builtin_amdgcn_sched_group_barrier(0x100, N_READ, 0);   // DS read
+#pragma unroll
+                    for (int i = 0; i < N_WRITE; ++i) {
+                        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
+                        __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);    // DS write
+                    }
+                    if constexpr (kind != Step::STAGE) {
+#pragma unroll
+                        for (int i = 0; i < (N_VMEM + 1) / 2; ++i) {
+                            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                            __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);  // VMEM read
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            lds_barrier();
+            f[NC & 1].read(nxt, nxt + BM * S, wm, wn, l32, h, 0);
+            // Keep the last chunk's MFMAs after the read of the next slab.
+            __builtin_amdgcn_sched_barrier(0);
+            f[(NC - 1) & 1].mfma(acc);
+            ++kt;
         }
-        __syncthreads();
-    }
+    };
+    using SF = std::integral_constant<Step, Step::STAGE_LOAD_FULL>;
+    using SP = std::integral_constant<Step, Step::STAGE_LOAD_PART>;
+    using SS = std::integral_constant<Step, Step::STAGE>;
+    using SL = std::integral_constant<Step, Step::LAST>;
+    while (kt + 2 < nfull) step(SF{});   // slab kt+2 is full
+    if (kt + 2 < nk) step(SP{});         // slab kt+2 is the partial one
+    if (kt + 1 < nk) step(SS{});
+    step(SL{});
 
     Epi epi(d, m0, n0);
 #pragma unroll

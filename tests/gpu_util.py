@@ -35,6 +35,22 @@ def run(case, precision="fp32", config=-1, stream=None):
     return C.cpu().numpy()[:case["C"].size]
 
 
+# Leading dimension (floats) beyond which byte offsets inside one column
+# block no longer fit the 32-bit buffer addressing: the library switches to
+# 64-bit addresses there.
+WIDE_LD = 2 ** 21 + 3
+
+
+def wide_ldc_case(seed, ta, tb, M, N, K, **kw):
+    """A synth case whose C has leading dimension WIDE_LD (keep N small:
+    the C buffer holds N * WIDE_LD floats)."""
+    c = synth.sgemm_case(seed, ta, tb, M, N, K, pad=3, **kw)
+    rng = np.random.default_rng(seed + 1)
+    c["C"] = synth.matrix(rng, M, N, WIDE_LD, pad=synth.C_SENTINEL)
+    c["ldc"] = WIDE_LD
+    return c
+
+
 def logical_c(cbuf, case):
     M, N, ldc = case["M"], case["N"], case["ldc"]
     return cbuf.reshape(N, ldc)[:, :M].T.astype(np.float64)

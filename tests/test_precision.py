@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import synth
-from gpu_util import log, logical_c, padding_untouched, run, sampled_check
+from gpu_util import log, logical_c, padding_untouched, run, sampled_check, wide_ldc_case
 
 pytestmark = pytest.mark.gpu
 
@@ -184,3 +184,13 @@ def test_packed_ragged_and_tiny(prec, cfg):
         c = synth.sgemm_case(41, "T", "N", M, N, K, alpha=1.5, beta=-0.5, pad=3)
         log("%s packed cfg %d %s" % (prec, cfg, shape))
         check_form(c, prec, run(c, precision=prec, config=cfg))
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+@pytest.mark.parametrize("cfg", [-1, 4])
+@pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "T")])
+def test_forms_leading_dimension_beyond_32bit_offsets(prec, cfg, ta, tb):
+    """ldc above 2**21 floats takes the 64-bit address path in both forms."""
+    c = wide_ldc_case(14, ta, tb, 300, 6, 600, alpha=1.5, beta=-0.5)
+    log("%s wide ldc cfg %d %s%s" % (prec, cfg, ta, tb))
+    check_form(c, prec, run(c, precision=prec, config=cfg))

@@ -5,7 +5,8 @@ import pytest
 import oracle
 import paper_1912_04379_amd as mg
 import synth
-from gpu_util import full_check, log, logical_c, padding_untouched, run, sampled_check
+from gpu_util import (full_check, log, logical_c, padding_untouched, run, sampled_check,
+                      wide_ldc_case)
 
 pytestmark = pytest.mark.gpu
 
@@ -52,6 +53,16 @@ def test_ragged_shapes(ta, tb, shape):
 def test_every_config(cfg, ta, tb):
     c = synth.sgemm_case(3, ta, tb, 300, 270, 77, alpha=1.5, beta=-0.5, pad=3)
     log("f32 cfg %d %s%s" % (cfg, ta, tb))
+    full_check(c, run(c, config=cfg))
+
+
+@pytest.mark.parametrize("cfg", [-1, 1, 5])
+@pytest.mark.parametrize("ta,tb", TRANS)
+def test_leading_dimension_beyond_32bit_offsets(cfg, ta, tb):
+    """ldc above 2**21 floats: the 64-bit address path runs, whichever
+    configuration is asked for.  K = 200 spans 12 full slabs and a partial one."""
+    c = wide_ldc_case(13, ta, tb, 300, 6, 200, alpha=1.5, beta=-0.5)
+    log("f32 wide ldc cfg %d %s%s" % (cfg, ta, tb))
     full_check(c, run(c, config=cfg))
 
 
