@@ -34,24 +34,17 @@ static hipError_t launch_kernel(dim3 grid, const GemmDesc& d, uint32_t tm, uint3
     return hipGetLastError();
 }
 
-template <class Cfg, Form F, bool AK, bool BKC>
-static hipError_t launch_one(dim3 grid, const GemmDesc& d, uint32_t tm, uint32_t tn,
-                             hipStream_t s) {
-    return buffer_path_ok(d) ? launch_kernel<Cfg, F, AK, BKC, true>(grid, d, tm, tn, s)
-                             : launch_kernel<Cfg, F, AK, BKC, false>(grid, d, tm, tn, s);
-}
-
-template <class Cfg, Form F>
+template <class Cfg, Form F, bool BUF>
 static hipError_t launch_cfg(bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
     const int64_t tiles_m = (d.M + Cfg::BM - 1) / Cfg::BM;
     const int64_t tiles_n = (d.N + Cfg::BN - 1) / Cfg::BN;
     if (tiles_m * tiles_n > 0xffffffffLL) return hipErrorInvalidValue;
     dim3 grid((uint32_t)(tiles_m * tiles_n));
     const uint32_t tm = (uint32_t)tiles_m, tn = (uint32_t)tiles_n;
-    if (!ta && !tb) return launch_one<Cfg, F, false, true>(grid, d, tm, tn, s);
-    if (!ta && tb) return launch_one<Cfg, F, false, false>(grid, d, tm, tn, s);
-    if (ta && !tb) return launch_one<Cfg, F, true, true>(grid, d, tm, tn, s);
-    return launch_one<Cfg, F, true, false>(grid, d, tm, tn, s);
+    if (!ta && !tb) return launch_kernel<Cfg, F, false, true, BUF>(grid, d, tm, tn, s);
+    if (!ta && tb) return launch_kernel<Cfg, F, false, false, BUF>(grid, d, tm, tn, s);
+    if (ta && !tb) return launch_kernel<Cfg, F, true, true, BUF>(grid, d, tm, tn, s);
+    return launch_kernel<Cfg, F, true, false, BUF>(grid, d, tm, tn, s);
 }
 
 using LPCfg0 = CfgLP<256, 256, 2, 4>;  // 8 waves of 128x64
@@ -74,12 +67,18 @@ static TileConfigInfo lowp_info(int cfg) {
 
 template <Form F>
 static hipError_t lowp_launch(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
+    if (cfg < 0 || cfg >= LOWP_INSTAGE_CONFIGS) return hipErrorInvalidValue;
+    // A leading dimension beyond 32-bit buffer offsets takes the 64-bit
+    // address path, built for the 64x64 and 128x128 tiles only (larger
+    // tiles would spill registers there).
+    if (!buffer_path_ok(d))
+        return cfg == 3 ? launch_cfg<LPCfg3, F, false>(ta, tb, d, s)
+                        : launch_cfg<LPCfg1, F, false>(ta, tb, d, s);
     switch (cfg) {
-        case 0: return launch_cfg<LPCfg0, F>(ta, tb, d, s);
-        case 1: return launch_cfg<LPCfg1, F>(ta, tb, d, s);
-        case 2: return launch_cfg<LPCfg2, F>(ta, tb, d, s);
-        case 3: return launch_cfg<LPCfg3, F>(ta, tb, d, s);
-        default: return hipErrorInvalidValue;
+        case 0: return launch_cfg<LPCfg0, F, true>(ta, tb, d, s);
+        case 1: return launch_cfg<LPCfg1, F, true>(ta, tb, d, s);
+        case 2: return launch_cfg<LPCfg2, F, true>(ta, tb, d, s);
+        default: return launch_cfg<LPCfg3, F, true>(ta, tb, d, s);
     }
 }
 

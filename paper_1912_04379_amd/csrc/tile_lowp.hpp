@@ -141,19 +141,8 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
         stage_lowp<F, LB, NT>(lb, base + BM * 64, lo + BM * 64, d.expB, n0 / 32, pan_b, tid);
     };
 
-    const int64_t nk = (d.K + BK - 1) / BK;
-    la.load(pa, 0, tid);
-    lb.load(pb, 0, tid);
-    put(0);
-    __syncthreads();
-
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int cur = (int)(kt & 1);
-        const bool more = kt + 1 < nk;
-        if (more) {
-            la.load(pa, (kt + 1) * BK, tid);
-            lb.load(pb, (kt + 1) * BK, tid);
-        }
+    // MFMAs of the slab in LDS stage `cur`.
+    auto compute = [&](int cur) {
         const char* Ah = stage_ptr(cur);
         const char* Bh = Ah + BM * 64;
         const char* Al = Ah + ARR;
@@ -215,9 +204,42 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
                                                                            acc[i][j], 0, 0, 0);
             }
         }
-        if (more) put(cur ^ 1);
-        __syncthreads();
-    }
+    };
+
+    // The K loop is split into straight-line pieces (full-slab loads, the
+    // one partial slab, the last slab) so that no iteration joins two load
+    // sequences, which would make the compiler wait for every load in
+    // flight before the MFMAs.  The loads of slab kt+1 are kept ahead of
+    // the MFMAs of slab kt.
+    const int64_t nk = (d.K + BK - 1) / BK;   // >= 1: K == 0 never reaches here
+    const int64_t nfull = d.K / BK;
+    la.load(pa, 0, tid);
+    lb.load(pb, 0, tid);
+    put(0);
+    __syncthreads();
+
+    int64_t kt = 0;
+    auto step = [&](auto kind_tag) {
+        constexpr int kind = decltype(kind_tag)::value;   // 0 full, 1 partial, 2 last
+        const int cur = (int)(kt & 1);
+        if constexpr (kind == 0) {
+            la.template load<true>(pa, (kt + 1) * BK);
+            lb.template load<true>(pb, (kt + 1) * BK);
+        } else if constexpr (kind == 1) {
+            la.template load<false>(pa, (kt + 1) * BK);
+            lb.template load<false>(pb, (kt + 1) * BK);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        compute(cur);
+        if constexpr (kind != 2) {
+            put(cur ^ 1);
+            __syncthreads();
+            ++kt;
+        }
+    };
+    while (kt + 1 < nfull) step(std::integral_constant<int, 0>{});
+    if (kt + 1 < nk) step(std::integral_constant<int, 1>{});
+    step(std::integral_constant<int, 2>{});
 
     Epi epi(d, m0, n0);
 #pragma unroll
