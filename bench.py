@@ -72,6 +72,59 @@ def timed(fn, steps, warmup, stream):
     return e0.elapsed_time(e1) / steps
 
 
+def per_call_ms(fn, reps, stream):
+    """Median of `reps` individually timed calls (after the timed region)."""
+    import torch
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
+def clock_under_load(fn, seconds=2.0):
+    """Engine clock of each XCD, read with `amd-smi metric --clock --json`
+    while `fn` runs back to back for about `seconds` (None if amd-smi is
+    not there)."""
+    import subprocess
+    import threading
+    import torch
+    out = {}
+
+    def sample():
+        time.sleep(seconds / 2)
+        try:
+            r = subprocess.run(["amd-smi", "metric", "--clock", "--json"], capture_output=True,
+                               text=True, timeout=30)
+            out["json"] = r.stdout if r.returncode == 0 else None
+        except (OSError, subprocess.SubprocessError):
+            out["json"] = None
+
+    th = threading.Thread(target=sample)
+    th.start()
+    t0 = time.perf_counter()
+    while th.is_alive() or time.perf_counter() - t0 < seconds:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
+    th.join()
+    try:
+        gpu = json.loads(out["json"])["gpu_data"][0]["clock"]
+        mhz = [v["clk"]["value"] for k, v in sorted(gpu.items()) if k.startswith("gfx_")]
+        return {"mean_mhz": round(sum(mhz) / len(mhz), 1), "per_xcd_mhz": mhz,
+                "max_mhz": gpu["gfx_0"]["max_clk"]["value"],
+                "how": "amd-smi metric --clock, sampled once mid-way through %.0f s of "
+                       "back-to-back calls" % seconds}
+    except (KeyError, TypeError, ValueError, ZeroDivisionError):
+        return None
+
+
 def cold_time(fn, reps, stream, flush):
     """Median time of one call after writing a 512 MB buffer (evicts L2 and
     the MALL), as the paper flushes caches between calls."""
@@ -178,6 +231,10 @@ def main():
         torch.cuda.synchronize()
 
     f32 = results["fp32"]
+    f32_call = call("fp32", C)
+    f32["median_ms"] = per_call_ms(f32_call, max(20, args.steps), stream)
+    log("fp32: median of single calls %.3f ms; sampling the clock ..." % f32["median_ms"])
+    f32["clock"] = clock_under_load(f32_call)
     line = {
         "metric": METRIC,
         "value": round(f32["tflops"], 3),
@@ -198,6 +255,8 @@ def main():
         "pct_of_fp32_mfma_peak": round(100.0 * f32["tflops"] / PEAK["fp32"], 2),
         "fp32_normwise_err": f32["err"],
         "fp32_cold_ms": f32["cold_ms"],
+        "fp32_median_ms": round(f32["median_ms"], 4),
+        "gpu_clock": f32["clock"],
     }
     key = "sgemm_f32_nn_%d" % n
     traffic = measured_traffic(key, "fp32")
@@ -221,6 +280,7 @@ def main():
                          "normwise_err": h["err"],
                          "mfma_frac": round(h["tflops"] / PEAK["fp16"], 4)}
 
+    line["small_256"] = bench_small(args, mg, torch)
     if not args.no_grouped:
         line["grouped"] = bench_grouped(args, mg, torch)
     if not args.no_dense:
@@ -228,6 +288,7 @@ def main():
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(oracle, case, n, alpha, beta, ld)
+        line["cpu_baseline"]["single_thread_1024"] = cpu_single_thread(oracle, synth)
     print(json.dumps(line), flush=True)
 
 
@@ -249,6 +310,40 @@ def cpu_baseline(oracle, case, n, alpha, beta, ld, target_s=12.0):
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "FP64 oracle, columns 0..%d of the same %d^3 NN product "
                       "(%d x %d outputs), %.1f s" % (J - 1, n, n, J, dt)}
+
+
+def cpu_single_thread(oracle, synth, n=1024):
+    """The oracle on one thread at n^3 (NN, ld n+16, alpha 1.5, beta -0.5)."""
+    c = synth.sgemm_case(0, "N", "N", n, n, n, alpha=1.5, beta=-0.5, pad=16)
+    default = oracle.num_threads()
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        oracle.sgemm("N", "N", n, n, n, 1.5, c["A"], c["lda"], c["B"], c["ldb"], -0.5, c["C"],
+                     c["ldc"])
+        dt = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(default)
+    return {"value": round(2.0 * n ** 3 / dt / 1e12, 6), "unit": "TFLOP/s", "cores": 1,
+            "sample": "FP64 oracle, %d^3 NN, whole product, %.1f s" % (n, dt)}
+
+
+def bench_small(args, mg, torch):
+    """256^3 NN, ld 256, alpha 1, beta 0: the latency-bound end (one small
+    grid of work-groups); reported in microseconds per call."""
+    import numpy as np
+    import synth
+    n = 256
+    c = synth.sgemm_case(0, "N", "N", n, n, n, pad=0)
+    A, B, C = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
+    fn = lambda: mg.sgemm("N", "N", n, n, n, 1.0, A, n, B, n, 0.0, C, n)
+    stream = torch.cuda.current_stream()
+    ms = timed(fn, 200, 20, stream)
+    med = per_call_ms(fn, 50, stream)
+    return {"workload": "sgemm NN 256^3 ld 256 alpha 1 beta 0 fp32",
+            "us_per_call": round(1000 * ms, 2), "median_us": round(1000 * med, 2),
+            "tflops": round(2.0 * n ** 3 / ms / 1e9, 3),
+            "tile_config": mg.default_config("fp32", "N", "N", n, n, n)}
 
 
 def bench_grouped(args, mg, torch):

@@ -46,6 +46,8 @@ def lib():
             f.restype = ctypes.c_int
         L.oracle_num_threads.argtypes = []
         L.oracle_num_threads.restype = ctypes.c_int
+        L.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        L.oracle_set_num_threads.restype = None
         _lib = L
     return _lib
 
@@ -53,6 +55,11 @@ def lib():
 def num_threads():
     """Threads the oracle's parallel loops use."""
     return lib().oracle_num_threads()
+
+
+def set_num_threads(n):
+    """Threads for later oracle calls (results do not depend on it)."""
+    lib().oracle_set_num_threads(int(n))
 
 
 def _ptr(a):

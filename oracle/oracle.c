@@ -210,3 +210,10 @@ int oracle_num_threads(void)
 {
     return omp_get_max_threads();
 }
+
+/* Set that number (n >= 1) for later calls from this thread.  Results do
+ * not depend on it: every output is one sequential dot product. */
+void oracle_set_num_threads(int n)
+{
+    omp_set_num_threads(n < 1 ? 1 : n);
+}

@@ -37,9 +37,9 @@ hipError_t launch_f16_exponents(bool transA, bool transB, const GemmDesc& d,
 hipError_t launch_f16s(int cfg, bool transA, bool transB, const GemmDesc& d,
                        hipStream_t stream);
 
-// Pre-packed 16-bit path (direct-to-LDS engine).  Configurations 0..6 of
-// this family are exposed as configurations 4..10 of the BF16x3 and FP16
-// forms (3 is FP16 only).  The caller provides `workspace` of
+// Pre-packed 16-bit path (direct-to-LDS engine).  Configuration c of this
+// family is configuration LOWP_INSTAGE_CONFIGS + c of the BF16x3 and FP16
+// forms (those whose BF16x3 LDS ring exceeds a CU are FP16 only).  The caller provides `workspace` of
 // packed_workspace_bytes(); for the FP16 form d.expA / d.expB must already
 // hold the panel exponents.
 constexpr int LOWP_INSTAGE_CONFIGS = 4;

@@ -108,7 +108,10 @@ static bool packed_pays(int64_t M, int64_t N, int64_t K) {
 }
 
 int bf16x3_default_config(int64_t M, int64_t N, int64_t K) {
-    if (packed_pays(M, N, K)) return LOWP_INSTAGE_CONFIGS + 1;   // 256x256, 4 x 16-k stages
+    // 256x256, 4 x 16-k stages, fragments of the next stage read while the
+    // current one's second half of MFMAs runs (measured fastest at 4096^3
+    // and 8192^3).
+    if (packed_pays(M, N, K)) return LOWP_INSTAGE_CONFIGS + 6;
     return lowp_default(M, N);
 }
 hipError_t launch_bf16x3(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t s) {

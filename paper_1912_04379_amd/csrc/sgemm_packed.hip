@@ -96,6 +96,21 @@ using PKCfg4 = CfgPK<256, 128, 2, 2, 3, 16>;   // 4 waves of 128x64, 3 stages of
 using PKCfg5 = CfgPK<128, 256, 2, 2, 3, 16>;   // 4 waves of 64x128, 3 stages of 16 k
 // As 1 with fragment double buffering (tile_packed_pp).
 using PKCfg6 = CfgPK<256, 256, 2, 4, 4, 16, 2, true>;
+constexpr int PACKED_CONFIGS = 7;
+
+// Calls f(Cfg{}) for configuration `cfg` (0 <= cfg < PACKED_CONFIGS).
+template <class Fn>
+static auto with_packed_cfg(int cfg, Fn&& f) {
+    switch (cfg) {
+        case 0: return f(PKCfg0{});
+        case 1: return f(PKCfg1{});
+        case 2: return f(PKCfg2{});
+        case 3: return f(PKCfg3{});
+        case 4: return f(PKCfg4{});
+        case 5: return f(PKCfg5{});
+        default: return f(PKCfg6{});
+    }
+}
 
 template <class Cfg, Form F>
 static hipError_t launch_main(const GemmDesc& d, const PackedArgs& pk, hipStream_t s) {
@@ -112,22 +127,28 @@ static hipError_t launch_main(const GemmDesc& d, const PackedArgs& pk, hipStream
     return hipGetLastError();
 }
 
-int packed_config_count() { return 7; }
+int packed_config_count() { return PACKED_CONFIGS; }
 
 TileConfigInfo packed_config_info(int cfg) {
-    switch (cfg) {
-        case 0: return {PKCfg0::BM, PKCfg0::BN, PKCfg0::BK, PKCfg0::NT};
-        case 1: return {PKCfg1::BM, PKCfg1::BN, PKCfg1::BK, PKCfg1::NT};
-        case 2: return {PKCfg2::BM, PKCfg2::BN, PKCfg2::BK, PKCfg2::NT};
-        case 3: return {PKCfg3::BM, PKCfg3::BN, PKCfg3::BK, PKCfg3::NT};
-        case 4: return {PKCfg4::BM, PKCfg4::BN, PKCfg4::BK, PKCfg4::NT};
-        case 5: return {PKCfg5::BM, PKCfg5::BN, PKCfg5::BK, PKCfg5::NT};
-        case 6: return {PKCfg6::BM, PKCfg6::BN, PKCfg6::BK, PKCfg6::NT};
-        default: return {0, 0, 0, 0};
-    }
+    if (cfg < 0 || cfg >= PACKED_CONFIGS) return {0, 0, 0, 0};
+    return with_packed_cfg(cfg, [](auto c) {
+        using C = decltype(c);
+        return TileConfigInfo{C::BM, C::BN, C::BK, C::NT};
+    });
 }
 
-static int packed_kw(int cfg) { return cfg == 1 || cfg >= 4 ? 16 : 32; }
+static int packed_kw(int cfg) {
+    return with_packed_cfg(cfg, [](auto c) { return decltype(c)::KW; });
+}
+
+// LDS ring of the configuration for the form fits in one CU.
+static bool packed_fits(bool bf16x3, int cfg) {
+    return with_packed_cfg(cfg, [&](auto c) {
+        using C = decltype(c);
+        return (bf16x3 ? PackedStage<C, Form::BF16X3>::SMEM : PackedStage<C, Form::F16S>::SMEM) <=
+               160 * 1024;
+    });
+}
 
 // Bytes of device workspace for the packed operands.
 int64_t packed_workspace_bytes(bool bf16x3, int cfg, int64_t M, int64_t N, int64_t K) {
@@ -142,7 +163,7 @@ int64_t packed_workspace_bytes(bool bf16x3, int cfg, int64_t M, int64_t N, int64
 bool packed_supported(bool bf16x3, int cfg, int64_t M, int64_t N, int64_t K) {
     (void)M;
     (void)N;
-    if (cfg < 0 || cfg >= packed_config_count() || (bf16x3 && cfg == 3)) return false;
+    if (cfg < 0 || cfg >= PACKED_CONFIGS || !packed_fits(bf16x3, cfg)) return false;
     const int kw = packed_kw(cfg);
     return 8 * ((K + kw - 1) / kw) * 64LL * kw < (1LL << 31);
 }
@@ -185,22 +206,14 @@ hipError_t launch_packed(bool bf16x3, int cfg, bool ta, bool tb, const GemmDesc&
             e = launch_pack<Form::F16S, 16>(!tb, d.B, d.ldb, d.N, d.K, b_hi, nullptr, d.expB, s);
     }
     if (e != hipSuccess) return e;
-    switch (cfg) {
-        case 0: return bf16x3 ? launch_main<PKCfg0, Form::BF16X3>(d, pk, s)
-                              : launch_main<PKCfg0, Form::F16S>(d, pk, s);
-        case 1: return bf16x3 ? launch_main<PKCfg1, Form::BF16X3>(d, pk, s)
-                              : launch_main<PKCfg1, Form::F16S>(d, pk, s);
-        case 2: return bf16x3 ? launch_main<PKCfg2, Form::BF16X3>(d, pk, s)
-                              : launch_main<PKCfg2, Form::F16S>(d, pk, s);
-        case 3: return bf16x3 ? hipErrorInvalidValue : launch_main<PKCfg3, Form::F16S>(d, pk, s);
-        case 4: return bf16x3 ? launch_main<PKCfg4, Form::BF16X3>(d, pk, s)
-                              : launch_main<PKCfg4, Form::F16S>(d, pk, s);
-        case 5: return bf16x3 ? launch_main<PKCfg5, Form::BF16X3>(d, pk, s)
-                              : launch_main<PKCfg5, Form::F16S>(d, pk, s);
-        case 6: return bf16x3 ? launch_main<PKCfg6, Form::BF16X3>(d, pk, s)
-                              : launch_main<PKCfg6, Form::F16S>(d, pk, s);
-        default: return hipErrorInvalidValue;
-    }
+    if (cfg < 0 || cfg >= PACKED_CONFIGS || !packed_fits(bf16x3, cfg)) return hipErrorInvalidValue;
+    return with_packed_cfg(cfg, [&](auto c) {
+        using C = decltype(c);
+        if constexpr (PackedStage<C, Form::BF16X3>::SMEM <= 160 * 1024) {
+            if (bf16x3) return launch_main<C, Form::BF16X3>(d, pk, s);
+        }
+        return launch_main<C, Form::F16S>(d, pk, s);
+    });
 }
 
 }  // namespace mgemm

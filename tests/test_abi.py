@@ -84,9 +84,13 @@ def test_lowercase_and_conjugate_flags():
 def test_unsupported_precision_and_config():
     assert call(precision=7) == _lib.ERR_UNSUPPORTED
     assert call(config=99) == _lib.ERR_UNSUPPORTED
-    assert mg.config_count("fp32") >= 2
-    info = mg.config_info("fp32", 0)
-    assert info["bm"] > 0 and info["threads"] % 64 == 0
+    assert mg.config_count("fp32") == 8
+    # test_precision enumerates the 16-bit configurations by this count
+    assert mg.config_count("bf16x3") == 11 and mg.config_count("fp16s") == 11
+    for prec in ("fp32", "bf16x3", "fp16s"):
+        for cfg in range(mg.config_count(prec)):
+            info = mg.config_info(prec, cfg)
+            assert info["bm"] > 0 and info["bn"] > 0 and info["threads"] % 64 == 0
 
 
 def test_alias_detected_before_any_launch():

@@ -360,3 +360,21 @@ def test_dense_loss_matches_numpy():
     X, W, G = (v.astype(np.float64) for v in synth.dense_layer(4, 20, 12, 16))
     want = float(np.sum((X @ W) * G))
     assert abs(oracle.dense_loss(X, W, G) - want) <= 1e-12 * max(1.0, abs(want))
+
+
+def test_results_do_not_depend_on_thread_count():
+    """Every output is one sequential dot product, so the thread count can
+    only change who computes it: bitwise equal at 1 thread and at the
+    default count."""
+    c = synth.sgemm_case(77, "T", "N", 70, 130, 90, alpha=1.5, beta=-0.5, pad=3)
+    args = (c["transA"], c["transB"], c["M"], c["N"], c["K"], c["alpha"], c["A"], c["lda"],
+            c["B"], c["ldb"], c["beta"], c["C"], c["ldc"])
+    default = oracle.num_threads()
+    many = oracle.sgemm(*args)
+    try:
+        oracle.set_num_threads(1)
+        assert oracle.num_threads() == 1
+        one = oracle.sgemm(*args)
+    finally:
+        oracle.set_num_threads(default)
+    assert np.array_equal(one, many)
