@@ -87,13 +87,67 @@ __device__ inline void wait_vm_and_barrier() {
     asm volatile("s_waitcnt vmcnt(%0)\n\ts_barrier" ::"n"(N) : "memory");
 }
 
+// Global -> LDS loads of one stage.  A stage is [hi: A rows | B rows]
+// [lo: A rows | B rows] (FP16: the hi half only), cut into 1 KB pieces of
+// RPC rows of one array; wave w loads pieces w*PW .. w*PW+PW-1.  Which
+// array a piece belongs to depends only on the wave, so its base pointer
+// (advanced to the tile's first block) and the bytes left from there are
+// worked out once, as scalars; a stage then costs one descriptor per piece
+// and no selects or branches.  The packed path guarantees fewer than 2^31
+// blocks, so stage numbers are 32-bit.
+template <class Cfg, Form F>
+struct PackedIssuer {
+    using St = PackedStage<Cfg, F>;
+    static constexpr int PW = St::PER_WAVE, RPC = 1024 / Cfg::ROW_BYTES;
+    const char* base[PW];
+    int64_t bytes[PW];
+    uint32_t goff[PW];   // lane's byte offset from the piece's first block
+    int kb, wave;
+
+    __device__ inline PackedIssuer(const PackedArgs& pk, int64_t m0, int64_t n0, int wave_,
+                                   int lane) {
+        constexpr int BM = Cfg::BM, GROUPS = (Cfg::BM + Cfg::BN) / RPC;
+        kb = (int)pk.kb;
+        wave = wave_;
+#pragma unroll
+        for (int t = 0; t < PW; ++t) {
+            const int j = wave * PW + t;
+            const int within = j % GROUPS;                 // row group inside one array
+            const bool is_a = within < BM / RPC;
+            const bool lo = j >= GROUPS;
+            const int rg = is_a ? within : within - BM / RPC;
+            const int p = rg * RPC + lane / Cfg::CPR;      // tile-relative row
+            const int c = pk_slot<Cfg::KW>(p, lane % Cfg::CPR);   // logical chunk of this slot
+            goff[t] = (uint32_t)((int64_t)(p >> 5) * pk.kb * Cfg::BLOCK + (p & 31) * Cfg::ROW_BYTES +
+                                 c * 16);
+            const char* arr = is_a ? (lo ? pk.a_lo : pk.a_hi) : (lo ? pk.b_lo : pk.b_hi);
+            const int64_t first = (is_a ? m0 : n0) / 32 * pk.kb * Cfg::BLOCK;
+            base[t] = arr + first;
+            bytes[t] = (is_a ? pk.pb_a : pk.pb_b) * pk.kb * Cfg::BLOCK - first;
+        }
+    }
+
+    // Loads of stage s into LDS slot s % NS.  Stages past the end of K get
+    // an empty range: every lane reads 0.
+    __device__ inline void issue(char* smem, int s) const {
+        char* stage = smem + (s % Cfg::NS) * St::BYTES;
+        const bool live = s < kb;
+#pragma unroll
+        for (int t = 0; t < PW; ++t) {
+            const int64_t o = (int64_t)s * Cfg::BLOCK;
+            const BufRsrc r = make_rsrc(base[t] + o, live ? bytes[t] - o : 0);
+            char* dst = stage + (wave * PW + t) * 1024;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(r, MGEMM_LDS(dst), 16, goff[t], 0, 0, 0);
+        }
+    }
+};
+
 template <class Cfg, Form F, bool BUF>
 __device__ inline void tile_packed(const GemmDesc& d, const PackedArgs& pk, int64_t m0,
                                    int64_t n0, char* smem) {
     using St = PackedStage<Cfg, F>;
     constexpr int BM = Cfg::BM, NS = Cfg::NS, FM = Cfg::FM, FN = Cfg::FN;
-    constexpr int PW = St::PER_WAVE, KW = Cfg::KW, RB = Cfg::ROW_BYTES, CPR = Cfg::CPR;
-    constexpr int RPC = 1024 / RB;                      // rows per 1 KB load
+    constexpr int PW = St::PER_WAVE, KW = Cfg::KW, RB = Cfg::ROW_BYTES;
     using Epi = typename std::conditional<BUF, EpilogueB, EpilogueG>::type;
     const int tid = threadIdx.x, lane = tid & 63;
     // tid >> 6 is the same on every lane of a wave; say so, so that the
@@ -104,45 +158,8 @@ __device__ inline void tile_packed(const GemmDesc& d, const PackedArgs& pk, int6
     const int wn = (wave / Cfg::WGM) * Cfg::WN;
     const int64_t pan_a = (d.M + 31) / 32, pan_b = (d.N + 31) / 32;
 
-    // ---- which 1 KB pieces of a stage this wave loads ----------------------
-    // Stage layout: [hi: A rows | B rows][lo: A rows | B rows]; piece j covers
-    // RPC rows of one array.  Per piece: array (0 a_hi, 1 b_hi, 2 a_lo,
-    // 3 b_lo) and the lane's byte offset from the slab's first block.
-    int arr[PW];
-    uint32_t goff[PW];
-#pragma unroll
-    for (int t = 0; t < PW; ++t) {
-        const int j = wave * PW + t;
-        const int within = j % ((BM + Cfg::BN) / RPC);  // row group inside one array
-        const bool is_a = within < BM / RPC;
-        const int rg = is_a ? within : within - BM / RPC;
-        arr[t] = (j >= (BM + Cfg::BN) / RPC ? 2 : 0) + (is_a ? 0 : 1);
-        const int p = rg * RPC + lane / CPR;            // tile-relative row
-        const int c = pk_slot<KW>(p, lane % CPR);       // logical chunk of this slot
-        goff[t] = (uint32_t)((int64_t)(p >> 5) * pk.kb * Cfg::BLOCK + (p & 31) * RB + c * 16);
-    }
-    const int64_t blk_a = (m0 / 32) * pk.kb, blk_b = (n0 / 32) * pk.kb;
-    const int64_t bytes_a = pk.pb_a * pk.kb * Cfg::BLOCK, bytes_b = pk.pb_b * pk.kb * Cfg::BLOCK;
-
-    auto issue = [&](int64_t s) {
-        char* stage = smem + (int)(s % NS) * St::BYTES;
-        const int64_t off_a = (blk_a + s) * Cfg::BLOCK, off_b = (blk_b + s) * Cfg::BLOCK;
-        // Slabs past the end of K get an empty range: every lane reads 0.
-        const bool live = s < pk.kb;
-        const BufRsrc ra_hi = make_rsrc(pk.a_hi + off_a, live ? bytes_a - off_a : 0);
-        const BufRsrc rb_hi = make_rsrc(pk.b_hi + off_b, live ? bytes_b - off_b : 0);
-        BufRsrc ra_lo = ra_hi, rb_lo = rb_hi;
-        if constexpr (F == Form::BF16X3) {
-            ra_lo = make_rsrc(pk.a_lo + off_a, live ? bytes_a - off_a : 0);
-            rb_lo = make_rsrc(pk.b_lo + off_b, live ? bytes_b - off_b : 0);
-        }
-#pragma unroll
-        for (int t = 0; t < PW; ++t) {
-            const BufRsrc r = arr[t] == 0 ? ra_hi : arr[t] == 1 ? rb_hi : arr[t] == 2 ? ra_lo : rb_lo;
-            char* dst = stage + (wave * PW + t) * 1024;
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(r, MGEMM_LDS(dst), 16, goff[t], 0, 0, 0);
-        }
-    };
+    const PackedIssuer<Cfg, F> ld(pk, m0, n0, wave, lane);
+    auto issue = [&](int64_t st) { ld.issue(smem, (int)st); };
 
     f32x16 acc[FM][FN];
 #pragma unroll
@@ -266,8 +283,7 @@ __device__ inline void tile_packed_pp(const GemmDesc& d, const PackedArgs& pk, i
                                       int64_t n0, char* smem) {
     using St = PackedStage<Cfg, F>;
     constexpr int BM = Cfg::BM, NS = Cfg::NS, FM = Cfg::FM, FN = Cfg::FN;
-    constexpr int PW = St::PER_WAVE, KW = Cfg::KW, RB = Cfg::ROW_BYTES, CPR = Cfg::CPR;
-    constexpr int RPC = 1024 / RB;
+    constexpr int PW = St::PER_WAVE, KW = Cfg::KW, RB = Cfg::ROW_BYTES;
     static_assert(KW == 16, "one 16-deep MFMA step per stage");
     static_assert(NS >= 3, "at least three stages");
     using Epi = typename std::conditional<BUF, EpilogueB, EpilogueG>::type;
@@ -278,40 +294,8 @@ __device__ inline void tile_packed_pp(const GemmDesc& d, const PackedArgs& pk, i
     const int wn = (wave / Cfg::WGM) * Cfg::WN;
     const int64_t pan_a = (d.M + 31) / 32, pan_b = (d.N + 31) / 32;
 
-    int arr[PW];
-    uint32_t goff[PW];
-#pragma unroll
-    for (int t = 0; t < PW; ++t) {
-        const int j = wave * PW + t;
-        const int within = j % ((BM + Cfg::BN) / RPC);
-        const bool is_a = within < BM / RPC;
-        const int rg = is_a ? within : within - BM / RPC;
-        arr[t] = (j >= (BM + Cfg::BN) / RPC ? 2 : 0) + (is_a ? 0 : 1);
-        const int p = rg * RPC + lane / CPR;
-        const int c = pk_slot<KW>(p, lane % CPR);
-        goff[t] = (uint32_t)((int64_t)(p >> 5) * pk.kb * Cfg::BLOCK + (p & 31) * RB + c * 16);
-    }
-    const int64_t blk_a = (m0 / 32) * pk.kb, blk_b = (n0 / 32) * pk.kb;
-    const int64_t bytes_a = pk.pb_a * pk.kb * Cfg::BLOCK, bytes_b = pk.pb_b * pk.kb * Cfg::BLOCK;
-
-    auto issue = [&](int64_t s) {
-        char* stage = smem + (int)(s % NS) * St::BYTES;
-        const int64_t off_a = (blk_a + s) * Cfg::BLOCK, off_b = (blk_b + s) * Cfg::BLOCK;
-        const bool live = s < pk.kb;
-        const BufRsrc ra_hi = make_rsrc(pk.a_hi + off_a, live ? bytes_a - off_a : 0);
-        const BufRsrc rb_hi = make_rsrc(pk.b_hi + off_b, live ? bytes_b - off_b : 0);
-        BufRsrc ra_lo = ra_hi, rb_lo = rb_hi;
-        if constexpr (F == Form::BF16X3) {
-            ra_lo = make_rsrc(pk.a_lo + off_a, live ? bytes_a - off_a : 0);
-            rb_lo = make_rsrc(pk.b_lo + off_b, live ? bytes_b - off_b : 0);
-        }
-#pragma unroll
-        for (int t = 0; t < PW; ++t) {
-            const BufRsrc r = arr[t] == 0 ? ra_hi : arr[t] == 1 ? rb_hi : arr[t] == 2 ? ra_lo : rb_lo;
-            char* dst = stage + (wave * PW + t) * 1024;
-            __builtin_amdgcn_raw_ptr_buffer_load_lds(r, MGEMM_LDS(dst), 16, goff[t], 0, 0, 0);
-        }
-    };
+    const PackedIssuer<Cfg, F> ld(pk, m0, n0, wave, lane);
+    auto issue = [&](int64_t st) { ld.issue(smem, (int)st); };
     auto co = [](int p, int c) { return p * RB + (pk_slot<KW>(p, c) << 4); };
     auto read = [&](int64_t s, PPFrags<Cfg, F>& f) {
         const char* Ah = smem + (int)(s % NS) * St::BYTES;
