@@ -41,12 +41,14 @@ struct PackedArgs {
 
 // WPE: waves per SIMD the kernel is compiled for (registers <= 512 / WPE);
 // 2 with 4-wave work-groups means two work-groups share each CU.
-// PIPELINED: the fragment-double-buffered main loop (tile_packed_pp).
+// PIPELINED: the fragment-double-buffered main loop (tile_packed_pp), with
+// SPLIT8 eighths of each stage's MFMAs issued before its barrier.
 template <int BM_, int BN_, int WGM_, int WGN_, int NS_, int KW_, int WPE_ = 2,
-          bool PIPELINED_ = false>
+          bool PIPELINED_ = false, int SPLIT8_ = 4>
 struct CfgPK {
     static constexpr int BM = BM_, BN = BN_, BK = KW_, NS = NS_, KW = KW_, WPE = WPE_;
     static constexpr bool PIPELINED = PIPELINED_;
+    static constexpr int SPLIT8 = SPLIT8_;
     static constexpr int WGM = WGM_, WGN = WGN_;
     static constexpr int NT = 64 * WGM * WGN, NWAVES = WGM * WGN;
     static constexpr int WM = BM / WGM, WN = BN / WGN;
@@ -130,7 +132,7 @@ struct PackedIssuer {
     // Loads of stage s into LDS slot s % NS.  Stages past the end of K get
     // an empty range: every lane reads 0.
     __device__ inline void issue(char* smem, int s) const {
-        char* stage = smem + (s % Cfg::NS) * St::BYTES;
+        char* stage = smem + (int)((unsigned)s % Cfg::NS) * St::BYTES;
         const bool live = s < kb;
 #pragma unroll
         for (int t = 0; t < PW; ++t) {
@@ -297,8 +299,8 @@ __device__ inline void tile_packed_pp(const GemmDesc& d, const PackedArgs& pk, i
     const PackedIssuer<Cfg, F> ld(pk, m0, n0, wave, lane);
     auto issue = [&](int64_t st) { ld.issue(smem, (int)st); };
     auto co = [](int p, int c) { return p * RB + (pk_slot<KW>(p, c) << 4); };
-    auto read = [&](int64_t s, PPFrags<Cfg, F>& f) {
-        const char* Ah = smem + (int)(s % NS) * St::BYTES;
+    auto read = [&](int s, PPFrags<Cfg, F>& f) {
+        const char* Ah = smem + (int)((unsigned)s % NS) * St::BYTES;
         const char* Bh = Ah + BM * RB;
         const char* Al = Ah + St::ARR;
         const char* Bl = Al + BM * RB;
@@ -351,32 +353,37 @@ __device__ inline void tile_packed_pp(const GemmDesc& d, const PackedArgs& pk, i
             }
         }
     };
-    using Half = std::integral_constant<int, NQ / 2>;
+    // MFMAs issued before the barrier: any number >= 1 keeps the reads of
+    // stage k complete before stage k's buffer is reloaded (a wave reaches
+    // the barrier only after its first MFMA of stage k, which waits for them).
+    constexpr int SPLIT = NQ * Cfg::SPLIT8 / 8 < 1 ? 1 : NQ * Cfg::SPLIT8 / 8;
+    static_assert(SPLIT >= 1 && SPLIT <= NQ, "split point");
+    using Split = std::integral_constant<int, SPLIT>;
     using Zero = std::integral_constant<int, 0>;
     using All = std::integral_constant<int, NQ>;
 
-    const int64_t nk = pk.kb;
+    const int nk = (int)pk.kb;   // the packed path keeps block counts below 2^31
 #pragma unroll
     for (int s = 0; s < NS; ++s) issue(s);
     PPFrags<Cfg, F> fr[2];
     wait_vm_and_barrier<(NS - 1) * PW>();     // stage 0 has landed
     read(0, fr[0]);
 
-    for (int64_t kt = 0; kt < nk; kt += 2) {
+    for (int kt = 0; kt < nk; kt += 2) {
         // Two iterations per trip so that the register set is a constant.
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int64_t k = kt + u;
+            const int k = kt + u;
             if (k >= nk) break;
             PPFrags<Cfg, F>& cur = fr[u];
             PPFrags<Cfg, F>& nxt = fr[u ^ 1];
-            mfma_range(cur, Zero{}, Half{});
+            mfma_range(cur, Zero{}, Split{});
             __builtin_amdgcn_sched_barrier(0);
             wait_vm_and_barrier<(NS - 2) * PW>();   // stage k+1 has landed
             issue(k + NS);                          // into stage k's buffer
             if (k + 1 < nk) read(k + 1, nxt);
             __builtin_amdgcn_sched_barrier(0);
-            mfma_range(cur, Half{}, All{});
+            mfma_range(cur, Split{}, All{});
         }
     }
     wait_vm_and_barrier<0>();
