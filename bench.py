@@ -372,11 +372,13 @@ def bench_grouped(args, mg, torch):
                           B=base + 4 * offs[3 * i + 1], ldb=d["ldb"],
                           C=base + 4 * offs[3 * i + 2], ldc=d["ldc"]))
     flops = sum(2.0 * p["M"] * p["N"] * p["K"] for p in probs)
+    # Algorithmic bytes: A and B read once, C read (beta = 1) and written once.
+    nbytes = sum(4.0 * (p["M"] * p["K"] + p["K"] * p["N"] + 2 * p["M"] * p["N"]) for p in probs)
     stream = torch.cuda.current_stream()
     L = mg.lib()
     h = stream.cuda_stream
     out = {"workload": "512 GEMMs, M,N,K ~ U{16..512}, transA N/T, alpha=beta=1, seed 0",
-           "gflop_per_step": round(flops / 1e9, 3)}
+           "gflop_per_step": round(flops / 1e9, 3), "gbytes_per_step": round(nbytes / 1e9, 4)}
     for prec in ("fp32", "bf16x3"):
         cfg, _ = mg.tune_grouped(probs, prec, reps=3)
         arena.copy_(init)
@@ -396,6 +398,8 @@ def bench_grouped(args, mg, torch):
         out[prec] = {"bucket_configs": cfg, "tiles": info["tiles"],
                      "workgroups": info["workgroups"],
                      "graph_ms": round(ms_graph, 4), "tflops": round(flops / ms_graph / 1e9, 3),
+                     "gbs": round(nbytes / ms_graph / 1e6, 1),
+                     "hbm_frac": round(nbytes / ms_graph / 1e6 / HBM_PEAK_GBS, 4),
                      "eager_ms": round(ms_eager, 4),
                      "eager_tflops": round(flops / ms_eager / 1e9, 3),
                      "speedup_vs_eager": round(ms_eager / ms_graph, 3)}

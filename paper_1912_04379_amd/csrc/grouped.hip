@@ -2,15 +2,17 @@
 //
 // A plan holds, in device memory, one descriptor per problem (operands,
 // sizes, trans flags, the tile variant chosen for its size bucket, its tile
-// grid) and one list of (problem, tile) references sorted by decreasing
-// cost (K x tile area): longest-processing-time-first order.  The
-// persistent kernel starts (CUs x work-groups per CU) work-groups; after an
-// XCD-aware renumbering (the work-groups of one XCD take neighbouring list
-// entries, which mostly belong to the same problem and so share its
-// operands in that XCD's L2), work-group w computes list entries w, w+G,
-// w+2G, ...  Every tile is written by exactly one work-group with no
-// atomics, so results are bitwise reproducible run to run and between the
-// graph replay and a direct launch.
+// grid) and a schedule: the (problem, tile) references of every work-group
+// of the persistent kernel, made on the host by longest-processing-time-
+// first list scheduling (tiles by decreasing cost ~ (K + 32) x tile area,
+// each to the least-loaded work-group; the first G tiles, the largest, go
+// to work-groups 0..G-1 in order).  The kernel starts (CUs x work-groups
+// per CU) work-groups; after an XCD-aware renumbering (neighbouring
+// work-group numbers run on one XCD, so the neighbouring tiles of one
+// problem they start with share its operands in that XCD's L2), work-group
+// w computes its own list.  Every tile is written by exactly one work-group
+// with no atomics, so results are bitwise reproducible run to run and
+// between the graph replay and a direct launch.
 //
 // The plan records its launch into a HIP graph once; mgemm_grouped_plan_launch
 // replays it.  mgemm_grouped_tune picks the variant of each size bucket by
@@ -19,6 +21,8 @@
 
 #include <algorithm>
 #include <mutex>
+#include <queue>
+#include <utility>
 #include <string>
 #include <unordered_set>
 #include <vector>
@@ -112,10 +116,11 @@ __device__ __attribute__((noinline)) void lp_tile_any(const GemmDesc& d, int ta,
 template <int PREC>
 __global__ __launch_bounds__(256, 2) void grouped_kernel(const GroupedProblem* __restrict__ probs,
                                                       const TileRef* __restrict__ tiles,
-                                                      uint32_t ntiles) {
+                                                      const uint32_t* __restrict__ starts) {
     extern __shared__ __attribute__((aligned(16))) char grouped_smem[];
     const uint32_t w = xcd_remap(blockIdx.x, gridDim.x);
-    for (uint32_t t = w; t < ntiles; t += gridDim.x) {
+    const uint32_t end = starts[w + 1];
+    for (uint32_t t = starts[w]; t < end; ++t) {
         const TileRef tr = tiles[t];
         const GroupedProblem& gp = probs[tr.problem];
         const GemmDesc d = gp.d;
@@ -156,6 +161,7 @@ struct mgemm_plan {
     uint32_t grid = 0;
     mgemm::GroupedProblem* d_probs = nullptr;
     mgemm::TileRef* d_tiles = nullptr;
+    uint32_t* d_starts = nullptr;   // grid + 1 offsets into d_tiles
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -177,6 +183,7 @@ static void plan_free(mgemm_plan* p) {
     if (p->capture) (void)hipStreamDestroy(p->capture);
     if (p->d_probs) (void)hipFree(p->d_probs);
     if (p->d_tiles) (void)hipFree(p->d_tiles);
+    if (p->d_starts) (void)hipFree(p->d_starts);
     delete p;
 }
 
@@ -187,13 +194,12 @@ static int hip_err(hipError_t e, const char* where) {
 
 static hipError_t launch_plan_kernel(const mgemm_plan* p, hipStream_t s) {
     if (p->ntiles == 0) return hipSuccess;
-    const uint32_t n = (uint32_t)p->ntiles;
     if (p->precision == MGEMM_PREC_FP32)
         hipLaunchKernelGGL(grouped_kernel<MGEMM_PREC_FP32>, dim3(p->grid), dim3(256),
-                           lds_of(p->precision), s, p->d_probs, p->d_tiles, n);
+                           lds_of(p->precision), s, p->d_probs, p->d_tiles, p->d_starts);
     else
         hipLaunchKernelGGL(grouped_kernel<MGEMM_PREC_BF16X3>, dim3(p->grid), dim3(256),
-                           lds_of(p->precision), s, p->d_probs, p->d_tiles, n);
+                           lds_of(p->precision), s, p->d_probs, p->d_tiles, p->d_starts);
     return hipGetLastError();
 }
 
@@ -315,8 +321,6 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
     for (size_t k = 0; k < order.size(); ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(),
                      [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<TileRef> sorted(tl.size());
-    for (size_t k = 0; k < order.size(); ++k) sorted[k] = tl[order[k]];
 
     int st = check_device(nullptr);
     if (st) return st;
@@ -324,22 +328,7 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
     hipError_t e = hipGetDevice(&p->device);
     p->precision = precision;
     p->nprob = (int64_t)live.size();
-    p->ntiles = (int64_t)sorted.size();
-    if (e == hipSuccess && !live.empty())
-        e = hipMalloc((void**)&p->d_probs, live.size() * sizeof(GroupedProblem));
-    if (e == hipSuccess && !sorted.empty())
-        e = hipMalloc((void**)&p->d_tiles, sorted.size() * sizeof(TileRef));
-    if (e != hipSuccess) {
-        plan_free(p);
-        (void)hipGetLastError();
-        return fail(MGEMM_ERR_ALLOC, "device memory for the plan's tables");
-    }
-    if (!live.empty())
-        e = hipMemcpy(p->d_probs, live.data(), live.size() * sizeof(GroupedProblem),
-                      hipMemcpyHostToDevice);
-    if (e == hipSuccess && !sorted.empty())
-        e = hipMemcpy(p->d_tiles, sorted.data(), sorted.size() * sizeof(TileRef),
-                      hipMemcpyHostToDevice);
+    p->ntiles = (int64_t)tl.size();
     const void* k = kernel_of(precision);
     const int lds = lds_of(precision);
     if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
@@ -353,6 +342,56 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
     }
     const int64_t slots = (int64_t)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
     p->grid = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(slots, p->ntiles));
+
+    // Longest-processing-time-first list schedule over the work-groups:
+    // each tile, largest first, to the least-loaded work-group (ties to the
+    // lowest number, so the largest G tiles go to work-groups 0..G-1).
+    const uint32_t G = p->grid;
+    std::vector<std::vector<TileRef>> per_wg(G);
+    {
+        using Load = std::pair<double, uint32_t>;
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+        for (uint32_t w = 0; w < G; ++w) heap.push(Load{0.0, w});
+        for (size_t k2 = 0; k2 < order.size(); ++k2) {
+            Load l = heap.top();
+            heap.pop();
+            per_wg[l.second].push_back(tl[order[k2]]);
+            l.first += cost[order[k2]];
+            heap.push(l);
+        }
+    }
+    std::vector<TileRef> sched;
+    std::vector<uint32_t> starts(G + 1, 0);
+    sched.reserve(tl.size());
+    for (uint32_t w = 0; w < G; ++w) {
+        starts[w] = (uint32_t)sched.size();
+        sched.insert(sched.end(), per_wg[w].begin(), per_wg[w].end());
+    }
+    starts[G] = (uint32_t)sched.size();
+
+    if (!live.empty())
+        e = hipMalloc((void**)&p->d_probs, live.size() * sizeof(GroupedProblem));
+    if (e == hipSuccess && !sched.empty())
+        e = hipMalloc((void**)&p->d_tiles, sched.size() * sizeof(TileRef));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_starts, starts.size() * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        plan_free(p);
+        (void)hipGetLastError();
+        return fail(MGEMM_ERR_ALLOC, "device memory for the plan's tables");
+    }
+    if (!live.empty())
+        e = hipMemcpy(p->d_probs, live.data(), live.size() * sizeof(GroupedProblem),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess && !sched.empty())
+        e = hipMemcpy(p->d_tiles, sched.data(), sched.size() * sizeof(TileRef),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_starts, starts.data(), starts.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        plan_free(p);
+        return hip_err(e, "grouped plan upload");
+    }
     *out = p;
     return MGEMM_OK;
 }

@@ -112,19 +112,29 @@ static auto with_packed_cfg(int cfg, Fn&& f) {
     }
 }
 
-template <class Cfg, Form F>
-static hipError_t launch_main(const GemmDesc& d, const PackedArgs& pk, hipStream_t s) {
+template <class Cfg, Form F, bool BUF>
+static hipError_t launch_tiles(const GemmDesc& d, const PackedArgs& pk, hipStream_t s) {
     const int64_t tiles_m = (d.M + Cfg::BM - 1) / Cfg::BM;
     const int64_t tiles_n = (d.N + Cfg::BN - 1) / Cfg::BN;
     if (tiles_m * tiles_n > 0xffffffffLL) return hipErrorInvalidValue;
     constexpr int bytes = PackedStage<Cfg, F>::SMEM;
-    auto k = buffer_path_ok(d) ? packed_kernel<Cfg, F, true> : packed_kernel<Cfg, F, false>;
+    auto k = packed_kernel<Cfg, F, BUF>;
     hipError_t e = hipFuncSetAttribute((const void*)k,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3((uint32_t)(tiles_m * tiles_n)), dim3(Cfg::NT), bytes, s, d, pk,
                        (uint32_t)tiles_m, (uint32_t)tiles_n);
     return hipGetLastError();
+}
+
+template <class Cfg, Form F>
+static hipError_t launch_main(const GemmDesc& d, const PackedArgs& pk, hipStream_t s) {
+    if (buffer_path_ok(d)) return launch_tiles<Cfg, F, true>(d, pk, s);
+    // A leading dimension of C beyond 32-bit buffer offsets: the epilogue
+    // takes 64-bit addresses, built for one smaller tile per block depth
+    // (the packed operands do not change; larger tiles would spill there).
+    using G = typename std::conditional<Cfg::KW == 16, PKCfg4, PKCfg2>::type;
+    return launch_tiles<G, F, false>(d, pk, s);
 }
 
 int packed_config_count() { return PACKED_CONFIGS; }

@@ -249,8 +249,8 @@ __device__ __host__ inline int64_t stored_extent(int64_t rows, int64_t cols, int
 // a 32x32 block holds row 8*(r/4) + 4*(l/32) + (r%4) and column l%32.
 //
 // C <- alpha * acc + beta * C; beta == 0 never reads C.  EpilogueB masks
-// with out-of-range buffer offsets (a dropped store); EpilogueG with
-// predicates.
+// with out-of-range buffer offsets (a dropped store, a load of 0);
+// EpilogueG with predicates.
 // ---------------------------------------------------------------------------
 __device__ inline int mfma32_row(int r, int lane) {
     return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
@@ -269,13 +269,31 @@ struct EpilogueB {
         alpha = d.alpha;
         beta = d.beta;
     }
-    // (m, n) relative to the tile origin.
-    __device__ inline void store(int m, int n, float acc) {
-        const bool ok = m < mrem && n < nrem;
-        const uint32_t off = ok ? (uint32_t)(4 * (m + (int64_t)n * ldc)) : BUF_OOB;
-        float v = alpha * acc;
-        if (beta != 0.0f) v = fmaf(beta, buf_load_f32(r, off), v);
-        buf_store_f32(r, off, v);
+    // One 32x32 MFMA block of this lane: column m and rows n0b +
+    // mfma32_row(0..15, lane), relative to the tile origin.  The 16 loads of
+    // C are issued together, then the 16 stores: one memory round trip per
+    // block, not per element (a load cannot move above an earlier store to
+    // C, so element-wise code would wait for each load in turn).
+    __device__ inline void store_block(int m, int n0b, int lane, const f32x16& acc) {
+        uint32_t off[16];
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int n = n0b + mfma32_row(e, lane);
+            off[e] = m < mrem && n < nrem ? (uint32_t)(4 * (m + (int64_t)n * ldc)) : BUF_OOB;
+        }
+        f32x16 v;
+        if (beta != 0.0f) {
+            float c[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) c[e] = buf_load_f32(r, off[e]);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = fmaf(beta, c[e], alpha * acc[e]);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = alpha * acc[e];
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) buf_store_f32(r, off[e], v[e]);
     }
 };
 
@@ -291,12 +309,30 @@ struct EpilogueG {
         alpha = d.alpha;
         beta = d.beta;
     }
-    __device__ inline void store(int m, int n, float acc) {
-        if (m < mrem && n < nrem) {
-            float* c = C + m + (int64_t)n * ldc;
-            float v = alpha * acc;
-            if (beta != 0.0f) v = fmaf(beta, *c, v);
-            *c = v;
+    // As EpilogueB::store_block, in four groups of 4 (64-bit addresses).
+    __device__ inline void store_block(int m, int n0b, int lane, const f32x16& acc) {
+        float* col = C + m;
+#pragma unroll
+        for (int g = 0; g < 4; ++g) {
+            bool ok[4];
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                ok[e] = m < mrem && n0b + mfma32_row(4 * g + e, lane) < nrem;
+            if (beta != 0.0f) {
+                float c[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    c[e] = ok[e] ? col[(int64_t)(n0b + mfma32_row(4 * g + e, lane)) * ldc] : 0.0f;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = fmaf(beta, c[e], alpha * acc[4 * g + e]);
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = alpha * acc[4 * g + e];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (ok[e]) col[(int64_t)(n0b + mfma32_row(4 * g + e, lane)) * ldc] = v[e];
         }
     }
 };

@@ -241,9 +241,7 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
     for (int i = 0; i < FM; ++i)
 #pragma unroll
         for (int j = 0; j < FN; ++j)
-#pragma unroll
-            for (int r = 0; r < 16; ++r)
-                epi.store(wm + 32 * i + l32, wn + 32 * j + mfma32_row(r, lane), acc[i][j][r]);
+            epi.store_block(wm + 32 * i + l32, wn + 32 * j, lane, acc[i][j]);
 }
 
 }  // namespace mgemm

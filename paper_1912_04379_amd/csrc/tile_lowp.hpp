@@ -251,11 +251,12 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
                 const int64_t pa = (m0 + wm + 32 * i) / 32, pb = (n0 + wn + 32 * j) / 32;
                 sh = -((pa < pan_a ? d.expA[pa] : 0) + (pb < pan_b ? d.expB[pb] : 0));
             }
+            f32x16 v = acc[i][j];
+            if constexpr (F == Form::F16S) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const float v = F == Form::F16S ? ldexpf(acc[i][j][r], sh) : acc[i][j][r];
-                epi.store(wm + 32 * i + l32, wn + 32 * j + mfma32_row(r, lane), v);
+                for (int r = 0; r < 16; ++r) v[r] = ldexpf(v[r], sh);
             }
+            epi.store_block(wm + 32 * i + l32, wn + 32 * j, lane, v);
         }
 }
 
