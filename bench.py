@@ -88,6 +88,14 @@ def per_call_ms(fn, reps, stream):
     return ts[len(ts) // 2]
 
 
+def under_profiler():
+    """True when a profiler's library is preloaded into this process: then
+    no child program may be started (the preload would initialise the GPU
+    in the child before it replaces itself with the new program)."""
+    pre = os.environ.get("LD_PRELOAD", "")
+    return "rocprof" in pre or any(k.startswith("ROCPROF") for k in os.environ)
+
+
 def clock_under_load(fn, seconds=2.0):
     """Engine clock of each XCD, read with `amd-smi metric --clock --json`
     while `fn` runs back to back for about `seconds` (None if amd-smi is
@@ -155,6 +163,8 @@ def main():
     ap.add_argument("--cold-reps", type=int, default=7)
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-clock", action="store_true",
+                    help="do not sample the engine clock with amd-smi")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -234,7 +244,7 @@ def main():
     f32_call = call("fp32", C)
     f32["median_ms"] = per_call_ms(f32_call, max(20, args.steps), stream)
     log("fp32: median of single calls %.3f ms; sampling the clock ..." % f32["median_ms"])
-    f32["clock"] = clock_under_load(f32_call)
+    f32["clock"] = None if (args.no_clock or under_profiler()) else clock_under_load(f32_call)
     line = {
         "metric": METRIC,
         "value": round(f32["tflops"], 3),
