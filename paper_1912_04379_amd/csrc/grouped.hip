@@ -24,6 +24,7 @@
 #include <queue>
 #include <utility>
 #include <string>
+#include <tuple>
 #include <unordered_set>
 #include <vector>
 
@@ -65,9 +66,6 @@ template <class Cfg>
 constexpr int f32_lds() { return Cfg::SMEM_FLOATS * 4; }
 template <class Cfg>
 constexpr int lp_lds() { return 2 * 2 * (Cfg::BM + Cfg::BN) * Cfg::ROW_BYTES; }
-constexpr int cmax(int a, int b) { return a > b ? a : b; }
-constexpr int GROUPED_LDS_F32 = cmax(f32_lds<GF0>(), cmax(f32_lds<GF1>(), f32_lds<GF2>()));
-constexpr int GROUPED_LDS_LP = cmax(lp_lds<GL0>(), cmax(lp_lds<GL1>(), lp_lds<GL2>()));
 
 // Default variant per size bucket (bucket = by max(M, N)).
 static const int DEFAULT_F32[NUM_BUCKETS] = {0, 0, 1, 2};
@@ -89,31 +87,23 @@ struct TileRef {
     uint32_t problem, tile;
 };
 
-// Each variant is a separate (non-inlined) function so that its register
-// allocation is its own; the kernel needs only the largest of them.
-template <class Cfg>
-__device__ __attribute__((noinline)) void f32_tile_any(const GemmDesc& d, int ta, int tb, uint32_t tm, uint32_t tn,
-                                    char* smem) {
-    const int64_t m0 = (int64_t)tm * Cfg::BM, n0 = (int64_t)tn * Cfg::BN;
-    float* s = reinterpret_cast<float*>(smem);
-    // op(A) is K-contiguous for A 'T'; op(B) is K-contiguous for B 'N'.
-    if (!ta && !tb) tile_f32<Cfg, false, true, true>(d, m0, n0, s);
-    else if (!ta)   tile_f32<Cfg, false, false, true>(d, m0, n0, s);
-    else if (!tb)   tile_f32<Cfg, true, true, true>(d, m0, n0, s);
-    else            tile_f32<Cfg, true, false, true>(d, m0, n0, s);
+template <int V>
+using VariantF32 = typename std::tuple_element<V, std::tuple<GF0, GF1, GF2>>::type;
+template <int V>
+using VariantLP = typename std::tuple_element<V, std::tuple<GL0, GL1, GL2>>::type;
+
+template <int PREC, int V>
+constexpr int variant_lds() {
+    if constexpr (PREC == MGEMM_PREC_FP32) return f32_lds<VariantF32<V>>();
+    else return lp_lds<VariantLP<V>>();
 }
 
-template <class Cfg>
-__device__ __attribute__((noinline)) void lp_tile_any(const GemmDesc& d, int ta, int tb, uint32_t tm, uint32_t tn,
-                                   char* smem) {
-    const int64_t m0 = (int64_t)tm * Cfg::BM, n0 = (int64_t)tn * Cfg::BN;
-    if (!ta && !tb) tile_lowp<Cfg, Form::BF16X3, false, true, true>(d, m0, n0, smem);
-    else if (!ta)   tile_lowp<Cfg, Form::BF16X3, false, false, true>(d, m0, n0, smem);
-    else if (!tb)   tile_lowp<Cfg, Form::BF16X3, true, true, true>(d, m0, n0, smem);
-    else            tile_lowp<Cfg, Form::BF16X3, true, false, true>(d, m0, n0, smem);
-}
-
-template <int PREC>
+// One persistent kernel per (precision, tile variant): work-group w (after
+// the XCD renumbering) computes its scheduled tiles starts[w] ..
+// starts[w+1]-1.  The table pointers are kernel arguments, so every field
+// of a problem is a wave-uniform scalar load, and the four operand layouts
+// are inlined tile code, as in the single-call kernels.
+template <int PREC, int V>
 __global__ __launch_bounds__(256, 2) void grouped_kernel(const GroupedProblem* __restrict__ probs,
                                                       const TileRef* __restrict__ tiles,
                                                       const uint32_t* __restrict__ starts) {
@@ -125,31 +115,52 @@ __global__ __launch_bounds__(256, 2) void grouped_kernel(const GroupedProblem* _
         const GroupedProblem& gp = probs[tr.problem];
         const GemmDesc d = gp.d;
         const uint32_t tm = tr.tile % gp.tiles_m, tn = tr.tile / gp.tiles_m;
-        if (PREC == MGEMM_PREC_FP32) {
-            switch (gp.variant) {
-                case 0: f32_tile_any<GF0>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
-                case 1: f32_tile_any<GF1>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
-                default: f32_tile_any<GF2>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
-            }
+        // op(A) is K-contiguous for A 'T'; op(B) is K-contiguous for B 'N'.
+        if constexpr (PREC == MGEMM_PREC_FP32) {
+            using Cfg = VariantF32<V>;
+            const int64_t m0 = (int64_t)tm * Cfg::BM, n0 = (int64_t)tn * Cfg::BN;
+            float* sm = reinterpret_cast<float*>(grouped_smem);
+            if (!gp.ta && !gp.tb) tile_f32<Cfg, false, true, true>(d, m0, n0, sm);
+            else if (!gp.ta)      tile_f32<Cfg, false, false, true>(d, m0, n0, sm);
+            else if (!gp.tb)      tile_f32<Cfg, true, true, true>(d, m0, n0, sm);
+            else                  tile_f32<Cfg, true, false, true>(d, m0, n0, sm);
         } else {
-            switch (gp.variant) {
-                case 0: lp_tile_any<GL0>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
-                case 1: lp_tile_any<GL1>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
-                default: lp_tile_any<GL2>(d, gp.ta, gp.tb, tm, tn, grouped_smem); break;
-            }
+            using Cfg = VariantLP<V>;
+            const int64_t m0 = (int64_t)tm * Cfg::BM, n0 = (int64_t)tn * Cfg::BN;
+            if (!gp.ta && !gp.tb) tile_lowp<Cfg, Form::BF16X3, false, true, true>(d, m0, n0, grouped_smem);
+            else if (!gp.ta)      tile_lowp<Cfg, Form::BF16X3, false, false, true>(d, m0, n0, grouped_smem);
+            else if (!gp.tb)      tile_lowp<Cfg, Form::BF16X3, true, true, true>(d, m0, n0, grouped_smem);
+            else                  tile_lowp<Cfg, Form::BF16X3, true, false, true>(d, m0, n0, grouped_smem);
         }
         __syncthreads();  // LDS is reused by the next tile
     }
 }
 
-static const void* kernel_of(int precision) {
-    return precision == MGEMM_PREC_FP32 ? (const void*)grouped_kernel<MGEMM_PREC_FP32>
-                                        : (const void*)grouped_kernel<MGEMM_PREC_BF16X3>;
+template <int PREC, int V>
+static const void* kernel_ptr() { return (const void*)grouped_kernel<PREC, V>; }
+
+static const void* kernel_of(int precision, int v) {
+    if (precision == MGEMM_PREC_FP32)
+        return v == 0 ? kernel_ptr<MGEMM_PREC_FP32, 0>()
+                      : v == 1 ? kernel_ptr<MGEMM_PREC_FP32, 1>() : kernel_ptr<MGEMM_PREC_FP32, 2>();
+    return v == 0 ? kernel_ptr<MGEMM_PREC_BF16X3, 0>()
+                  : v == 1 ? kernel_ptr<MGEMM_PREC_BF16X3, 1>() : kernel_ptr<MGEMM_PREC_BF16X3, 2>();
 }
 
-static int lds_of(int precision) {
-    return precision == MGEMM_PREC_FP32 ? GROUPED_LDS_F32 : GROUPED_LDS_LP;
+static int lds_of(int precision, int v) {
+    if (precision == MGEMM_PREC_FP32)
+        return v == 0 ? variant_lds<MGEMM_PREC_FP32, 0>()
+                      : v == 1 ? variant_lds<MGEMM_PREC_FP32, 1>() : variant_lds<MGEMM_PREC_FP32, 2>();
+    return v == 0 ? variant_lds<MGEMM_PREC_BF16X3, 0>()
+                  : v == 1 ? variant_lds<MGEMM_PREC_BF16X3, 1>() : variant_lds<MGEMM_PREC_BF16X3, 2>();
 }
+
+// One launch of a plan: the kernel of one variant over its own schedule.
+struct VariantLaunch {
+    int variant;
+    uint32_t grid;
+    int64_t starts_off;   // first of its grid + 1 offsets in the plan's starts table
+};
 
 }  // namespace mgemm
 
@@ -158,7 +169,8 @@ struct mgemm_plan {
     int device = 0;
     int precision = 0;
     int64_t nprob = 0, ntiles = 0;
-    uint32_t grid = 0;
+    uint32_t grid = 0;   // work-groups of the largest launch
+    std::vector<mgemm::VariantLaunch> launches;   // in launch order
     mgemm::GroupedProblem* d_probs = nullptr;
     mgemm::TileRef* d_tiles = nullptr;
     uint32_t* d_starts = nullptr;   // grid + 1 offsets into d_tiles
@@ -193,13 +205,16 @@ static int hip_err(hipError_t e, const char* where) {
 }
 
 static hipError_t launch_plan_kernel(const mgemm_plan* p, hipStream_t s) {
-    if (p->ntiles == 0) return hipSuccess;
-    if (p->precision == MGEMM_PREC_FP32)
-        hipLaunchKernelGGL(grouped_kernel<MGEMM_PREC_FP32>, dim3(p->grid), dim3(256),
-                           lds_of(p->precision), s, p->d_probs, p->d_tiles, p->d_starts);
-    else
-        hipLaunchKernelGGL(grouped_kernel<MGEMM_PREC_BF16X3>, dim3(p->grid), dim3(256),
-                           lds_of(p->precision), s, p->d_probs, p->d_tiles, p->d_starts);
+    for (const VariantLaunch& l : p->launches) {
+        const void* k = kernel_of(p->precision, l.variant);
+        const GroupedProblem* probs = p->d_probs;
+        const TileRef* tiles = p->d_tiles;
+        const uint32_t* starts = p->d_starts + l.starts_off;
+        void* args[] = {&probs, &tiles, &starts};
+        hipError_t e = hipLaunchKernel(k, dim3(l.grid), dim3(256), args,
+                                       (size_t)lds_of(p->precision, l.variant), s);
+        if (e != hipSuccess) return e;
+    }
     return hipGetLastError();
 }
 
@@ -317,11 +332,6 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
         }
     }
     if (tl.size() > 0xffffffffULL) return fail(MGEMM_ERR_UNSUPPORTED, "too many tiles");
-    std::vector<size_t> order(tl.size());
-    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-
     int st = check_device(nullptr);
     if (st) return st;
     mgemm_plan* p = new mgemm_plan();
@@ -329,45 +339,66 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
     p->precision = precision;
     p->nprob = (int64_t)live.size();
     p->ntiles = (int64_t)tl.size();
-    const void* k = kernel_of(precision);
-    const int lds = lds_of(precision);
-    if (e == hipSuccess) e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    int per_cu = 0, cus = 0;
-    if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds);
+    int cus = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                                    p->device);
+
+    // One launch per variant in use, the costliest first.  Each variant's
+    // tiles are list-scheduled longest-processing-time-first over its
+    // work-groups: each tile, largest first, to the least-loaded work-group
+    // (ties to the lowest number, so the largest G tiles go to work-groups
+    // 0..G-1).  All schedules share one tile table and one offsets table.
+    double vcost[NUM_VARIANTS] = {0.0, 0.0, 0.0};
+    std::vector<size_t> by_variant[NUM_VARIANTS];
+    for (size_t k2 = 0; k2 < tl.size(); ++k2) {
+        const int v = live[tl[k2].problem].variant;
+        vcost[v] += cost[k2];
+        by_variant[v].push_back(k2);
+    }
+    int vorder[NUM_VARIANTS] = {0, 1, 2};
+    std::stable_sort(vorder, vorder + NUM_VARIANTS,
+                     [&](int a2, int b2) { return vcost[a2] > vcost[b2]; });
+    std::vector<TileRef> sched;
+    std::vector<uint32_t> starts;
+    sched.reserve(tl.size());
+    for (int vi = 0; vi < NUM_VARIANTS && e == hipSuccess; ++vi) {
+        const int v = vorder[vi];
+        std::vector<size_t>& idx = by_variant[v];
+        if (idx.empty()) continue;
+        const void* k = kernel_of(precision, v);
+        const int lds = lds_of(precision, v);
+        int per_cu = 0;
+        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds);
+        if (e != hipSuccess) break;
+        const int64_t slots = (int64_t)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
+        const uint32_t G = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(slots, (int64_t)idx.size()));
+        std::stable_sort(idx.begin(), idx.end(),
+                         [&](size_t a2, size_t b2) { return cost[a2] > cost[b2]; });
+        std::vector<std::vector<TileRef>> per_wg(G);
+        using Load = std::pair<double, uint32_t>;
+        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+        for (uint32_t w = 0; w < G; ++w) heap.push(Load{0.0, w});
+        for (size_t k2 : idx) {
+            Load l = heap.top();
+            heap.pop();
+            per_wg[l.second].push_back(tl[k2]);
+            l.first += cost[k2];
+            heap.push(l);
+        }
+        p->launches.push_back(VariantLaunch{v, G, (int64_t)starts.size()});
+        for (uint32_t w = 0; w < G; ++w) {
+            starts.push_back((uint32_t)sched.size());
+            sched.insert(sched.end(), per_wg[w].begin(), per_wg[w].end());
+        }
+        starts.push_back((uint32_t)sched.size());
+        p->grid = std::max(p->grid, G);
+    }
     if (e != hipSuccess) {
         plan_free(p);
         return hip_err(e, "grouped plan set-up");
     }
-    const int64_t slots = (int64_t)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
-    p->grid = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(slots, p->ntiles));
-
-    // Longest-processing-time-first list schedule over the work-groups:
-    // each tile, largest first, to the least-loaded work-group (ties to the
-    // lowest number, so the largest G tiles go to work-groups 0..G-1).
-    const uint32_t G = p->grid;
-    std::vector<std::vector<TileRef>> per_wg(G);
-    {
-        using Load = std::pair<double, uint32_t>;
-        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-        for (uint32_t w = 0; w < G; ++w) heap.push(Load{0.0, w});
-        for (size_t k2 = 0; k2 < order.size(); ++k2) {
-            Load l = heap.top();
-            heap.pop();
-            per_wg[l.second].push_back(tl[order[k2]]);
-            l.first += cost[order[k2]];
-            heap.push(l);
-        }
-    }
-    std::vector<TileRef> sched;
-    std::vector<uint32_t> starts(G + 1, 0);
-    sched.reserve(tl.size());
-    for (uint32_t w = 0; w < G; ++w) {
-        starts[w] = (uint32_t)sched.size();
-        sched.insert(sched.end(), per_wg[w].begin(), per_wg[w].end());
-    }
-    starts[G] = (uint32_t)sched.size();
+    if (starts.empty()) starts.push_back(0);
 
     if (!live.empty())
         e = hipMalloc((void**)&p->d_probs, live.size() * sizeof(GroupedProblem));
