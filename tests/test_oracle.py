@@ -378,3 +378,15 @@ def test_results_do_not_depend_on_thread_count():
     finally:
         oracle.set_num_threads(default)
     assert np.array_equal(one, many)
+
+
+def test_golden_integer_cases():
+    """The stored exact results (tests/golden, checked against Fractions
+    when they were written) are reproduced bitwise."""
+    from golden_util import golden_cases
+    cases = golden_cases()
+    assert len(cases) == 6
+    for c, want in cases:
+        got = oracle.sgemm(c["transA"], c["transB"], c["M"], c["N"], c["K"], c["alpha"], c["A"],
+                           c["lda"], c["B"], c["ldb"], c["beta"], c["C"], c["ldc"])
+        assert np.array_equal(got, want)

@@ -200,3 +200,15 @@ def test_forms_leading_dimension_beyond_32bit_offsets(prec, cfg, ta, tb):
     c = wide_ldc_case(14, ta, tb, 300, 6, 600, alpha=1.5, beta=-0.5)
     log("%s wide ldc cfg %d %s%s" % (prec, cfg, ta, tb))
     check_form(c, prec, run(c, precision=prec, config=cfg))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16s"])
+def test_golden_integer_cases_bitwise(prec):
+    """The stored exact integer results (tests/golden): every partial sum is
+    exact in all three forms, so each must reproduce them bitwise."""
+    from golden_util import golden_cases
+    for c, want in golden_cases():
+        log("%s golden %s%s %dx%dx%d" % (prec, c["transA"], c["transB"], c["M"], c["N"], c["K"]))
+        got_buf = run(c, precision=prec)
+        assert padding_untouched(got_buf, c)
+        assert np.array_equal(logical_c(got_buf, c), want)
