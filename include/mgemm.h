@@ -79,9 +79,20 @@ int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
 /*
  * The same operation in one of the MGEMM_PREC_* arithmetics, with an
  * explicit tile configuration `config` (0 .. mgemm_config_count(precision)-1)
- * or -1 for the library's choice.  MGEMM_PREC_FP16_SCALED allocates a small
- * stream-ordered workspace ((M+N)/32 exponents) and frees it in stream
- * order; an allocation failure returns MGEMM_ERR_ALLOC.
+ * or -1 for the library's choice.
+ *
+ * Workspace.  The two 16-bit forms allocate one stream-ordered workspace
+ * per call (hipMallocAsync on `stream`, freed with hipFreeAsync on it after
+ * the call's kernels), so calls on one stream reuse the pool's memory:
+ *   - MGEMM_PREC_FP16_SCALED: the panel exponents, (M+N)/32 ints, and the
+ *     per-panel partial maxima of the exponent pass;
+ *   - configurations 4 and up of either form (the library's choice for
+ *     large products): the operands packed once, 2 bytes per element of A
+ *     and of B for FP16, 4 bytes (hi and lo) for BF16x3 -- 512 MB at
+ *     M = N = K = 8192.
+ * An allocation failure returns MGEMM_ERR_ALLOC before anything runs.  A
+ * packed configuration that the product cannot use (K too long for 32-bit
+ * block offsets, or an LDS ring larger than a CU) runs configuration 0.
  */
 int mgemm_sgemm_ex(char transA, char transB, int64_t M, int64_t N, int64_t K,
                    float alpha, const float *A, int64_t lda,
@@ -156,10 +167,12 @@ typedef struct mgemm_plan mgemm_plan;
  * Problems are sorted into four size buckets (mgemm_grouped_bucket); each
  * bucket uses one tile variant (0 .. mgemm_grouped_variant_count()-1) from
  * `bucket_configs` (4 entries; NULL = library defaults, e.g. from
- * mgemm_grouped_tune).  The plan uploads a descriptor table and a tile
- * list ordered longest-first to device memory it owns, and records one
- * launch of the persistent grouped kernel into a HIP graph (on a private
- * stream; `stream` is unused and may be NULL).  Results are bitwise
+ * mgemm_grouped_tune).  The plan uploads to device memory it owns a
+ * descriptor table and, per tile variant in use, a schedule: every tile
+ * assigned to one work-group of that variant's persistent kernel, largest
+ * tiles first, each to the least-loaded work-group.  It records the
+ * launches (one per variant in use, costliest first) into a HIP graph on a
+ * private stream; `stream` is unused and may be NULL.  Results are bitwise
  * reproducible: every tile of C is written by one work-group, no atomics.
  */
 int mgemm_grouped_plan_create(const mgemm_problem *problems, int64_t count,
@@ -170,10 +183,10 @@ int mgemm_grouped_plan_create(const mgemm_problem *problems, int64_t count,
 /* Replay the plan's graph on `stream` (hipGraphLaunch). */
 int mgemm_grouped_plan_launch(mgemm_plan *plan, void *stream);
 
-/* Launch the plan's persistent kernel directly on `stream` (no graph). */
+/* Launch the plan's persistent kernels directly on `stream` (no graph). */
 int mgemm_grouped_plan_run(mgemm_plan *plan, void *stream);
 
-/* Number of tiles and of work-groups of the plan's persistent launch. */
+/* Number of tiles of the plan, and work-groups of its largest launch. */
 int mgemm_grouped_plan_info(const mgemm_plan *plan, int64_t *tiles,
                             int64_t *workgroups);
 

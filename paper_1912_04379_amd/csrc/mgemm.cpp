@@ -161,7 +161,7 @@ static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K,
     bool packed = cfg >= LOWP_INSTAGE_CONFIGS;
     if (packed && !packed_supported(bf, cfg - LOWP_INSTAGE_CONFIGS, M, N, K)) {
         // Not available for this form, or lane offsets would not fit in 31
-        // bits: stage in place with the same tile instead.
+        // bits: split while staging, with the 256 x 256 in-staging tile.
         packed = false;
         cfg = 0;
     }

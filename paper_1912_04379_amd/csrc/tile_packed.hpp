@@ -263,14 +263,16 @@ __device__ inline void tile_packed(const GemmDesc& d, const PackedArgs& pk, int6
 }
 
 // ---------------------------------------------------------------------------
-// Software-pipelined variant: one wave per SIMD with a large wave tile and
-// two register sets of MFMA fragments.  Iteration kt:
-//   1. first half of stage kt's MFMAs (fragments already in registers);
+// Software-pipelined variant: two register sets of MFMA fragments, so that
+// the next stage's fragments are read while the current stage's MFMAs run.
+// Iteration kt:
+//   1. the first SPLIT8/8 of stage kt's MFMAs (fragments already in
+//      registers);
 //   2. wait for stage kt+1's loads, barrier (every wave has now read stage
 //      kt's fragments, so its LDS buffer is free);
 //   3. issue the loads of stage kt+NS into that buffer;
 //   4. read stage kt+1's fragments into the other register set, overlapped
-//      with the second half of stage kt's MFMAs.
+//      with the rest of stage kt's MFMAs.
 // Every accumulator still takes lo*hi, hi*lo, hi*hi per 16-deep k step in k
 // order, so results equal the other packed configurations bitwise.
 // ---------------------------------------------------------------------------
