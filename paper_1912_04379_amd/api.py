@@ -36,16 +36,43 @@ def _check_tensor(t, name):
         raise TypeError("%s must be a device tensor" % name)
 
 
+def _check_extent(t, name, rows, cols, ld):
+    """The referenced part of a rows x cols column-major array at leading
+    dimension ld, starting at a tensor argument's data_ptr(), must lie in
+    the tensor's storage, so that no kernel reads or writes past it (views
+    such as W.t() are fine; raw addresses are the caller's own)."""
+    if t is None or isinstance(t, int) or rows <= 0 or cols <= 0 or ld < rows:
+        return          # nothing referenced, or the library rejects ld
+    need = 4 * ((cols - 1) * ld + rows)
+    storage = t.untyped_storage()
+    lo, hi = storage.data_ptr(), storage.data_ptr() + storage.nbytes()
+    if t.data_ptr() < lo or t.data_ptr() + need > hi:
+        raise ValueError("%s: a %d x %d array at ld %d needs %d bytes from data_ptr(); the "
+                         "tensor's storage has %d" % (name, rows, cols, ld, need,
+                                                     hi - t.data_ptr()))
+
+
+def check_operands(transA, transB, M, N, K, alpha, A, lda, B, ldb, C, ldc):
+    """Dtype, device and extent checks of tensor arguments."""
+    for t, n in ((A, "A"), (B, "B"), (C, "C")):
+        _check_tensor(t, n)
+    ta, tb = transA in "TtCc", transB in "TtCc"
+    if alpha != 0 and K > 0:
+        _check_extent(A, "A", K if ta else M, M if ta else K, lda)
+        _check_extent(B, "B", N if tb else K, K if tb else N, ldb)
+    _check_extent(C, "C", M, N, ldc)
+
+
 def sgemm(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, *,
           precision="fp32", config=-1, stream=None):
     """C <- alpha op(A) op(B) + beta C on column-major device buffers.
 
-    A, B, C are float32 device tensors (their storage is read as flat
-    column-major arrays from data_ptr()) or raw device addresses.  Raises
-    MgemmError on any non-zero status.
+    A, B, C are float32 device tensors (read as flat column-major arrays
+    from data_ptr(); the part the call references must lie in the tensor's
+    storage, else ValueError) or raw device addresses.  Raises MgemmError on
+    any non-zero status.
     """
-    for t, n in ((A, "A"), (B, "B"), (C, "C")):
-        _check_tensor(t, n)
+    check_operands(transA, transB, M, N, K, alpha, A, lda, B, ldb, C, ldc)
     p = _prec(precision)
     s = stream_handle(stream)
     L = lib()
@@ -131,8 +158,7 @@ def tune_sgemm(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, *,
     """Time every tile configuration for this product (C is overwritten) and
     record the fastest as the library's choice for it.  Returns
     (config, milliseconds)."""
-    for t, n in ((A, "A"), (B, "B"), (C, "C")):
-        _check_tensor(t, n)
+    check_operands(transA, transB, M, N, K, alpha, A, lda, B, ldb, C, ldc)
     cfg = ctypes.c_int(-1)
     ms = ctypes.c_float(0.0)
     check(lib().mgemm_tune_sgemm(transA.encode(), transB.encode(), M, N, K, alpha, _ptr(A), lda,

@@ -143,3 +143,49 @@ def test_recorded_choice_overrides_the_heuristic():
     assert mg.default_config("fp32", "N", "N", 777, 555, 333) == base
     assert L.mgemm_record_choice(0, b"N", b"N", 1, 1, 1, 99) == _lib.ERR_UNSUPPORTED
     assert L.mgemm_record_choice(0, b"Q", b"N", 1, 1, 1, 0) == -1
+
+
+class _FakeStorage:
+    def __init__(self, ptr, nbytes):
+        self.ptr, self.n = ptr, nbytes
+
+    def data_ptr(self):
+        return self.ptr
+
+    def nbytes(self):
+        return self.n
+
+
+class _FakeTensor:
+    """Enough of a device tensor for the binding's argument checks."""
+    is_cuda = True
+
+    def __init__(self, ptr, nbytes, offset=0):
+        import torch
+        self.dtype = torch.float32
+        self._st = _FakeStorage(ptr, nbytes)
+        self._off = offset
+
+    def untyped_storage(self):
+        return self._st
+
+    def data_ptr(self):
+        return self._st.ptr + self._off
+
+
+def test_tensor_extent_is_checked_before_any_call():
+    """A tensor too small for the referenced M x K (ld) array is rejected
+    by the binding, so no kernel can run past it."""
+    from paper_1912_04379_amd.api import check_operands
+    ok = _FakeTensor(FA, 4 * 64 * 64)
+    check_operands("N", "N", 64, 64, 64, 1.0, ok, 64, _FakeTensor(FB, 4 * 64 * 64), 64,
+                   _FakeTensor(FC, 4 * 64 * 64), 64)
+    with pytest.raises(ValueError):        # A one float short
+        check_operands("N", "N", 64, 64, 64, 1.0, _FakeTensor(FA, 4 * 64 * 64 - 4), 64,
+                       ok, 64, ok, 64)
+    with pytest.raises(ValueError):        # C as a view starting 1 KB in
+        check_operands("N", "T", 64, 64, 64, 1.0, ok, 64, ok, 64,
+                       _FakeTensor(FC, 4 * 64 * 64, offset=1024), 64)
+    # alpha == 0: A and B are not referenced, so an empty A is fine
+    check_operands("N", "N", 64, 64, 64, 0.0, _FakeTensor(FA, 0), 64, _FakeTensor(FB, 0), 64,
+                   _FakeTensor(FC, 4 * 64 * 64), 64)
