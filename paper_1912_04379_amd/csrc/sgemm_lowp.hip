@@ -138,8 +138,8 @@ hipError_t launch_f16s(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t
 // Pass 1: one work-group per (panel, 2048-deep range of k) writes the range's
 // amax (NaN if the range holds a NaN) to `partial`.  P-contiguous panels:
 // thread t reads row t % 32 of columns t / 32, t / 32 + 8, ... (each wave
-// instruction reads two 128-byte columns).  K-contiguous panels: the 256
-// threads walk each of the 32 rows along k.
+// instruction reads two 128-byte columns; 8 loads in flight per thread).
+// K-contiguous panels: 16-byte loads along each row, 4 rows at a time.
 // Pass 2: one thread per panel reduces its ranges and writes e.
 // ---------------------------------------------------------------------------
 constexpr int64_t EXP_KRANGE = 2048;
@@ -167,21 +167,58 @@ __global__ __launch_bounds__(256) void f16_amax_kernel(GemmDesc d, int ta, int t
     const int t = threadIdx.x;
     float amax = 0.0f;
     int nan = 0;
+    auto take = [&](float x) {
+        nan |= x != x;
+        amax = fmaxf(amax, fabsf(x));
+    };
     if (pcontig) {
+        // Lane r reads row r of the panel; the 8 lane groups take every
+        // 8th k, 8 loads in flight per lane.
         const int r = t & 31;
-        if (r < rows)
-            for (int64_t k = k0 + (t >> 5); k < k1; k += 8) {
-                const float x = X[(p0 + r) + k * ld];
-                nan |= x != x;
-                amax = fmaxf(amax, fabsf(x));
+        if (r < rows) {
+            const float* col = X + p0 + r;
+            int64_t k = k0 + (t >> 5);
+            for (; k + 56 < k1; k += 64) {
+                float x[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) x[u] = col[(k + 8 * u) * ld];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) take(x[u]);
             }
+            for (; k < k1; k += 8) take(col[k * ld]);
+        }
     } else {
-        for (int64_t r = 0; r < rows; ++r)
-            for (int64_t k = k0 + t; k < k1; k += 256) {
-                const float x = X[k + (p0 + r) * ld];
-                nan |= x != x;
-                amax = fmaxf(amax, fabsf(x));
-            }
+        // Each row of the panel is contiguous over [k0, k1): 16-byte buffer
+        // loads from a descriptor over exactly that range (per-element at the
+        // end), 4 rows at a time.
+        static_assert(EXP_KRANGE <= 2 * 1024, "two sweeps of 1024 k cover a range");
+        const int len = (int)(k1 - k0);
+        for (int64_t r0 = 0; r0 < rows; r0 += 4) {
+            f32x4 v[4][2];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    v[q][i] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+                    if (r0 + q >= rows) continue;
+                    const BufRsrc rs = make_rsrc(X + (p0 + r0 + q) * ld + k0, 4 * (int64_t)len);
+                    const int kk = 4 * t + 1024 * i;
+                    if (kk + 3 < len) {
+                        v[q][i] = buf_load_f32x4(rs, (uint32_t)(4 * kk));
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            v[q][i][e] = buf_load_f32(rs, kk + e < len ? (uint32_t)(4 * (kk + e))
+                                                                       : BUF_OOB);
+                    }
+                }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) take(v[q][i][e]);
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
         amax = fmaxf(amax, __shfl_xor(amax, o));

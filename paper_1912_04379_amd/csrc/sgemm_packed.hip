@@ -8,44 +8,79 @@
 namespace mgemm {
 
 // ---------------------------------------------------------------------------
-// Pack: one work-group (256 threads) per 32-row x 32-k region of op(X);
-// thread t owns 4 consecutive k of one row.  K-contiguous sources (A 'T',
-// B 'N') number the threads k-fastest (8 threads read one 128-byte row
-// segment); P-contiguous sources number them p-fastest (each of the 4 loads
-// reads 32 consecutive rows of one column).  The region lands in one 32 x 32
-// block (KW = 32) or two 32 x 16 blocks (KW = 16), each row-major with k
-// contiguous.  Elements outside P x K are written as zeros.
+// Pack: one work-group (256 threads) per 32-row x 128-k group of op(X) per
+// iteration; thread t owns 4 consecutive k of one row in each of the 4
+// 32-k regions of the group, and issues all 16 loads before it stores.
+// K-contiguous sources (A 'T', B 'N') number the threads k-fastest (8
+// threads read one 128-byte row segment, 16 bytes each); P-contiguous
+// sources number them p-fastest (each load reads 32 consecutive rows of one
+// column).  A region lands in one 32 x 32 block (KW = 32) or two 32 x 16
+// blocks (KW = 16), each row-major with k contiguous.  Elements outside
+// P x K are written as zeros.  BUF: raw buffer loads rebased to each
+// group's first element (elements outside P x K get an out-of-range offset
+// and read 0); otherwise predicated 64-bit loads (leading dimensions above
+// the buffer limit).
 // ---------------------------------------------------------------------------
-template <Form F, bool KC, int KW>
+constexpr int PACK_KG = 128;   // k per group
+
+template <Form F, bool KC, int KW, bool BUF>
 __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ X, int64_t ld,
-                                                   int64_t P, int64_t K, int64_t kb,
-                                                   int64_t kregions, int64_t nregions,
+                                                   int64_t P, int64_t K, int64_t extent,
+                                                   int64_t kb, int64_t kgroups, int64_t ngroups,
                                                    char* __restrict__ hi, char* __restrict__ lo,
                                                    const int* __restrict__ expo) {
     constexpr int RB = 2 * KW;
     const int t = threadIdx.x;
     const int r = KC ? t >> 3 : t & 31;
     const int kq = KC ? t & 7 : t >> 5;
-    for (int64_t g = blockIdx.x; g < nregions; g += gridDim.x) {
-        const int64_t pb = g / kregions, kr = g - pb * kregions;
-        const int64_t p = pb * 32 + r, k = kr * 32 + 4 * kq;
-        const int64_t blk = k / KW;
-        if (blk >= kb) continue;                       // past the last KW block
-        f32x4 v;
+    for (int64_t g = blockIdx.x; g < ngroups; g += gridDim.x) {
+        const int64_t pb = g / kgroups, kg0 = (g - pb * kgroups) * PACK_KG;
+        const int64_t p = pb * 32 + r;
+        f32x4 v[4];
+        if constexpr (BUF) {
+            const int64_t first = KC ? kg0 + pb * 32 * ld : pb * 32 + kg0 * ld;
+            const BufRsrc rs = make_rsrc(X + first, 4 * (extent - first));
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            float x = 0.0f;
-            if (p < P && k + e < K) x = X[KC ? (k + e) + p * ld : p + (k + e) * ld];
-            v[e] = x;
-        }
-        const int64_t off = ((pb * kb + blk) * 32 + r) * RB + (k % KW) * 2;
-        if constexpr (F == Form::BF16X3) {
-            u32x2 h2, l2;
-            split_bf16x4(v, h2, l2);
-            *reinterpret_cast<u32x2*>(hi + off) = h2;
-            *reinterpret_cast<u32x2*>(lo + off) = l2;
+            for (int j = 0; j < 4; ++j) {
+                const int kk = 32 * j + 4 * kq;       // k relative to the group
+                const int64_t k = kg0 + kk;
+                if (KC && p < P && k + 3 < K) {
+                    v[j] = buf_load_f32x4(rs, (uint32_t)(4 * (kk + (int64_t)r * ld)));
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const bool in = p < P && k + e < K;
+                        const uint32_t o = KC ? (uint32_t)(4 * (kk + e + (int64_t)r * ld))
+                                              : (uint32_t)(4 * (r + (int64_t)(kk + e) * ld));
+                        v[j][e] = buf_load_f32(rs, in ? o : BUF_OOB);
+                    }
+                }
+            }
         } else {
-            *reinterpret_cast<u32x2*>(hi + off) = scale_f16x4(v, expo[pb]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t k = kg0 + 32 * j + 4 * kq + e;
+                    float x = 0.0f;
+                    if (p < P && k < K) x = X[KC ? k + p * ld : p + k * ld];
+                    v[j][e] = x;
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t k = kg0 + 32 * j + 4 * kq;
+            const int64_t blk = k / KW;
+            if (blk >= kb) continue;                   // past the last KW block
+            const int64_t off = ((pb * kb + blk) * 32 + r) * RB + (k % KW) * 2;
+            if constexpr (F == Form::BF16X3) {
+                u32x2 h2, l2;
+                split_bf16x4(v[j], h2, l2);
+                *reinterpret_cast<u32x2*>(hi + off) = h2;
+                *reinterpret_cast<u32x2*>(lo + off) = l2;
+            } else {
+                *reinterpret_cast<u32x2*>(hi + off) = scale_f16x4(v[j], expo[pb]);
+            }
         }
     }
 }
@@ -53,16 +88,17 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ X, 
 template <Form F, int KW>
 static hipError_t launch_pack(bool kcontig, const float* X, int64_t ld, int64_t P, int64_t K,
                               char* hi, char* lo, const int* expo, hipStream_t s) {
-    const int64_t pb = (P + 31) / 32, kb = (K + KW - 1) / KW, kreg = (K + 31) / 32;
-    const int64_t n = pb * kreg;
+    const int64_t pb = (P + 31) / 32, kb = (K + KW - 1) / KW;
+    const int64_t kgroups = (K + PACK_KG - 1) / PACK_KG;
+    const int64_t n = pb * kgroups;
     if (n == 0) return hipSuccess;
+    const int64_t extent = kcontig ? stored_extent(K, P, ld) : stored_extent(P, K, ld);
     const uint32_t grid = (uint32_t)(n < 65536 ? n : 65536);
-    if (kcontig)
-        hipLaunchKernelGGL((pack_kernel<F, true, KW>), dim3(grid), dim3(256), 0, s, X, ld, P, K,
-                           kb, kreg, n, hi, lo, expo);
-    else
-        hipLaunchKernelGGL((pack_kernel<F, false, KW>), dim3(grid), dim3(256), 0, s, X, ld, P,
-                           K, kb, kreg, n, hi, lo, expo);
+    const bool buf = ld <= MAX_BUF_LD;
+    auto k = kcontig ? (buf ? pack_kernel<F, true, KW, true> : pack_kernel<F, true, KW, false>)
+                     : (buf ? pack_kernel<F, false, KW, true> : pack_kernel<F, false, KW, false>);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(256), 0, s, X, ld, P, K, extent, kb, kgroups, n, hi, lo,
+                       expo);
     return hipGetLastError();
 }
 
