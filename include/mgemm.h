@@ -81,9 +81,12 @@ int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  * explicit tile configuration `config` (0 .. mgemm_config_count(precision)-1)
  * or -1 for the library's choice.
  *
- * Workspace.  The two 16-bit forms allocate one stream-ordered workspace
- * per call (hipMallocAsync on `stream`, freed with hipFreeAsync on it after
- * the call's kernels), so calls on one stream reuse the pool's memory:
+ * Workspace.  The two 16-bit forms take one stream-ordered workspace per
+ * call (hipMallocFromPoolAsync on `stream`, freed with hipFreeAsync on it
+ * after the call's kernels) from a memory pool the library keeps per
+ * device.  The pool keeps freed memory across synchronisations (release
+ * threshold: unlimited), so later calls reuse it; mgemm_trim_workspace()
+ * hands it back.  The workspace holds:
  *   - MGEMM_PREC_FP16_SCALED: the panel exponents, (M+N)/32 ints, and the
  *     per-panel partial maxima of the exponent pass;
  *   - configurations 4 and up of either form (the library's choice for
@@ -99,6 +102,12 @@ int mgemm_sgemm_ex(char transA, char transB, int64_t M, int64_t N, int64_t K,
                    const float *B, int64_t ldb,
                    float beta, float *C, int64_t ldc, void *stream,
                    int precision, int config);
+
+/*
+ * Return the memory the workspace pools keep (freed workspaces of earlier
+ * 16-bit calls) to the device.  Calls still in flight keep theirs.
+ */
+int mgemm_trim_workspace(void);
 
 /* Number of tile configurations for a precision (0 for an unknown one). */
 int mgemm_config_count(int precision);

@@ -13,7 +13,8 @@ current HIP stream.  PyTorch supplies device memory and streams.
 from ._lib import (MgemmError, PREC_BF16X3, PREC_FP16_SCALED, PREC_FP32, PRECISIONS,
                    check, lib)
 from .api import (clear_choices, config_count, config_info, default_config, matmul,
-                  matmul_args, record_choice, sgemm, stream_handle, tune_sgemm, version)
+                  matmul_args, record_choice, sgemm, stream_handle, trim_workspace, tune_sgemm,
+                  version)
 
 
 def linear(X, W, precision="fp32"):
@@ -27,4 +28,4 @@ from .grouped import GroupedPlan, tune as tune_grouped  # noqa: E402
 __all__ = ["GroupedPlan", "tune_grouped", "MgemmError", "PREC_FP32", "PREC_BF16X3", "PREC_FP16_SCALED", "PRECISIONS",
            "sgemm", "matmul", "matmul_args", "linear", "config_count", "config_info",
            "default_config", "version", "lib", "check", "stream_handle", "tune_sgemm",
-           "record_choice", "clear_choices"]
+           "record_choice", "clear_choices", "trim_workspace"]

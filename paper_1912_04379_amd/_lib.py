@@ -54,6 +54,7 @@ _SIGS = {
                                 ctypes.POINTER(ctypes.c_float)]),
     "mgemm_record_choice": (_i32, [_i32, _ch, _ch, _i64, _i64, _i64, _i32]),
     "mgemm_clear_choices": (_i32, []),
+    "mgemm_trim_workspace": (_i32, []),
     "mgemm_grouped_plan_create": (_i32, [ctypes.POINTER(Problem), _i64, _i32,
                                          ctypes.POINTER(_i32), _vp, ctypes.POINTER(_vp),
                                          ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),

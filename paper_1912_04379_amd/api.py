@@ -179,3 +179,8 @@ def clear_choices():
 
 def version():
     return lib().mgemm_version()
+
+
+def trim_workspace():
+    """Return the memory the library's workspace pools keep to the device."""
+    check(lib().mgemm_trim_workspace())

@@ -6,8 +6,10 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "host_common.hpp"
@@ -105,6 +107,52 @@ int check_device(int* out_dev) {
     return MGEMM_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Workspace pool.  The 16-bit forms take a stream-ordered workspace per
+// call from a memory pool of the library's own, one per device, whose
+// release threshold is the maximum: freed workspace stays with the pool
+// across synchronisations and is handed back only by mgemm_trim_workspace.
+// (The device's default pool returns its memory at every synchronisation,
+// so the next call would map it again: up to a few tenths of a millisecond
+// for the hundreds of megabytes that packed 8192^3 operands take.)
+// ---------------------------------------------------------------------------
+static std::mutex g_pool_mu;
+static hipMemPool_t g_pools[64] = {};
+
+static hipError_t workspace_pool(int dev, hipMemPool_t* out) {
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    if (!g_pools[dev]) {
+        hipMemPoolProps props{};
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        hipError_t e = hipMemPoolCreate(&pool, &props);
+        if (e != hipSuccess) return e;
+        uint64_t keep = UINT64_MAX;
+        e = hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        if (e != hipSuccess) {
+            (void)hipMemPoolDestroy(pool);
+            return e;
+        }
+        g_pools[dev] = pool;
+    }
+    *out = g_pools[dev];
+    return hipSuccess;
+}
+
+int trim_workspace() {
+    std::lock_guard<std::mutex> lk(g_pool_mu);
+    for (hipMemPool_t pool : g_pools) {
+        if (!pool) continue;
+        hipError_t e = hipMemPoolTrimTo(pool, 0);
+        if (e != hipSuccess) return hip_fail(e, "hipMemPoolTrimTo");
+    }
+    return MGEMM_OK;
+}
+
 int config_count(int precision) {
     switch (precision) {
         case MGEMM_PREC_FP32: return f32_config_count();
@@ -142,7 +190,8 @@ static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K,
     if (no_product && beta == 1.0f) return MGEMM_OK;
     if (overlaps(ta, tb, M, N, K, alpha, A, lda, B, ldb, C, ldc))
         return fail(MGEMM_ERR_ALIAS, "C overlaps A or B");
-    int st = check_device(nullptr);
+    int dev = 0;
+    int st = check_device(&dev);
     if (st) return st;
 
     hipStream_t s = (hipStream_t)stream;
@@ -175,7 +224,10 @@ static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K,
         packed ? packed_workspace_bytes(bf, cfg - LOWP_INSTAGE_CONFIGS, M, N, K) : 0;
     char* ws = nullptr;
     if (exp_bytes + pack_bytes > 0) {
-        e = hipMallocAsync((void**)&ws, (size_t)(exp_bytes + pack_bytes), s);
+        hipMemPool_t pool = nullptr;
+        e = workspace_pool(dev, &pool);
+        if (e == hipSuccess)
+            e = hipMallocFromPoolAsync((void**)&ws, (size_t)(exp_bytes + pack_bytes), pool, s);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return fail(MGEMM_ERR_ALLOC, "stream-ordered workspace");
@@ -207,6 +259,8 @@ static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K,
 using namespace mgemm;
 
 extern "C" {
+
+int mgemm_trim_workspace(void) { return trim_workspace(); }
 
 int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
                 const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,

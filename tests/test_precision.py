@@ -212,3 +212,26 @@ def test_golden_integer_cases_bitwise(prec):
         got_buf = run(c, precision=prec)
         assert padding_untouched(got_buf, c)
         assert np.array_equal(logical_c(got_buf, c), want)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+def test_workspace_pool_across_streams_and_trim(prec):
+    """The 16-bit forms take their workspace from the library's pool: calls
+    alternate between a side stream and the default stream, with
+    synchronisations and a trim of the pool in between; every result is
+    checked against the oracle."""
+    import torch
+    import paper_1912_04379_amd as mg
+    cases = [synth.sgemm_case(50 + i, "N", "T", 700 + 64 * i, 650, 900, alpha=1.5, beta=-0.5)
+             for i in range(3)]
+    side = torch.cuda.Stream()
+    for rep in range(2):
+        for i, c in enumerate(cases):
+            log("%s pool rep %d case %d" % (prec, rep, i))
+            if i % 2:
+                with torch.cuda.stream(side):
+                    got = run(c, precision=prec, config=4, stream=side)
+            else:
+                got = run(c, precision=prec, config=4, stream=0)
+            check_form(c, prec, got)
+        mg.trim_workspace()
