@@ -2,6 +2,7 @@
 checked in BLAS order before any HIP call, quick returns launch nothing."""
 import ctypes
 import os
+import random
 import re
 
 import pytest
@@ -143,6 +144,27 @@ def test_recorded_choice_overrides_the_heuristic():
     assert mg.default_config("fp32", "N", "N", 777, 555, 333) == base
     assert L.mgemm_record_choice(0, b"N", b"N", 1, 1, 1, 99) == _lib.ERR_UNSUPPORTED
     assert L.mgemm_record_choice(0, b"Q", b"N", 1, 1, 1, 0) == -1
+
+
+def test_default_configs_are_valid_and_scale_with_the_problem():
+    """The built-in choice is a valid configuration for every shape and
+    transpose; a 1 x 1 x 1 product takes the smallest tile of its form and a
+    large square product a 256-row tile."""
+    rng = random.Random(11)
+    dims = [1, 2, 17, 255, 256, 511, 1000, 3001, 4608, 8192, 40000, 2**20]
+    for prec in ("fp32", "bf16x3", "fp16s"):
+        n_cfg = mg.config_count(prec)
+        for _ in range(200):
+            M, N, K = (rng.choice(dims) for _ in range(3))
+            for ta in "NT":
+                for tb in "NT":
+                    assert 0 <= mg.default_config(prec, ta, tb, M, N, K) < n_cfg
+        tiny = mg.config_info(prec, mg.default_config(prec, "N", "N", 1, 1, 1))
+        smallest = min(mg.config_info(prec, c)["bm"] * mg.config_info(prec, c)["bn"]
+                       for c in range(n_cfg))
+        assert tiny["bm"] * tiny["bn"] == smallest
+        big = mg.config_info(prec, mg.default_config(prec, "N", "N", 8192, 8192, 8192))
+        assert big["bm"] == 256
 
 
 class _FakeStorage:
