@@ -1,0 +1,98 @@
+// defaults.cpp -- built-in tile-configuration rules for single calls, used
+// when no measured choice is recorded for the product.  Host code only.
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace mgemm {
+
+// Default-configuration model.  A tile configuration that runs at `rate` once
+// every CU is busy delivers, on an M x N product, rate x (useful share of the
+// work-group slots it occupies): M*N over rounds x CUs x BM*BN, where a round
+// is one work-group per CU.  This counts both the CUs left idle in the last
+// round and the padding of edge tiles.  MI355X has 256 CUs.
+static constexpr int64_t NUM_CUS = 256;
+static int64_t tile_count(int64_t M, int64_t N, int bm, int bn) {
+    return ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
+}
+static double slot_share(int64_t M, int64_t N, int bm, int bn) {
+    const int64_t rounds = (tile_count(M, N, bm, bn) + NUM_CUS - 1) / NUM_CUS;
+    return rounds == 0 ? 0.0
+                       : (double)M * (double)N / ((double)rounds * NUM_CUS * bm * bn);
+}
+
+int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
+    (void)K;
+    // Candidates with their steady rates measured on MI355X (TFLOP/s, large
+    // square products): 256x128 at 2 waves per SIMD (128x256 for TT, whose
+    // operand layouts favour it), 128x128, 64x64.  Each is scored by the
+    // slot-share model, less 10% while it has fewer tiles than it needs
+    // resident per CU to hide its load latency.  Against measured sweeps
+    // (1024^3 to 8192^3, odd and rectangular shapes, all four transposes)
+    // the pick is within 4% of the fastest of the eight configurations or
+    // is the fastest.
+    struct Cand {
+        int cfg, bm, bn;
+        double rate;
+        int64_t resident;
+    };
+    const Cand cands[3] = {
+        ta && tb ? Cand{6, 128, 256, 147.0, 2} : Cand{5, 256, 128, 147.0, 2},
+        Cand{0, 128, 128, 142.0, 3},
+        Cand{1, 64, 64, 125.0, 6},
+    };
+    int best = 1;
+    double best_score = -1.0;
+    for (const Cand& c : cands) {
+        double score = c.rate * slot_share(M, N, c.bm, c.bn);
+        if (tile_count(M, N, c.bm, c.bn) < c.resident * NUM_CUS) score *= 0.9;
+        if (score > best_score) {
+            best_score = score;
+            best = c.cfg;
+        }
+    }
+    return best;
+}
+
+// In-staging tiles, for products too shallow to repay pre-packing: 256x256
+// once the chip gets at least two rounds of work-groups, otherwise the tile
+// that still gives every CU several work-groups.
+static int lowp_default(int64_t M, int64_t N) {
+    if (tile_count(M, N, 256, 256) >= 512) return 0;
+    if (tile_count(M, N, 128, 128) >= 1024) return 1;
+    return 3;
+}
+
+int bf16x3_default_config(int64_t M, int64_t N, int64_t K) {
+    // From measured sweeps on MI355X (1024^3 to 8192^3, odd and rectangular
+    // shapes, all four transposes).  Pre-packing costs one extra read of A
+    // and B and a write of their two halves: repaid by the pipelined packed
+    // 256x256 tile (4 x 16-k stages) once both M and N reach ~4.5k, while
+    // the in-staging 256x256 tile is faster on a chip's worth of smaller
+    // tiles.  Below that, the tile count decides: in-staging 128x128 while
+    // it still gives every CU more than one tile, packed 128x128 (3 x 32-k
+    // stages) for about one round of deep products, in-staging 64x64 below.
+    const int64_t t256 = tile_count(M, N, 256, 256), t128 = tile_count(M, N, 128, 128);
+    if (t256 >= NUM_CUS && (M < N ? M : N) >= 4608 && K >= 512)
+        return LOWP_INSTAGE_CONFIGS + 6;
+    if (t256 >= 144) return 0;
+    if (t128 > NUM_CUS) return 1;
+    if (t128 >= 192 && K >= 512) return LOWP_INSTAGE_CONFIGS + 2;
+    return 3;
+}
+
+int f16s_default_config(int64_t M, int64_t N, int64_t K) {
+    // Pre-packing costs FP16 only one extra read of A and B and a half-size
+    // write, and its direct-to-LDS main loop beats the in-staging one at
+    // every measured size from 1024^3 up (1.15x there, up to 2.6x at 2048^3
+    // to 3001^3): packed tiles unless K is too short to repay the pass.
+    // Between the packed 256x256 pipelined tile (893 TFLOP/s at 8192^3) and
+    // the packed 128x128 tile (825), the slot-share model picks; the larger
+    // tile's longer prologue needs K of 2048 or more.
+    if (K < 512) return lowp_default(M, N);
+    const double big = 893.0 * slot_share(M, N, 256, 256);
+    const double mid = 825.0 * slot_share(M, N, 128, 128);
+    return K >= 2048 && big > mid ? LOWP_INSTAGE_CONFIGS + 6 : LOWP_INSTAGE_CONFIGS + 2;
+}
+
+}  // namespace mgemm

@@ -12,21 +12,6 @@ struct TileConfigInfo {
     int bm, bn, bk, threads;
 };
 
-// Default-configuration model.  A tile configuration that runs at `rate` once
-// every CU is busy delivers, on an M x N product, rate x (useful share of the
-// work-group slots it occupies): M*N over rounds x CUs x BM*BN, where a round
-// is one work-group per CU.  This counts both the CUs left idle in the last
-// round and the padding of edge tiles.  MI355X has 256 CUs.
-constexpr int64_t NUM_CUS = 256;
-inline int64_t tile_count(int64_t M, int64_t N, int bm, int bn) {
-    return ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
-}
-inline double slot_share(int64_t M, int64_t N, int bm, int bn) {
-    const int64_t rounds = (tile_count(M, N, bm, bn) + NUM_CUS - 1) / NUM_CUS;
-    return rounds == 0 ? 0.0
-                       : (double)M * (double)N / ((double)rounds * NUM_CUS * bm * bn);
-}
-
 // FP32 MFMA path.
 int f32_config_count();
 TileConfigInfo f32_config_info(int cfg);

@@ -82,15 +82,6 @@ static hipError_t lowp_launch(int cfg, bool ta, bool tb, const GemmDesc& d, hipS
     }
 }
 
-// In-staging tiles, for products too shallow to repay pre-packing: 256x256
-// once the chip gets at least two rounds of work-groups, otherwise the tile
-// that still gives every CU several work-groups.
-static int lowp_default(int64_t M, int64_t N) {
-    if (tile_count(M, N, 256, 256) >= 512) return 0;
-    if (tile_count(M, N, 128, 128) >= 1024) return 1;
-    return 3;
-}
-
 static TileConfigInfo lowp_any_info(int cfg) {
     return cfg < LOWP_INSTAGE_CONFIGS ? lowp_info(cfg)
                                       : packed_config_info(cfg - LOWP_INSTAGE_CONFIGS);
@@ -98,42 +89,12 @@ static TileConfigInfo lowp_any_info(int cfg) {
 
 int bf16x3_config_count() { return LOWP_INSTAGE_CONFIGS + packed_config_count(); }
 TileConfigInfo bf16x3_config_info(int cfg) { return lowp_any_info(cfg); }
-int bf16x3_default_config(int64_t M, int64_t N, int64_t K) {
-    // From measured sweeps on MI355X (1024^3 to 8192^3, odd and rectangular
-    // shapes, all four transposes).  Pre-packing costs one extra read of A
-    // and B and a write of their two halves: repaid by the pipelined packed
-    // 256x256 tile (4 x 16-k stages) once both M and N reach ~4.5k, while
-    // the in-staging 256x256 tile is faster on a chip's worth of smaller
-    // tiles.  Below that, the tile count decides: in-staging 128x128 while
-    // it still gives every CU more than one tile, packed 128x128 (3 x 32-k
-    // stages) for about one round of deep products, in-staging 64x64 below.
-    const int64_t t256 = tile_count(M, N, 256, 256), t128 = tile_count(M, N, 128, 128);
-    if (t256 >= NUM_CUS && (M < N ? M : N) >= 4608 && K >= 512)
-        return LOWP_INSTAGE_CONFIGS + 6;
-    if (t256 >= 144) return 0;
-    if (t128 > NUM_CUS) return 1;
-    if (t128 >= 192 && K >= 512) return LOWP_INSTAGE_CONFIGS + 2;
-    return 3;
-}
 hipError_t launch_bf16x3(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
     return lowp_launch<Form::BF16X3>(cfg, ta, tb, d, s);
 }
 
 int f16s_config_count() { return LOWP_INSTAGE_CONFIGS + packed_config_count(); }
 TileConfigInfo f16s_config_info(int cfg) { return lowp_any_info(cfg); }
-int f16s_default_config(int64_t M, int64_t N, int64_t K) {
-    // Pre-packing costs FP16 only one extra read of A and B and a half-size
-    // write, and its direct-to-LDS main loop beats the in-staging one at
-    // every measured size from 1024^3 up (1.15x there, up to 2.6x at 2048^3
-    // to 3001^3): packed tiles unless K is too short to repay the pass.
-    // Between the packed 256x256 pipelined tile (893 TFLOP/s at 8192^3) and
-    // the packed 128x128 tile (825), the slot-share model picks; the larger
-    // tile's longer prologue needs K of 2048 or more.
-    if (K < 512) return lowp_default(M, N);
-    const double big = 893.0 * slot_share(M, N, 256, 256);
-    const double mid = 825.0 * slot_share(M, N, 128, 128);
-    return K >= 2048 && big > mid ? LOWP_INSTAGE_CONFIGS + 6 : LOWP_INSTAGE_CONFIGS + 2;
-}
 hipError_t launch_f16s(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
     return lowp_launch<Form::F16S>(cfg, ta, tb, d, s);
 }
