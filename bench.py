@@ -163,6 +163,8 @@ def main():
     ap.add_argument("--cold-reps", type=int, default=7)
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-vendor", action="store_true",
+                    help="skip the ROCm BLAS (torch.addmm) comparison")
     ap.add_argument("--no-clock", action="store_true",
                     help="do not sample the engine clock with amd-smi")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -291,6 +293,8 @@ def main():
                          "mfma_frac": round(h["tflops"] / PEAK["fp16"], 4)}
 
     line["small_256"] = bench_small(args, mg, torch)
+    if not (args.no_vendor or args.no_forms):
+        line["vendor_blas"] = bench_vendor(args, torch, n, alpha, beta)
     if not args.no_grouped:
         line["grouped"] = bench_grouped(args, mg, torch)
     if not args.no_dense:
@@ -354,6 +358,27 @@ def bench_small(args, mg, torch):
             "us_per_call": round(1000 * ms, 2), "median_us": round(1000 * med, 2),
             "tflops": round(2.0 * n ** 3 / ms / 1e9, 3),
             "tile_config": mg.default_config("fp32", "N", "N", n, n, n)}
+
+
+def bench_vendor(args, torch, n, alpha, beta):
+    """Context, not a target: the same FP32 products through torch.addmm
+    (ROCm's BLAS libraries), TF32-style reduced precision disabled, on
+    unpadded square operands."""
+    torch.backends.cuda.matmul.allow_tf32 = False
+    stream = torch.cuda.current_stream()
+    out = {"library": "torch.addmm %s (ROCm BLAS), fp32" % torch.__version__}
+    for size, steps, warmup in ((n, args.steps, args.warmup), (256, 200, 20)):
+        g = torch.Generator(device="cuda").manual_seed(0)
+        A = torch.rand(size, size, device="cuda", generator=g) * 2 - 1
+        B = torch.rand(size, size, device="cuda", generator=g) * 2 - 1
+        C = torch.rand(size, size, device="cuda", generator=g) * 2 - 1
+        D = torch.empty_like(C)
+        fn = lambda: torch.addmm(C, A, B, beta=beta, alpha=alpha, out=D)
+        ms = timed(fn, steps, warmup, stream)
+        out["n%d" % size] = {"ms": round(ms, 4), "tflops": round(2.0 * size ** 3 / ms / 1e9, 3)}
+        del A, B, C, D
+    log("vendor fp32: %s" % out)
+    return out
 
 
 def bench_grouped(args, mg, torch):
