@@ -22,28 +22,30 @@ static double slot_share(int64_t M, int64_t N, int bm, int bn) {
 }
 
 int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
-    (void)K;
     // Candidates with their steady rates measured on MI355X (TFLOP/s, large
-    // square products): 256x128 at 2 waves per SIMD (128x256 for TT, whose
-    // operand layouts favour it), 128x128, 64x64.  Each is scored by the
-    // slot-share model, less 10% while it has fewer tiles than it needs
-    // resident per CU to hide its load latency.  Against measured sweeps
-    // (1024^3 to 8192^3, odd and rectangular shapes, all four transposes)
-    // the pick is within 4% of the fastest of the eight configurations or
-    // is the fastest.
+    // square products): 256x256 with 32-deep slabs (only for K >= 4096: its
+    // longer prologue and epilogue cost more on shorter products), 256x128
+    // at 2 waves per SIMD (128x256 for TT, whose operand layouts favour it),
+    // 128x128, 64x64.  Each is scored by the slot-share model, less 10%
+    // while it has fewer tiles than it needs resident per CU to hide its
+    // load latency.  Against measured sweeps (1024^3 to 8192^3, odd and
+    // rectangular shapes, all four transposes) the pick is within 4% of the
+    // fastest of the configurations or is the fastest.
     struct Cand {
         int cfg, bm, bn;
         double rate;
-        int64_t resident;
+        int64_t resident, min_k;
     };
-    const Cand cands[3] = {
-        ta && tb ? Cand{6, 128, 256, 147.0, 2} : Cand{5, 256, 128, 147.0, 2},
-        Cand{0, 128, 128, 142.0, 3},
-        Cand{1, 64, 64, 125.0, 6},
+    const Cand cands[4] = {
+        Cand{8, 256, 256, 148.5, 1, 4096},
+        ta && tb ? Cand{6, 128, 256, 147.0, 2, 0} : Cand{5, 256, 128, 147.0, 2, 0},
+        Cand{0, 128, 128, 142.0, 3, 0},
+        Cand{1, 64, 64, 125.0, 6, 0},
     };
     int best = 1;
     double best_score = -1.0;
     for (const Cand& c : cands) {
+        if (K < c.min_k) continue;
         double score = c.rate * slot_share(M, N, c.bm, c.bn);
         if (tile_count(M, N, c.bm, c.bn) < c.resident * NUM_CUS) score *= 0.9;
         if (score > best_score) {

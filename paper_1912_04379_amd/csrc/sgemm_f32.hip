@@ -48,11 +48,14 @@ using F32Cfg4 = CfgF32<128, 128, 16, 2, 2, 2, 2>;  // as 0, at most 2 work-group
 using F32Cfg5 = CfgF32<256, 128, 16, 2, 2, 2>;  // as 3, held to 2 waves per SIMD
 using F32Cfg6 = CfgF32<128, 256, 16, 2, 2, 2>;  // 4 waves of 64x128, 2 waves per SIMD
 using F32Cfg7 = CfgF32<128, 128, 32, 2, 2, 2, 2>;  // as 2, at most 2 work-groups per CU
+// 8 waves of 128x64 at 2 waves per SIMD, one work-group per CU (144 KB of
+// LDS): a third fewer global loads per flop than 256x128.
+using F32Cfg8 = CfgF32<256, 256, 32, 2, 4, 2>;
 
 template <class Cfg>
 static TileConfigInfo info_of() { return {Cfg::BM, Cfg::BN, Cfg::BK, Cfg::NT}; }
 
-int f32_config_count() { return 8; }
+int f32_config_count() { return 9; }
 
 TileConfigInfo f32_config_info(int cfg) {
     switch (cfg) {
@@ -64,6 +67,7 @@ TileConfigInfo f32_config_info(int cfg) {
         case 5: return info_of<F32Cfg5>();
         case 6: return info_of<F32Cfg6>();
         case 7: return info_of<F32Cfg7>();
+        case 8: return info_of<F32Cfg8>();
         default: return {0, 0, 0, 0};
     }
 }
@@ -84,7 +88,8 @@ hipError_t launch_f32(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t 
         case 4: return launch_cfg<F32Cfg4, true>(ta, tb, d, s);
         case 5: return launch_cfg<F32Cfg5, true>(ta, tb, d, s);
         case 6: return launch_cfg<F32Cfg6, true>(ta, tb, d, s);
-        default: return launch_cfg<F32Cfg7, true>(ta, tb, d, s);
+        case 7: return launch_cfg<F32Cfg7, true>(ta, tb, d, s);
+        default: return launch_cfg<F32Cfg8, true>(ta, tb, d, s);
     }
 }
 

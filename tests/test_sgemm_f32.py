@@ -48,7 +48,7 @@ def test_ragged_shapes(ta, tb, shape):
     full_check(c, run(c))
 
 
-@pytest.mark.parametrize("cfg", range(8))
+@pytest.mark.parametrize("cfg", range(9))
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_every_config(cfg, ta, tb):
     c = synth.sgemm_case(3, ta, tb, 300, 270, 77, alpha=1.5, beta=-0.5, pad=3)
@@ -56,7 +56,7 @@ def test_every_config(cfg, ta, tb):
     full_check(c, run(c, config=cfg))
 
 
-@pytest.mark.parametrize("cfg", [-1, 1, 5])
+@pytest.mark.parametrize("cfg", [-1, 1, 5, 8])
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_leading_dimension_beyond_32bit_offsets(cfg, ta, tb):
     """ldc above 2**21 floats: the 64-bit address path runs, whichever
