@@ -18,6 +18,9 @@ TileConfigInfo f32_config_info(int cfg);
 int f32_default_config(bool transA, bool transB, int64_t M, int64_t N, int64_t K);
 hipError_t launch_f32(int cfg, bool transA, bool transB, const GemmDesc& d,
                       hipStream_t stream);
+// FP32 small-product kernel (16 x 16 tiles, k split over 4 waves); needs
+// buffer_path_ok(d).
+hipError_t launch_small(bool transA, bool transB, const GemmDesc& d, hipStream_t stream);
 
 // BF16x3 split path.
 int bf16x3_config_count();

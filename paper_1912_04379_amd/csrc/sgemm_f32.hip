@@ -55,7 +55,10 @@ using F32Cfg8 = CfgF32<256, 256, 32, 2, 4, 2>;
 template <class Cfg>
 static TileConfigInfo info_of() { return {Cfg::BM, Cfg::BN, Cfg::BK, Cfg::NT}; }
 
-int f32_config_count() { return 9; }
+// Configuration 9 is the small-product kernel (sgemm_small.hip).
+constexpr int F32_SMALL_CONFIG = 9;
+
+int f32_config_count() { return 10; }
 
 TileConfigInfo f32_config_info(int cfg) {
     switch (cfg) {
@@ -68,6 +71,7 @@ TileConfigInfo f32_config_info(int cfg) {
         case 6: return info_of<F32Cfg6>();
         case 7: return info_of<F32Cfg7>();
         case 8: return info_of<F32Cfg8>();
+        case F32_SMALL_CONFIG: return {16, 16, 16, 256};
         default: return {0, 0, 0, 0};
     }
 }
@@ -78,8 +82,8 @@ hipError_t launch_f32(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t 
     // address path, built for the 64x64 and 128x128 tiles only (larger
     // tiles would spill registers there).
     if (!buffer_path_ok(d))
-        return cfg == 1 ? launch_cfg<F32Cfg1, false>(ta, tb, d, s)
-                        : launch_cfg<F32Cfg0, false>(ta, tb, d, s);
+        return cfg == 1 || cfg == F32_SMALL_CONFIG ? launch_cfg<F32Cfg1, false>(ta, tb, d, s)
+                                                   : launch_cfg<F32Cfg0, false>(ta, tb, d, s);
     switch (cfg) {
         case 0: return launch_cfg<F32Cfg0, true>(ta, tb, d, s);
         case 1: return launch_cfg<F32Cfg1, true>(ta, tb, d, s);
@@ -89,7 +93,8 @@ hipError_t launch_f32(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t 
         case 5: return launch_cfg<F32Cfg5, true>(ta, tb, d, s);
         case 6: return launch_cfg<F32Cfg6, true>(ta, tb, d, s);
         case 7: return launch_cfg<F32Cfg7, true>(ta, tb, d, s);
-        default: return launch_cfg<F32Cfg8, true>(ta, tb, d, s);
+        case 8: return launch_cfg<F32Cfg8, true>(ta, tb, d, s);
+        default: return launch_small(ta, tb, d, s);
     }
 }
 

@@ -85,7 +85,7 @@ def test_lowercase_and_conjugate_flags():
 def test_unsupported_precision_and_config():
     assert call(precision=7) == _lib.ERR_UNSUPPORTED
     assert call(config=99) == _lib.ERR_UNSUPPORTED
-    assert mg.config_count("fp32") == 9
+    assert mg.config_count("fp32") == 10
     # test_precision enumerates the 16-bit configurations by this count
     assert mg.config_count("bf16x3") == 11 and mg.config_count("fp16s") == 11
     for prec in ("fp32", "bf16x3", "fp16s"):
@@ -148,7 +148,7 @@ def test_recorded_choice_overrides_the_heuristic():
 
 def test_default_configs_are_valid_and_scale_with_the_problem():
     """The built-in choice is a valid configuration for every shape and
-    transpose; a 1 x 1 x 1 product takes the smallest tile of its form and a
+    transpose; a 1 x 1 x 1 product takes a tile of at most 64 x 64 and a
     large square product a 256-row tile."""
     rng = random.Random(11)
     dims = [1, 2, 17, 255, 256, 511, 1000, 3001, 4608, 8192, 40000, 2**20]
@@ -160,9 +160,7 @@ def test_default_configs_are_valid_and_scale_with_the_problem():
                 for tb in "NT":
                     assert 0 <= mg.default_config(prec, ta, tb, M, N, K) < n_cfg
         tiny = mg.config_info(prec, mg.default_config(prec, "N", "N", 1, 1, 1))
-        smallest = min(mg.config_info(prec, c)["bm"] * mg.config_info(prec, c)["bn"]
-                       for c in range(n_cfg))
-        assert tiny["bm"] * tiny["bn"] == smallest
+        assert tiny["bm"] * tiny["bn"] <= 64 * 64
         big = mg.config_info(prec, mg.default_config(prec, "N", "N", 8192, 8192, 8192))
         assert big["bm"] == 256
 

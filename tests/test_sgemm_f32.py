@@ -48,7 +48,7 @@ def test_ragged_shapes(ta, tb, shape):
     full_check(c, run(c))
 
 
-@pytest.mark.parametrize("cfg", range(9))
+@pytest.mark.parametrize("cfg", range(10))
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_every_config(cfg, ta, tb):
     c = synth.sgemm_case(3, ta, tb, 300, 270, 77, alpha=1.5, beta=-0.5, pad=3)
@@ -56,7 +56,19 @@ def test_every_config(cfg, ta, tb):
     full_check(c, run(c, config=cfg))
 
 
-@pytest.mark.parametrize("cfg", [-1, 1, 5, 8])
+@pytest.mark.parametrize("ta,tb", TRANS)
+@pytest.mark.parametrize("shape", [(1, 1, 1), (17, 15, 3), (16, 16, 16), (33, 47, 17),
+                                   (20, 40, 65), (100, 3, 129), (64, 64, 200), (48, 80, 1000)])
+def test_small_product_kernel(ta, tb, shape):
+    """Configuration 9 (16 x 16 tiles, k split over four waves): ragged
+    tiles, k ranges from one group shared by four waves to many batches."""
+    M, N, K = shape
+    c = synth.sgemm_case(17, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=3)
+    log("f32 small %s %s%s" % (shape, ta, tb))
+    full_check(c, run(c, config=9))
+
+
+@pytest.mark.parametrize("cfg", [-1, 1, 5, 8, 9])
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_leading_dimension_beyond_32bit_offsets(cfg, ta, tb):
     """ldc above 2**21 floats: the 64-bit address path runs, whichever
@@ -64,6 +76,49 @@ def test_leading_dimension_beyond_32bit_offsets(cfg, ta, tb):
     c = wide_ldc_case(13, ta, tb, 300, 6, 200, alpha=1.5, beta=-0.5)
     log("f32 wide ldc cfg %d %s%s" % (cfg, ta, tb))
     full_check(c, run(c, config=cfg))
+
+
+def test_single_calls_captured_in_a_graph():
+    """FP32 calls allocate nothing and never synchronise, so a caller can
+    capture them in a HIP graph.  Two calls (the small-product kernel and a
+    256 x 256 tile kernel) are captured; each of three replays, with eager
+    work and a synchronisation between them, equals the eager result
+    bitwise."""
+    import torch
+    from gpu_util import to_dev
+    cases = [synth.sgemm_case(21, "N", "N", 256, 256, 256, alpha=1.5, beta=0.0, pad=0),
+             synth.sgemm_case(22, "T", "N", 600, 520, 4100, alpha=1.0, beta=0.0, pad=3)]
+    cfgs = [9, 8]
+    bufs = [tuple(to_dev(c[k]) for k in ("A", "B", "C")) for c in cases]
+
+    def calls():
+        for c, cfg, (A, B, C) in zip(cases, cfgs, bufs):
+            mg.sgemm(c["transA"], c["transB"], c["M"], c["N"], c["K"], float(c["alpha"]), A,
+                     c["lda"], B, c["ldb"], float(c["beta"]), C, c["ldc"], config=cfg)
+
+    log("f32 graph capture: eager")
+    calls()
+    torch.cuda.synchronize()
+    eager = [C.clone() for (_, _, C) in bufs]
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        calls()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    log("f32 graph capture: capture")
+    with torch.cuda.graph(g):
+        calls()
+    for rep in range(3):
+        for c, (_, _, C) in zip(cases, bufs):     # C's logical part only
+            C[:c["N"] * c["ldc"]].view(c["N"], c["ldc"])[:, :c["M"]].fill_(float("nan"))
+        torch.cuda.synchronize()
+        log("f32 graph capture: replay %d" % rep)
+        g.replay()
+        torch.cuda.synchronize()
+        for (_, _, C), ref in zip(bufs, eager):
+            assert torch.equal(C, ref), "replay %d differs from the eager result" % rep
 
 
 @pytest.mark.parametrize("ta,tb", TRANS)
