@@ -133,7 +133,8 @@ def test_integer_inputs_bitwise(ta, tb):
     assert np.array_equal(got, ref)
 
 
-def test_identity_is_exact():
+@pytest.mark.parametrize("cfg", [-1, 1, 8, 9])
+def test_identity_is_exact(cfg):
     n, N = 160, 70
     rng = np.random.default_rng(4)
     A = np.eye(n, dtype=np.float32).ravel(order="F")
@@ -141,7 +142,7 @@ def test_identity_is_exact():
     C = synth.matrix(rng, n, N, n, pad=synth.C_SENTINEL)
     c = dict(transA="N", transB="N", M=n, N=N, K=n, alpha=np.float32(1), beta=np.float32(0),
              A=A, lda=n, B=B, ldb=n + 4, C=C, ldc=n)
-    got = logical_c(run(c), c)
+    got = logical_c(run(c, config=cfg), c)
     assert np.array_equal(got, B.reshape(N, n + 4)[:, :n].T.astype(np.float64))
 
 
@@ -154,10 +155,11 @@ def test_k_zero_and_alpha_zero():
         assert padding_untouched(got, c)
 
 
-def test_beta_zero_ignores_nan_in_c():
+@pytest.mark.parametrize("cfg", [-1, 8, 9])
+def test_beta_zero_ignores_nan_in_c(cfg):
     c = synth.sgemm_case(6, "T", "N", 90, 80, 70, pad=2)
     c["C"] = np.where(c["C"] == synth.C_SENTINEL, c["C"], np.float32(np.nan)).astype(np.float32)
-    got = run(c)
+    got = run(c, config=cfg)
     assert np.all(np.isfinite(logical_c(got, c)))
 
 
@@ -177,12 +179,13 @@ def test_side_stream_and_default_stream():
     full_check(c, run(c, stream=0))
 
 
-def test_nan_in_a_row_reaches_that_row_only():
+@pytest.mark.parametrize("cfg", [-1, 8, 9])
+def test_nan_in_a_row_reaches_that_row_only(cfg):
     c = synth.sgemm_case(10, "N", "N", 100, 60, 50, pad=1)
     A = c["A"].copy()
     A[17 + 3 * c["lda"]] = np.nan       # op(A)[17, 3]
     c["A"] = A
-    got = logical_c(run(c), c)
+    got = logical_c(run(c, config=cfg), c)
     assert np.all(np.isnan(got[17, :]))
     assert np.all(np.isfinite(np.delete(got, 17, axis=0)))
 
