@@ -217,8 +217,10 @@ int mgemm_grouped_variant_info(int precision, int variant, int *bm, int *bn,
 /*
  * Autotuner: choose the variant of every size bucket present in the batch
  * by timing the whole grouped launch on `stream` (best of `reps` timed
- * runs after one warm-up, HIP events), one bucket at a time, starting from
- * the defaults.  Writes 4 entries to bucket_configs and the best time in
+ * runs after one warm-up, HIP events): the defaults and each assignment of
+ * one variant to every bucket are timed, then, from the fastest, each
+ * bucket in turn tries every variant (two passes).  Writes 4 entries to
+ * bucket_configs and the best time in
  * milliseconds to *best_ms (may be NULL).  The problems are RUN: every C
  * is overwritten with unspecified values, so tune on scratch outputs or
  * re-initialise C afterwards.  Synchronises `stream`.

@@ -553,23 +553,39 @@ int mgemm_grouped_tune(const mgemm_problem* problems, int64_t count, int precisi
         ms = best;
         return MGEMM_OK;
     };
+    // Start from the fastest of the defaults and the single-variant
+    // assignments (one launch for the whole batch: no launch waits behind
+    // another's last work-groups), then descend one bucket at a time, in two
+    // passes so that an early bucket is revisited once the later ones moved.
     float cur = 0.0f;
     int st = time_of(bucket_configs, cur);
-    for (int b = 0; b < NUM_BUCKETS && st == MGEMM_OK; ++b) {
-        if (!used[b]) continue;
-        const int keep = bucket_configs[b];
-        int best_v = keep;
-        for (int v = 0; v < NUM_VARIANTS && st == MGEMM_OK; ++v) {
-            if (v == keep) continue;
-            bucket_configs[b] = v;
-            float t = 0.0f;
-            st = time_of(bucket_configs, t);
-            if (st == MGEMM_OK && t < cur) {
-                cur = t;
-                best_v = v;
-            }
+    for (int v = 0; v < NUM_VARIANTS && st == MGEMM_OK; ++v) {
+        int uni[NUM_BUCKETS];
+        for (int b = 0; b < NUM_BUCKETS; ++b) uni[b] = v;
+        float t = 0.0f;
+        st = time_of(uni, t);
+        if (st == MGEMM_OK && t < cur) {
+            cur = t;
+            for (int b = 0; b < NUM_BUCKETS; ++b) bucket_configs[b] = v;
         }
-        bucket_configs[b] = best_v;
+    }
+    for (int pass = 0; pass < 2 && st == MGEMM_OK; ++pass) {
+        for (int b = 0; b < NUM_BUCKETS && st == MGEMM_OK; ++b) {
+            if (!used[b]) continue;
+            const int keep = bucket_configs[b];
+            int best_v = keep;
+            for (int v = 0; v < NUM_VARIANTS && st == MGEMM_OK; ++v) {
+                if (v == keep) continue;
+                bucket_configs[b] = v;
+                float t = 0.0f;
+                st = time_of(bucket_configs, t);
+                if (st == MGEMM_OK && t < cur) {
+                    cur = t;
+                    best_v = v;
+                }
+            }
+            bucket_configs[b] = best_v;
+        }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
