@@ -175,8 +175,9 @@ typedef struct mgemm_plan mgemm_plan;
  * problem's C, A or B.  Leading dimensions must not exceed 2^21 - 64.
  * Problems are sorted into four size buckets (mgemm_grouped_bucket); each
  * bucket uses one tile variant (0 .. mgemm_grouped_variant_count()-1) from
- * `bucket_configs` (4 entries; NULL = library defaults, e.g. from
- * mgemm_grouped_tune).  The plan uploads to device memory it owns a
+ * `bucket_configs` (4 entries, e.g. from mgemm_grouped_tune; NULL = the
+ * library defaults, one variant for every bucket: FP32 64x64x16, BF16x3
+ * 128x128).  The plan uploads to device memory it owns a
  * descriptor table and, per tile variant in use, a schedule: every tile
  * assigned to one work-group of that variant's persistent kernel, largest
  * tiles first, each to the least-loaded work-group.  It records the

@@ -121,11 +121,14 @@ def check_batch(problems, data, out_host, precision, tol):
 
 @pytest.mark.gpu
 @pytest.mark.parametrize("precision,tol", [("fp32", 1e-5), ("bf16x3", 1e-5)])
-def test_512_uneven_problems_against_oracle(precision, tol):
+@pytest.mark.parametrize("buckets", [None, [0, 1, 2, 2], [2, 2, 2, 2]])
+def test_512_uneven_problems_against_oracle(precision, tol, buckets):
+    """Library defaults (one launch), every variant at once (three
+    launches) and the largest tile throughout."""
     import torch
-    print("grouped 512 problems", precision, flush=True)
+    print("grouped 512 problems", precision, buckets, flush=True)
     problems, data, arena, host = make_batch()
-    with mg.GroupedPlan(problems, precision) as plan:
+    with mg.GroupedPlan(problems, precision, bucket_configs=buckets) as plan:
         info = plan.info()
         assert info["tiles"] > 512 and info["workgroups"] > 0
         plan.launch()
