@@ -73,19 +73,22 @@ static int lowp_default(int64_t M, int64_t N) {
 
 int bf16x3_default_config(int64_t M, int64_t N, int64_t K) {
     // From measured sweeps on MI355X (1024^3 to 8192^3, odd and rectangular
-    // shapes, all four transposes).  Pre-packing costs one extra read of A
-    // and B and a write of their two halves: repaid by the pipelined packed
-    // 256x256 tile (4 x 16-k stages) once both M and N reach ~4.5k, while
-    // the in-staging 256x256 tile is faster on a chip's worth of smaller
-    // tiles.  Below that, the tile count decides: in-staging 128x128 while
-    // it still gives every CU more than one tile, packed 128x128 (3 x 32-k
-    // stages) for about one round of deep products, in-staging 64x64 below.
+    // shapes, all four transposes).  Configuration 10 is the pipelined
+    // packed 256x256 tile (4 x 16-k stages), 11 the pipelined packed
+    // 128x128 tile.  Pre-packing costs one extra read of A and B and a write
+    // of their two halves: repaid once both M and N reach ~4.5k, where the
+    // 256x256 tile wins if its tiles fill the chip evenly and K is deep
+    // enough for its longer prologue, and the 128x128 tile otherwise.  Below that the in-staging 256x256 tile is fastest on
+    // a chip's worth of its tiles; then, by tile count, packed 128x128 for
+    // deep products, in-staging 128x128 for shallow ones, in-staging 64x64
+    // below one round of 128x128 tiles.
     const int64_t t256 = tile_count(M, N, 256, 256), t128 = tile_count(M, N, 128, 128);
     if (t256 >= NUM_CUS && (M < N ? M : N) >= 4608 && K >= 512)
-        return LOWP_INSTAGE_CONFIGS + 6;
+        return K >= 2048 && slot_share(M, N, 256, 256) >= 0.85 ? LOWP_INSTAGE_CONFIGS + 6
+                                                               : LOWP_INSTAGE_CONFIGS + 7;
     if (t256 >= 144) return 0;
+    if (t128 >= 192 && K >= 512) return LOWP_INSTAGE_CONFIGS + 7;
     if (t128 > NUM_CUS) return 1;
-    if (t128 >= 192 && K >= 512) return LOWP_INSTAGE_CONFIGS + 2;
     return 3;
 }
 
@@ -94,13 +97,13 @@ int f16s_default_config(int64_t M, int64_t N, int64_t K) {
     // write, and its direct-to-LDS main loop beats the in-staging one at
     // every measured size from 1024^3 up (1.15x there, up to 2.6x at 2048^3
     // to 3001^3): packed tiles unless K is too short to repay the pass.
-    // Between the packed 256x256 pipelined tile (893 TFLOP/s at 8192^3) and
-    // the packed 128x128 tile (825), the slot-share model picks; the larger
-    // tile's longer prologue needs K of 2048 or more.
+    // Between the pipelined packed 256x256 tile (893 TFLOP/s at 8192^3) and
+    // the pipelined packed 128x128 tile (about 850), the slot-share model
+    // picks; the larger tile's longer prologue needs K of 3072 or more.
     if (K < 512) return lowp_default(M, N);
     const double big = 893.0 * slot_share(M, N, 256, 256);
-    const double mid = 825.0 * slot_share(M, N, 128, 128);
-    return K >= 2048 && big > mid ? LOWP_INSTAGE_CONFIGS + 6 : LOWP_INSTAGE_CONFIGS + 2;
+    const double mid = 850.0 * slot_share(M, N, 128, 128);
+    return K >= 3072 && big > mid ? LOWP_INSTAGE_CONFIGS + 6 : LOWP_INSTAGE_CONFIGS + 7;
 }
 
 }  // namespace mgemm

@@ -132,7 +132,9 @@ using PKCfg4 = CfgPK<256, 128, 2, 2, 3, 16>;   // 4 waves of 128x64, 3 stages of
 using PKCfg5 = CfgPK<128, 256, 2, 2, 3, 16>;   // 4 waves of 64x128, 3 stages of 16 k
 // As 1 with fragment double buffering (tile_packed_pp).
 using PKCfg6 = CfgPK<256, 256, 2, 4, 4, 16, 2, true>;
-constexpr int PACKED_CONFIGS = 7;
+// As 2 in 4 x 16-k stages with fragment double buffering (64 KB BF16x3).
+using PKCfg7 = CfgPK<128, 128, 2, 2, 4, 16, 2, true>;
+constexpr int PACKED_CONFIGS = 8;
 
 // Calls f(Cfg{}) for configuration `cfg` (0 <= cfg < PACKED_CONFIGS).
 template <class Fn>
@@ -144,7 +146,8 @@ static auto with_packed_cfg(int cfg, Fn&& f) {
         case 3: return f(PKCfg3{});
         case 4: return f(PKCfg4{});
         case 5: return f(PKCfg5{});
-        default: return f(PKCfg6{});
+        case 6: return f(PKCfg6{});
+        default: return f(PKCfg7{});
     }
 }
 
