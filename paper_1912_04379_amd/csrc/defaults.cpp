@@ -59,6 +59,21 @@ int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
             best = c.cfg;
         }
     }
+    // Configuration 10: 256x256 tiles in whole rounds and 128x128 quarters
+    // for a part-filled last round.  The tail of r tiles takes about a
+    // quarter of a round per ceil(4r / CUs) quarters on a CU; 4% is lost to
+    // the second launch and the smaller tile (measured 143, 136 and 127
+    // TFLOP/s at 6144^3, 7168^3 and 5120^3).
+    if (K >= 4096) {
+        const int64_t t = tile_count(M, N, 256, 256), tail = t % NUM_CUS;
+        if (tail > 0) {
+            const double rounds = (double)(t - tail) / NUM_CUS +
+                                  0.25 * (double)((4 * tail + NUM_CUS - 1) / NUM_CUS);
+            const double pad = (double)M * (double)N / ((double)t * 256.0 * 256.0);
+            const double score = 148.5 * 0.96 * pad * ((double)t / NUM_CUS) / rounds;
+            if (score > best_score) best = 10;
+        }
+    }
     return best;
 }
 

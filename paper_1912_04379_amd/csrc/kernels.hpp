@@ -21,6 +21,11 @@ hipError_t launch_f32(int cfg, bool transA, bool transB, const GemmDesc& d,
 // FP32 small-product kernel (16 x 16 tiles, k split over 4 waves); needs
 // buffer_path_ok(d).
 hipError_t launch_small(bool transA, bool transB, const GemmDesc& d, hipStream_t stream);
+// FP32 configuration 10: 256 x 256 x 32 tiles in whole rounds of one per
+// CU (`cus` CUs), 128 x 128 tiles in the tail; needs buffer_path_ok(d).
+constexpr int F32_TAIL_CONFIG = 10;
+hipError_t launch_f32_tail(bool transA, bool transB, const GemmDesc& d, int cus,
+                           hipStream_t stream);
 
 // BF16x3 split path.
 int bf16x3_config_count();

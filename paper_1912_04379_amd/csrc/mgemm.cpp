@@ -116,6 +116,21 @@ int check_device(int* out_dev) {
 // so the next call would map it again: up to a few tenths of a millisecond
 // for the hundreds of megabytes that packed 8192^3 operands take.)
 // ---------------------------------------------------------------------------
+// Compute units of a device (cached; 0 if unknown).
+static std::atomic<int> g_cus[64];
+
+static int device_cus(int dev) {
+    if (dev < 0 || dev >= 64) return 0;
+    int n = g_cus[dev].load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    g_cus[dev].store(n, std::memory_order_relaxed);
+    return n;
+}
+
 static std::mutex g_pool_mu;
 static hipMemPool_t g_pools[64] = {};
 
@@ -202,6 +217,12 @@ static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K,
         return e == hipSuccess ? MGEMM_OK : hip_fail(e, "scale kernel launch");
     }
     int cfg = config >= 0 ? config : default_config(precision, ta, tb, M, N, K);
+    if (precision == MGEMM_PREC_FP32 && cfg == F32_TAIL_CONFIG) {
+        // The 64-bit address path has no split tail: 128 x 128 tiles.
+        e = buffer_path_ok(d) ? launch_f32_tail(ta, tb, d, device_cus(dev), s)
+                              : launch_f32(0, ta, tb, d, s);
+        return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
+    }
     if (precision == MGEMM_PREC_FP32) {
         e = launch_f32(cfg, ta, tb, d, s);
         return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");

@@ -55,10 +55,82 @@ using F32Cfg8 = CfgF32<256, 256, 32, 2, 4, 2>;
 template <class Cfg>
 static TileConfigInfo info_of() { return {Cfg::BM, Cfg::BN, Cfg::BK, Cfg::NT}; }
 
-// Configuration 9 is the small-product kernel (sgemm_small.hip).
+// ---------------------------------------------------------------------------
+// Configuration 10: 256 x 256 x 32 tiles in whole rounds, 128 x 128 tiles in
+// the tail.  With one 256 x 256 work-group per CU, T tiles take
+// ceil(T / CUs) rounds, and a last round of r < CUs tiles leaves the other
+// CUs idle for a whole tile's time.  Here the whole rounds run as usual and
+// the r tail tiles are computed as 128 x 128 quarters (configuration 0's
+// tile, several work-groups per CU), about a quarter of a round's time when
+// r is at most a third of the CUs and no more than half of it up to r ~
+// 0.6 CUs.  Ordinary tiles throughout: no workspace, no atomics.
+// ---------------------------------------------------------------------------
+using BigCfg = F32Cfg8;
+using TailCfg = F32Cfg0;
+
+template <class Cfg, bool AK, bool BKC>
+__global__ __launch_bounds__(Cfg::NT, Cfg::WPE) void sgemm_f32_tail_kernel(GemmDesc d,
+                                                                         uint32_t tiles_m,
+                                                                         uint32_t tiles_n,
+                                                                         uint32_t first_tile) {
+    constexpr int R = BigCfg::BM / Cfg::BM;
+    static_assert(R * Cfg::BM == BigCfg::BM && R * Cfg::BN == BigCfg::BN, "quarters");
+    __shared__ __attribute__((aligned(16))) float smem[Cfg::SMEM_FLOATS];
+    const uint32_t w = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t t = w / (R * R), q = w % (R * R);
+    uint32_t tm, tn;
+    grouped_tile<8>(first_tile + t, tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = (int64_t)tm * BigCfg::BM + (int64_t)(q % R) * Cfg::BM;
+    const int64_t n0 = (int64_t)tn * BigCfg::BN + (int64_t)(q / R) * Cfg::BN;
+    if (m0 >= d.M || n0 >= d.N) return;   // a quarter past the edge of C
+    tile_f32<Cfg, AK, BKC, true>(d, m0, n0, smem);
+}
+
+hipError_t launch_f32_tail(bool ta, bool tb, const GemmDesc& d, int cus, hipStream_t s) {
+    if (!buffer_path_ok(d) || cus < 1) return hipErrorInvalidValue;
+    const int64_t tiles_m = (d.M + BigCfg::BM - 1) / BigCfg::BM;
+    const int64_t tiles_n = (d.N + BigCfg::BN - 1) / BigCfg::BN;
+    const int64_t tiles = tiles_m * tiles_n;
+    constexpr int64_t R2 = (BigCfg::BM / TailCfg::BM) * (BigCfg::BN / TailCfg::BN);
+    if (tiles * R2 > 0xffffffffLL) return hipErrorInvalidValue;
+    const int64_t tail = tiles % cus, whole = tiles - tail;
+    const uint32_t tm = (uint32_t)tiles_m, tn = (uint32_t)tiles_n;
+    // Whole rounds: the ordinary kernel over the first `whole` tiles of the
+    // rasterised order (its grid size bounds the tile ids it takes).
+    if (whole > 0) {
+        using Cfg = BigCfg;
+        const dim3 grid((uint32_t)whole), block(Cfg::NT);
+        if (!ta && !tb)
+            hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, false, true, true>), grid, block, 0, s, d, tm, tn);
+        else if (!ta && tb)
+            hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, false, false, true>), grid, block, 0, s, d, tm, tn);
+        else if (ta && !tb)
+            hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, true, true, true>), grid, block, 0, s, d, tm, tn);
+        else
+            hipLaunchKernelGGL((sgemm_f32_kernel<Cfg, true, false, true>), grid, block, 0, s, d, tm, tn);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    if (tail == 0) return hipSuccess;
+    using Cfg = TailCfg;
+    const dim3 grid((uint32_t)(tail * R2)), block(Cfg::NT);
+    const uint32_t first = (uint32_t)whole;
+    if (!ta && !tb)
+        hipLaunchKernelGGL((sgemm_f32_tail_kernel<Cfg, false, true>), grid, block, Cfg::PAD_BYTES, s, d, tm, tn, first);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((sgemm_f32_tail_kernel<Cfg, false, false>), grid, block, Cfg::PAD_BYTES, s, d, tm, tn, first);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((sgemm_f32_tail_kernel<Cfg, true, true>), grid, block, Cfg::PAD_BYTES, s, d, tm, tn, first);
+    else
+        hipLaunchKernelGGL((sgemm_f32_tail_kernel<Cfg, true, false>), grid, block, Cfg::PAD_BYTES, s, d, tm, tn, first);
+    return hipGetLastError();
+}
+
+// Configuration 9 is the small-product kernel (sgemm_small.hip);
+// configuration 10 the 256 x 256 x 32 tile with a 128 x 128 tail (above).
 constexpr int F32_SMALL_CONFIG = 9;
 
-int f32_config_count() { return 10; }
+int f32_config_count() { return 11; }
 
 TileConfigInfo f32_config_info(int cfg) {
     switch (cfg) {
@@ -72,6 +144,7 @@ TileConfigInfo f32_config_info(int cfg) {
         case 7: return info_of<F32Cfg7>();
         case 8: return info_of<F32Cfg8>();
         case F32_SMALL_CONFIG: return {16, 16, 16, 256};
+        case F32_TAIL_CONFIG: return info_of<BigCfg>();
         default: return {0, 0, 0, 0};
     }
 }
@@ -94,7 +167,8 @@ hipError_t launch_f32(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t 
         case 6: return launch_cfg<F32Cfg6, true>(ta, tb, d, s);
         case 7: return launch_cfg<F32Cfg7, true>(ta, tb, d, s);
         case 8: return launch_cfg<F32Cfg8, true>(ta, tb, d, s);
-        default: return launch_small(ta, tb, d, s);
+        case F32_SMALL_CONFIG: return launch_small(ta, tb, d, s);
+        default: return hipErrorInvalidValue;   // configuration 10: launch_f32_tail
     }
 }
 

@@ -48,7 +48,7 @@ def test_ragged_shapes(ta, tb, shape):
     full_check(c, run(c))
 
 
-@pytest.mark.parametrize("cfg", range(10))
+@pytest.mark.parametrize("cfg", range(11))
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_every_config(cfg, ta, tb):
     c = synth.sgemm_case(3, ta, tb, 300, 270, 77, alpha=1.5, beta=-0.5, pad=3)
@@ -68,7 +68,30 @@ def test_small_product_kernel(ta, tb, shape):
     full_check(c, run(c, config=9))
 
 
-@pytest.mark.parametrize("cfg", [-1, 1, 5, 8, 9])
+@pytest.mark.parametrize("ta,tb", TRANS)
+@pytest.mark.parametrize("shape", [(600, 520, 333), (300, 700, 7), (257, 513, 1000)])
+def test_big_tiles_with_small_tile_tail_full(ta, tb, shape):
+    """Configuration 10 with fewer 256 x 256 tiles than CUs: every tile is
+    the tail, computed as 128 x 128 quarters (those past the edge of C are
+    skipped)."""
+    M, N, K = shape
+    c = synth.sgemm_case(23, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=3)
+    log("f32 big+tail %s %s%s" % (shape, ta, tb))
+    full_check(c, run(c, config=10))
+
+
+@pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "T")])
+def test_big_tiles_whole_round_and_tail_sampled(ta, tb):
+    """4097^3: 289 tiles of 256 x 256, one whole round on 256 CUs and a tail
+    of 33 tiles as 128 x 128 quarters; checked on sampled entries, padding
+    and finiteness everywhere."""
+    n = 4097
+    c = synth.sgemm_case(24, ta, tb, n, n, n, alpha=1.5, beta=-0.5, pad=16)
+    log("f32 big+tail 4097 %s%s" % (ta, tb))
+    sampled_check(c, run(c, config=10))
+
+
+@pytest.mark.parametrize("cfg", [-1, 1, 5, 8, 9, 10])
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_leading_dimension_beyond_32bit_offsets(cfg, ta, tb):
     """ldc above 2**21 floats: the 64-bit address path runs, whichever
