@@ -112,13 +112,14 @@ int f16s_default_config(int64_t M, int64_t N, int64_t K) {
     // write, and its direct-to-LDS main loop beats the in-staging one at
     // every measured size from 1024^3 up (1.15x there, up to 2.6x at 2048^3
     // to 3001^3): packed tiles unless K is too short to repay the pass.
-    // Between the pipelined packed 256x256 tile (893 TFLOP/s at 8192^3) and
-    // the pipelined packed 128x128 tile (about 850), the slot-share model
-    // picks; the larger tile's longer prologue needs K of 3072 or more.
+    // Between the pipelined packed 256x256 tile in 32-deep stages (906
+    // TFLOP/s at 8192^3) and the pipelined packed 128x128 tile (about 850),
+    // the slot-share model picks; the larger tile's longer prologue needs K
+    // of 3072 or more.
     if (K < 512) return lowp_default(M, N);
-    const double big = 893.0 * slot_share(M, N, 256, 256);
+    const double big = 906.0 * slot_share(M, N, 256, 256);
     const double mid = 850.0 * slot_share(M, N, 128, 128);
-    return K >= 3072 && big > mid ? LOWP_INSTAGE_CONFIGS + 6 : LOWP_INSTAGE_CONFIGS + 7;
+    return K >= 3072 && big > mid ? LOWP_INSTAGE_CONFIGS + 8 : LOWP_INSTAGE_CONFIGS + 7;
 }
 
 }  // namespace mgemm

@@ -134,7 +134,9 @@ using PKCfg5 = CfgPK<128, 256, 2, 2, 3, 16>;   // 4 waves of 64x128, 3 stages of
 using PKCfg6 = CfgPK<256, 256, 2, 4, 4, 16, 2, true>;
 // As 2 in 4 x 16-k stages with fragment double buffering (64 KB BF16x3).
 using PKCfg7 = CfgPK<128, 128, 2, 2, 4, 16, 2, true>;
-constexpr int PACKED_CONFIGS = 8;
+// FP16 only: as 6 in 4 x 32-k stages (128 KB), half the barriers per MFMA.
+using PKCfg8 = CfgPK<256, 256, 2, 4, 4, 32, 2, true>;
+constexpr int PACKED_CONFIGS = 9;
 
 // Calls f(Cfg{}) for configuration `cfg` (0 <= cfg < PACKED_CONFIGS).
 template <class Fn>
@@ -147,7 +149,8 @@ static auto with_packed_cfg(int cfg, Fn&& f) {
         case 4: return f(PKCfg4{});
         case 5: return f(PKCfg5{});
         case 6: return f(PKCfg6{});
-        default: return f(PKCfg7{});
+        case 7: return f(PKCfg7{});
+        default: return f(PKCfg8{});
     }
 }
 

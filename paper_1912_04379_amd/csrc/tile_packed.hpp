@@ -273,14 +273,15 @@ __device__ inline void tile_packed(const GemmDesc& d, const PackedArgs& pk, int6
 //   3. issue the loads of stage kt+NS into that buffer;
 //   4. read stage kt+1's fragments into the other register set, overlapped
 //      with the rest of stage kt's MFMAs.
-// Every accumulator still takes lo*hi, hi*lo, hi*hi per 16-deep k step in k
-// order, so results equal the other packed configurations bitwise.
+// A stage is one or two 16-deep k steps (KW 16 or 32); every accumulator
+// still takes lo*hi, hi*lo, hi*hi per 16-deep k step in k order, so results
+// equal the other packed configurations bitwise.
 // ---------------------------------------------------------------------------
 template <class Cfg, Form F>
 struct PPFrags {
-    static constexpr int FM = Cfg::FM, FN = Cfg::FN;
-    bf16x8 ah[FM], al[FM], bh[FN], bl[FN];     // BF16x3
-    f16x8 aq[FM], bq[FN];                       // FP16
+    static constexpr int FM = Cfg::FM, FN = Cfg::FN, KS = Cfg::KW / 16;
+    bf16x8 ah[KS][FM], al[KS][FM], bh[KS][FN], bl[KS][FN];     // BF16x3
+    f16x8 aq[KS][FM], bq[KS][FN];                               // FP16
 };
 
 template <class Cfg, Form F, bool BUF>
@@ -289,7 +290,8 @@ __device__ inline void tile_packed_pp(const GemmDesc& d, const PackedArgs& pk, i
     using St = PackedStage<Cfg, F>;
     constexpr int BM = Cfg::BM, NS = Cfg::NS, FM = Cfg::FM, FN = Cfg::FN;
     constexpr int PW = St::PER_WAVE, KW = Cfg::KW, RB = Cfg::ROW_BYTES;
-    static_assert(KW == 16, "one 16-deep MFMA step per stage");
+    static_assert(KW == 16 || KW == 32, "one or two 16-deep MFMA steps per stage");
+    constexpr int KS = KW / 16;
     static_assert(NS >= 3, "at least three stages");
     using Epi = typename std::conditional<BUF, EpilogueB, EpilogueG>::type;
     const int tid = threadIdx.x, lane = tid & 63;
@@ -308,23 +310,27 @@ __device__ inline void tile_packed_pp(const GemmDesc& d, const PackedArgs& pk, i
         const char* Al = Ah + St::ARR;
         const char* Bl = Al + BM * RB;
 #pragma unroll
-        for (int i = 0; i < FM; ++i) {
-            const int o = co(wm + 32 * i + l32, h);
-            if constexpr (F == Form::BF16X3) {
-                f.ah[i] = *reinterpret_cast<const bf16x8*>(Ah + o);
-                f.al[i] = *reinterpret_cast<const bf16x8*>(Al + o);
-            } else {
-                f.aq[i] = *reinterpret_cast<const f16x8*>(Ah + o);
-            }
-        }
+        for (int ks = 0; ks < KS; ++ks) {
+            const int c = 2 * ks + h;
 #pragma unroll
-        for (int j = 0; j < FN; ++j) {
-            const int o = co(wn + 32 * j + l32, h);
-            if constexpr (F == Form::BF16X3) {
-                f.bh[j] = *reinterpret_cast<const bf16x8*>(Bh + o);
-                f.bl[j] = *reinterpret_cast<const bf16x8*>(Bl + o);
-            } else {
-                f.bq[j] = *reinterpret_cast<const f16x8*>(Bh + o);
+            for (int i = 0; i < FM; ++i) {
+                const int o = co(wm + 32 * i + l32, c);
+                if constexpr (F == Form::BF16X3) {
+                    f.ah[ks][i] = *reinterpret_cast<const bf16x8*>(Ah + o);
+                    f.al[ks][i] = *reinterpret_cast<const bf16x8*>(Al + o);
+                } else {
+                    f.aq[ks][i] = *reinterpret_cast<const f16x8*>(Ah + o);
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < FN; ++j) {
+                const int o = co(wn + 32 * j + l32, c);
+                if constexpr (F == Form::BF16X3) {
+                    f.bh[ks][j] = *reinterpret_cast<const bf16x8*>(Bh + o);
+                    f.bl[ks][j] = *reinterpret_cast<const bf16x8*>(Bl + o);
+                } else {
+                    f.bq[ks][j] = *reinterpret_cast<const f16x8*>(Bh + o);
+                }
             }
         }
     };
@@ -336,23 +342,26 @@ __device__ inline void tile_packed_pp(const GemmDesc& d, const PackedArgs& pk, i
         for (int j = 0; j < FN; ++j)
             acc[i][j] = f32x16{};
 
-    // MFMA number q (0 .. NQ-1) of one k step: term-major over (term, i, j).
+    // MFMA number q (0 .. NQ-1) of one stage: k-step-major, then term-major
+    // over (term, i, j), so every accumulator sees its k steps in order.
     constexpr int TERMS = F == Form::BF16X3 ? 3 : 1;
-    constexpr int NQ = TERMS * FM * FN;
+    constexpr int PER_KS = TERMS * FM * FN;
+    constexpr int NQ = KS * PER_KS;
     auto mfma_range = [&](const PPFrags<Cfg, F>& f, auto lo_c, auto hi_c) {
         constexpr int LO = decltype(lo_c)::value, HI = decltype(hi_c)::value;
 #pragma unroll
         for (int q = LO; q < HI; ++q) {
-            const int term = q / (FM * FN), i = (q / FN) % FM, j = q % FN;
+            const int ks = q / PER_KS, r = q % PER_KS;
+            const int term = r / (FM * FN), i = (r / FN) % FM, j = r % FN;
             if constexpr (F == Form::BF16X3) {
                 if (term == 0)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bl[j], f.ah[i], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bl[ks][j], f.ah[ks][i], acc[i][j], 0, 0, 0);
                 else if (term == 1)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bh[j], f.al[i], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bh[ks][j], f.al[ks][i], acc[i][j], 0, 0, 0);
                 else
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bh[j], f.ah[i], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.bh[ks][j], f.ah[ks][i], acc[i][j], 0, 0, 0);
             } else {
-                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.bq[j], f.aq[i], acc[i][j], 0, 0, 0);
+                acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(f.bq[ks][j], f.aq[ks][i], acc[i][j], 0, 0, 0);
             }
         }
     };

@@ -87,7 +87,7 @@ def test_unsupported_precision_and_config():
     assert call(config=99) == _lib.ERR_UNSUPPORTED
     assert mg.config_count("fp32") == 11
     # test_precision enumerates the 16-bit configurations by this count
-    assert mg.config_count("bf16x3") == 12 and mg.config_count("fp16s") == 12
+    assert mg.config_count("bf16x3") == 13 and mg.config_count("fp16s") == 13
     for prec in ("fp32", "bf16x3", "fp16s"):
         for cfg in range(mg.config_count(prec)):
             info = mg.config_info(prec, cfg)

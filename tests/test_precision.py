@@ -18,7 +18,7 @@ from gpu_util import log, logical_c, padding_untouched, run, sampled_check, wide
 
 # Tile configurations of the 16-bit forms: 0..3 split while staging, the
 # rest stream pre-packed operands (test_abi checks the count).
-N_CONFIGS = 12
+N_CONFIGS = 13
 PACKED_CONFIGS = list(range(4, N_CONFIGS))
 
 pytestmark = pytest.mark.gpu
@@ -178,7 +178,7 @@ def test_packed_equals_in_staging_bitwise(prec, ta, tb):
     check_form(c, prec, b)
     # Other packed tiles, stage depths and loop schedules keep the order of
     # the MFMAs into every accumulator.
-    for cfg in (5, 6, 10, 11):
+    for cfg in (5, 6, 10, 11, 12):
         assert np.array_equal(a, run(c, precision=prec, config=cfg)), cfg
 
 
