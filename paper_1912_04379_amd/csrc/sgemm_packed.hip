@@ -15,8 +15,9 @@ namespace mgemm {
 // threads read one 128-byte row segment, 16 bytes each); P-contiguous
 // sources number them p-fastest (each load reads 32 consecutive rows of one
 // column).  A region lands in one 32 x 32 block (KW = 32) or two 32 x 16
-// blocks (KW = 16), each row-major with k contiguous.  Elements outside
-// P x K are written as zeros.  BUF: raw buffer loads rebased to each
+// blocks (KW = 16), each row-major with k contiguous; the group's blocks
+// are one contiguous range per array, which P-contiguous sources assemble
+// in LDS and write in order.  Elements outside P x K are written as zeros.  BUF: raw buffer loads rebased to each
 // group's first element (elements outside P x K get an out-of-range offset
 // and read 0); otherwise predicated 64-bit loads (leading dimensions above
 // the buffer limit).
@@ -30,6 +31,9 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ X, 
                                                    char* __restrict__ hi, char* __restrict__ lo,
                                                    const int* __restrict__ expo) {
     constexpr int RB = 2 * KW;
+    constexpr int GROUP_BYTES = 32 * PACK_KG * 2;   // one array's share of a group
+    __shared__ __attribute__((aligned(16))) char stage_hi[KC ? 16 : GROUP_BYTES];
+    __shared__ __attribute__((aligned(16))) char stage_lo[KC || F != Form::BF16X3 ? 16 : GROUP_BYTES];
     const int t = threadIdx.x;
     const int r = KC ? t >> 3 : t & 31;
     const int kq = KC ? t & 7 : t >> 5;
@@ -67,20 +71,55 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ X, 
                     v[j][e] = x;
                 }
         }
+        if constexpr (KC) {
+            // Eight threads cover one 64-byte row segment: stores are
+            // contiguous as they are.
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t k = kg0 + 32 * j + 4 * kq;
-            const int64_t blk = k / KW;
-            if (blk >= kb) continue;                   // past the last KW block
-            const int64_t off = ((pb * kb + blk) * 32 + r) * RB + (k % KW) * 2;
-            if constexpr (F == Form::BF16X3) {
-                u32x2 h2, l2;
-                split_bf16x4(v[j], h2, l2);
-                *reinterpret_cast<u32x2*>(hi + off) = h2;
-                *reinterpret_cast<u32x2*>(lo + off) = l2;
-            } else {
-                *reinterpret_cast<u32x2*>(hi + off) = scale_f16x4(v[j], expo[pb]);
+            for (int j = 0; j < 4; ++j) {
+                const int64_t k = kg0 + 32 * j + 4 * kq;
+                const int64_t blk = k / KW;
+                if (blk >= kb) continue;               // past the last KW block
+                const int64_t off = ((pb * kb + blk) * 32 + r) * RB + (k % KW) * 2;
+                if constexpr (F == Form::BF16X3) {
+                    u32x2 h2, l2;
+                    split_bf16x4(v[j], h2, l2);
+                    *reinterpret_cast<u32x2*>(hi + off) = h2;
+                    *reinterpret_cast<u32x2*>(lo + off) = l2;
+                } else {
+                    *reinterpret_cast<u32x2*>(hi + off) = scale_f16x4(v[j], expo[pb]);
+                }
             }
+        } else {
+            // Threads run along rows here, so their 8-byte pieces would be
+            // scattered one per row; the group's blocks (one contiguous
+            // GROUP_BYTES range per array) are assembled in LDS first and
+            // then written with 16-byte stores that walk it in order.
+            const int64_t blk0 = kg0 / KW;
+            const int live = (int)((kb - blk0) < PACK_KG / KW ? (kb - blk0) : PACK_KG / KW) * 32 * RB;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int kk = 32 * j + 4 * kq;
+                const int off = ((kk / KW) * 32 + r) * RB + (kk % KW) * 2;
+                if constexpr (F == Form::BF16X3) {
+                    u32x2 h2, l2;
+                    split_bf16x4(v[j], h2, l2);
+                    *reinterpret_cast<u32x2*>(stage_hi + off) = h2;
+                    *reinterpret_cast<u32x2*>(stage_lo + off) = l2;
+                } else {
+                    *reinterpret_cast<u32x2*>(stage_hi + off) = scale_f16x4(v[j], expo[pb]);
+                }
+            }
+            __syncthreads();
+            const int64_t base = (pb * kb + blk0) * 32 * RB;
+#pragma unroll
+            for (int q = 0; q < GROUP_BYTES / (256 * 16); ++q) {
+                const int o = (q * 256 + t) * 16;
+                if (o >= live) continue;               // past the last KW block
+                *reinterpret_cast<u32x4*>(hi + base + o) = *reinterpret_cast<const u32x4*>(stage_hi + o);
+                if constexpr (F == Form::BF16X3)
+                    *reinterpret_cast<u32x4*>(lo + base + o) = *reinterpret_cast<const u32x4*>(stage_lo + o);
+            }
+            __syncthreads();                           // the stage is reused
         }
     }
 }
