@@ -22,21 +22,22 @@ static double slot_share(int64_t M, int64_t N, int bm, int bn) {
 }
 
 int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
-    // Candidates with their steady rates measured on MI355X (TFLOP/s, large
-    // square products): 256x256 with 32-deep slabs (only for K >= 4096: its
-    // longer prologue and epilogue cost more on shorter products), 256x128
-    // at 2 waves per SIMD (128x256 for TT, whose operand layouts favour it),
-    // 128x128, 64x64.  Each is scored by the slot-share model, less 10%
-    // while it has fewer tiles than it needs resident per CU to hide its
-    // load latency.  Against measured sweeps (1024^3 to 8192^3, odd and
-    // rectangular shapes, all four transposes) the pick is within 4% of the
-    // fastest of the configurations or is the fastest.
     // Few 64x64 tiles and a k range worth splitting: the small-product
     // kernel (16x16 tiles, k split over 4 waves).  Measured kernel times:
     // 5.7 us vs 8.9 us for 64x64 tiles at 256^3, 34 us vs 89 us at
     // 256 x 256 x 4096; at 64^3 its fixed cost makes it 1.5 us slower, and
     // from 64 tiles of 64x64 up (512^3: 19 us vs 15 us) it loses.
     if (tile_count(M, N, 64, 64) <= 32 && K >= 128) return 9;
+
+    // Otherwise, candidates with their steady rates measured on MI355X
+    // (TFLOP/s, large square products): 256x256 with 32-deep slabs (only
+    // for K >= 4096: its longer prologue and epilogue cost more on shorter
+    // products), 256x128 at 2 waves per SIMD (128x256 for TT, whose operand
+    // layouts favour it), 128x128, 64x64.  Each is scored by the slot-share
+    // model, less 10% while it has fewer tiles than it needs resident per CU
+    // to hide its load latency.  Against measured sweeps (1024^3 to 8192^3,
+    // odd and rectangular shapes, all four transposes) the pick is the
+    // fastest configuration or within 6% of it.
     struct Cand {
         int cfg, bm, bn;
         double rate;
