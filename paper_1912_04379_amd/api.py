@@ -5,11 +5,16 @@ from ._lib import PRECISIONS, check, lib
 
 
 def stream_handle(stream=None):
-    """hipStream_t of a torch stream (None: torch's current stream)."""
+    """hipStream_t of a torch stream (None: torch's current stream, read
+    through torch's raw-stream query where it has one: constructing a Stream
+    object costs more than the rest of a small call's host work)."""
     if isinstance(stream, int):
         return stream
     import torch
     if stream is None:
+        raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+        if raw is not None:
+            return raw(torch.cuda.current_device())
         stream = torch.cuda.current_stream()
     return stream.cuda_stream
 
@@ -44,6 +49,8 @@ def _check_extent(t, name, rows, cols, ld):
     if t is None or isinstance(t, int) or rows <= 0 or cols <= 0 or ld < rows:
         return          # nothing referenced, or the library rejects ld
     need = 4 * ((cols - 1) * ld + rows)
+    if need <= 4 * t.numel() and t.is_contiguous():
+        return          # within the tensor's own elements (the common case, no storage query)
     storage = t.untyped_storage()
     lo, hi = storage.data_ptr(), storage.data_ptr() + storage.nbytes()
     if t.data_ptr() < lo or t.data_ptr() + need > hi:

@@ -81,15 +81,22 @@ bool overlaps(int ta, int tb, int64_t M, int64_t N, int64_t K, float alpha, cons
 // 1 ok, 2 wrong architecture.
 static std::atomic<int> g_dev_state[64];
 
+static std::atomic<int> g_device_count{0};
+
 int check_device(int* out_dev) {
-    int count = 0;
-    hipError_t e = hipGetDeviceCount(&count);
-    if (e != hipSuccess || count <= 0) {
-        (void)hipGetLastError();
-        return fail(MGEMM_ERR_NO_DEVICE, "no HIP device is visible");
+    // The device count does not change within a process: query it until a
+    // device is seen, then keep it.
+    if (g_device_count.load(std::memory_order_relaxed) <= 0) {
+        int count = 0;
+        hipError_t e = hipGetDeviceCount(&count);
+        if (e != hipSuccess || count <= 0) {
+            (void)hipGetLastError();
+            return fail(MGEMM_ERR_NO_DEVICE, "no HIP device is visible");
+        }
+        g_device_count.store(count, std::memory_order_relaxed);
     }
     int dev = 0;
-    e = hipGetDevice(&dev);
+    hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
     if (out_dev) *out_dev = dev;
     int state = dev < 64 ? g_dev_state[dev].load(std::memory_order_relaxed) : 0;

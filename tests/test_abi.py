@@ -180,14 +180,21 @@ class _FakeTensor:
     """Enough of a device tensor for the binding's argument checks."""
     is_cuda = True
 
-    def __init__(self, ptr, nbytes, offset=0):
+    def __init__(self, ptr, nbytes, offset=0, contiguous=False):
         import torch
         self.dtype = torch.float32
         self._st = _FakeStorage(ptr, nbytes)
         self._off = offset
+        self._contiguous = contiguous
 
     def untyped_storage(self):
         return self._st
+
+    def numel(self):
+        return max(0, (self._st.n - self._off) // 4)
+
+    def is_contiguous(self):
+        return self._contiguous
 
     def data_ptr(self):
         return self._st.ptr + self._off
@@ -206,6 +213,13 @@ def test_tensor_extent_is_checked_before_any_call():
     with pytest.raises(ValueError):        # C as a view starting 1 KB in
         check_operands("N", "T", 64, 64, 64, 1.0, ok, 64, ok, 64,
                        _FakeTensor(FC, 4 * 64 * 64, offset=1024), 64)
+    # A contiguous tensor whose own elements hold the array needs no storage
+    # query; one whose elements fall short is still checked against its storage.
+    check_operands("N", "N", 64, 64, 64, 1.0, _FakeTensor(FA, 4 * 64 * 64, contiguous=True), 64,
+                   ok, 64, ok, 64)
+    with pytest.raises(ValueError):
+        check_operands("N", "N", 64, 64, 64, 1.0,
+                       _FakeTensor(FA, 4 * 64 * 64 - 4, contiguous=True), 64, ok, 64, ok, 64)
     # alpha == 0: A and B are not referenced, so an empty A is fine
     check_operands("N", "N", 64, 64, 64, 0.0, _FakeTensor(FA, 0), 64, _FakeTensor(FB, 0), 64,
                    _FakeTensor(FC, 4 * 64 * 64), 64)
