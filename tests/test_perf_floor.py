@@ -9,7 +9,7 @@ from gpu_util import log
 pytestmark = pytest.mark.gpu
 
 
-def time_ms(fn, reps=10, warmup=3):
+def time_ms(fn, reps=20, warmup=10):
     import torch
     for _ in range(warmup):
         fn()
