@@ -38,7 +38,7 @@ namespace mgemm {
 // ---- tile variants of the persistent kernel (all 256 threads) -------------
 using GF0 = CfgF32<64, 64, 16, 2, 2>;
 using GF1 = CfgF32<128, 128, 16, 2, 2>;
-using GF2 = CfgF32<128, 128, 32, 2, 2>;
+using GF2 = CfgF32<64, 64, 32, 2, 2>;   // 32-deep slabs: half the barriers per MFMA
 using GL0 = CfgLP<64, 64, 2, 2>;
 using GL1 = CfgLP<128, 128, 2, 2>;
 using GL2 = CfgLP<128, 64, 2, 2>;
@@ -69,8 +69,8 @@ constexpr int lp_lds() { return 2 * 2 * (Cfg::BM + Cfg::BN) * Cfg::ROW_BYTES; }
 
 // Default variant per size bucket (bucket = by max(M, N)): one variant for
 // every bucket, so an untuned batch is one launch (measured fastest on a
-// batch of 512 problems with M, N, K uniform on 16..512: FP32 64x64x16,
-// BF16x3 128x128).
+// batch of 512 problems with M, N, K uniform on 16..512: FP32 64x64, with
+// 16- and 32-deep slabs within 1% of each other; BF16x3 128x128).
 static const int DEFAULT_F32[NUM_BUCKETS] = {0, 0, 0, 0};
 static const int DEFAULT_LP[NUM_BUCKETS] = {1, 1, 1, 1};
 
