@@ -56,6 +56,17 @@ def test_every_config(cfg, ta, tb):
     full_check(c, run(c, config=cfg))
 
 
+@pytest.mark.parametrize("cfg", range(11))
+@pytest.mark.parametrize("K", [1, 17, 33])
+@pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "T")])
+def test_short_k_every_config(cfg, K, ta, tb):
+    """K shorter than one slab, one slab plus a ragged one, and so on, for
+    every configuration (slab depths 16 and 32)."""
+    c = synth.sgemm_case(27, ta, tb, 300, 270, K, alpha=1.5, beta=-0.5, pad=3)
+    log("f32 short K cfg %d K %d %s%s" % (cfg, K, ta, tb))
+    full_check(c, run(c, config=cfg))
+
+
 @pytest.mark.parametrize("ta,tb", TRANS)
 @pytest.mark.parametrize("shape", [(1, 1, 1), (17, 15, 3), (16, 16, 16), (33, 47, 17),
                                    (20, 40, 65), (100, 3, 129), (64, 64, 200), (48, 80, 1000)])
