@@ -292,6 +292,8 @@ def main():
                          "normwise_err": h["err"],
                          "mfma_frac": round(h["tflops"] / PEAK["fp16"], 4)}
 
+    if not args.no_forms:
+        line["wide_range_inputs"] = bench_wide_range(args, mg, torch, oracle, synth, n)
     line["small_256"] = bench_small(args, mg, torch)
     if not (args.no_vendor or args.no_forms):
         line["vendor_blas"] = bench_vendor(args, torch, n, alpha, beta)
@@ -385,6 +387,40 @@ def graph_us_per_call(fn, torch, stream, reps=100):
     g.replay()
     torch.cuda.synchronize()
     return round(1000 * timed(g.replay, 10, 2, stream) / reps, 2)
+
+
+def bench_wide_range(args, mg, torch, oracle, synth, n):
+    """The three paths on sign-random inputs of magnitude 2**U[-8, 8] (NN,
+    lda = rows + 16, alpha 1, beta 0): time and sampled normwise error, so
+    that the 16-bit forms' speedups are stated at equal error on inputs
+    spanning 16 binades."""
+    c = synth.sgemm_case(0, "N", "N", n, n, n, dist="loguni")
+    ld = c["lda"]
+    dev = torch.device("cuda:0")
+    A = torch.from_numpy(c["A"]).to(dev)
+    B = torch.from_numpy(c["B"]).to(dev)
+    C = torch.zeros(c["C"].size, dtype=torch.float32, device=dev)
+    rows, cols = synth.sample_entries(2, n, n, 2048)
+    ref = oracle.sgemm_entries("N", "N", n, n, n, 1.0, c["A"], ld, c["B"], ld, 0.0, c["C"], ld,
+                               rows, cols)
+    stream = torch.cuda.current_stream()
+    out = {"workload": "sgemm NN %d^3 lda=ldb=ldc=%d alpha=1 beta=0, sign-random 2**U[-8,8], "
+                       "seed 0" % (n, ld)}
+    for prec in ("fp32", "bf16x3", "fp16s"):
+        fn = lambda: mg.sgemm("N", "N", n, n, n, 1.0, A, ld, B, ld, 0.0, C, ld, precision=prec)
+        fn()
+        torch.cuda.synchronize()
+        got = C.view(n, ld)[torch.from_numpy(cols).to(dev), torch.from_numpy(rows).to(dev)]
+        err = oracle.normwise_rel_err(got.double().cpu().numpy(), ref)
+        ms = timed(fn, args.steps, args.warmup, stream)
+        out[prec] = {"ms": round(ms, 4), "tflops": round(2.0 * n ** 3 / ms / 1e9, 3),
+                     "normwise_err": err}
+        log("wide-range inputs %s: %.3f ms, sampled normwise error %.3e" % (prec, ms, err))
+    for prec in ("bf16x3", "fp16s"):
+        out[prec]["speedup_vs_fp32"] = round(out["fp32"]["ms"] / out[prec]["ms"], 3)
+    out["bf16x3"]["both_within_1e-5"] = bool(out["bf16x3"]["normwise_err"] <= 1e-5 and
+                                             out["fp32"]["normwise_err"] <= 1e-5)
+    return out
 
 
 def bench_vendor(args, torch, n, alpha, beta):
