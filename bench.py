@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-vendor", action="store_true",
                     help="skip the ROCm BLAS (torch.addmm) comparison")
+    ap.add_argument("--no-wide-range", action="store_true",
+                    help="skip the three paths on wide-range (2^U[-8,8]) inputs")
     ap.add_argument("--no-clock", action="store_true",
                     help="do not sample the engine clock with amd-smi")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -292,7 +294,7 @@ def main():
                          "normwise_err": h["err"],
                          "mfma_frac": round(h["tflops"] / PEAK["fp16"], 4)}
 
-    if not args.no_forms:
+    if not (args.no_forms or args.no_wide_range):
         line["wide_range_inputs"] = bench_wide_range(args, mg, torch, oracle, synth, n)
     line["small_256"] = bench_small(args, mg, torch)
     if not (args.no_vendor or args.no_forms):
