@@ -220,7 +220,9 @@ int mgemm_grouped_variant_info(int precision, int variant, int *bm, int *bn,
  * by timing the whole grouped launch on `stream` (best of `reps` timed
  * runs after one warm-up, HIP events): the defaults and each assignment of
  * one variant to every bucket are timed, then, from the fastest, each
- * bucket in turn tries every variant (two passes).  Writes 4 entries to
+ * bucket in turn tries every variant (two passes).  A change is kept only
+ * when it is more than 2% faster than the assignment it replaces, so near
+ * ties keep the earlier choice and repeated tunings agree.  Writes 4 entries to
  * bucket_configs and the best time in
  * milliseconds to *best_ms (may be NULL).  The problems are RUN: every C
  * is overwritten with unspecified values, so tune on scratch outputs or

@@ -560,6 +560,10 @@ int mgemm_grouped_tune(const mgemm_problem* problems, int64_t count, int precisi
     // assignments (one launch for the whole batch: no launch waits behind
     // another's last work-groups), then descend one bucket at a time, in two
     // passes so that an early bucket is revisited once the later ones moved.
+    // A change is taken only when it is faster by more than TUNE_MARGIN:
+    // assignments within timing noise of each other keep the earlier one, so
+    // the choice repeats from run to run.
+    constexpr float TUNE_MARGIN = 0.98f;
     float cur = 0.0f;
     int st = time_of(bucket_configs, cur);
     for (int v = 0; v < NUM_VARIANTS && st == MGEMM_OK; ++v) {
@@ -567,7 +571,7 @@ int mgemm_grouped_tune(const mgemm_problem* problems, int64_t count, int precisi
         for (int b = 0; b < NUM_BUCKETS; ++b) uni[b] = v;
         float t = 0.0f;
         st = time_of(uni, t);
-        if (st == MGEMM_OK && t < cur) {
+        if (st == MGEMM_OK && t < cur * TUNE_MARGIN) {
             cur = t;
             for (int b = 0; b < NUM_BUCKETS; ++b) bucket_configs[b] = v;
         }
@@ -582,7 +586,7 @@ int mgemm_grouped_tune(const mgemm_problem* problems, int64_t count, int precisi
                 bucket_configs[b] = v;
                 float t = 0.0f;
                 st = time_of(bucket_configs, t);
-                if (st == MGEMM_OK && t < cur) {
+                if (st == MGEMM_OK && t < cur * TUNE_MARGIN) {
                     cur = t;
                     best_v = v;
                 }
