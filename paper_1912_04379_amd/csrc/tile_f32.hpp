@@ -177,6 +177,11 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
         for (int c = 0; c + 2 < NC; ++c) {
             f[(c + 1) & 1].read(cur, cur + BM * S, wm, wn, l32, h, c + 1);
             f[c & 1].mfma(acc);
+            // Issue the next chunk's reads before this chunk's MFMAs, so that
+            // all of them hide the reads' latency (left alone, the scheduler
+            // sinks the reads to the last few MFMAs).
+            __builtin_amdgcn_sched_group_barrier(0x100, N_READ, 0);   // DS read
+            __builtin_amdgcn_sched_group_barrier(0x008, N_MFMA, 0);   // MFMA
         }
         if constexpr (kind == Step::LAST) {
             if constexpr (NC > 1) {
