@@ -57,6 +57,17 @@ def test_every_config(cfg, ta, tb):
 
 
 @pytest.mark.parametrize("cfg", range(11))
+@pytest.mark.parametrize("ta,tb", TRANS)
+def test_every_config_sizes_multiple_of_4(cfg, ta, tb):
+    """M and N multiples of 4 but of no tile edge, odd leading dimensions
+    (rows of A, B and C start at 4-byte but not 16-byte boundaries) and a
+    ragged K."""
+    c = synth.sgemm_case(31, ta, tb, 292, 268, 83, alpha=1.5, beta=-0.5, pad=3)
+    log("f32 sizes multiple of 4 cfg %d %s%s" % (cfg, ta, tb))
+    full_check(c, run(c, config=cfg))
+
+
+@pytest.mark.parametrize("cfg", range(11))
 @pytest.mark.parametrize("K", [1, 17, 33])
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "T")])
 def test_short_k_every_config(cfg, K, ta, tb):
