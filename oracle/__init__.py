@@ -17,6 +17,9 @@ Contents
   and the scaled product, evaluated in FP64 (not in the paper).
 * ``normwise_rel_err`` and ``elementwise_ratio``: error metrics.
 * ``dense_grads``: gradients of L = sum((X W) o G) for the dense layer.
+* ``mlp_forward`` / ``mlp_loss`` / ``mlp_grads`` / ``mlp_step``: one
+  plain-gradient-descent step of a multilayer perceptron, the application the
+  paper trains with its SGEMM (Section 4), in FP64 with numpy products.
 """
 import ctypes
 import os
@@ -344,3 +347,52 @@ def dense_loss(X, W, G):
     # X col-major is (I x B) ld I -> 'N'.
     Yt = dgemm("N", "N", no, nb, ni, 1.0, W.ravel(), no, X.ravel(), ni, 0.0, None, no)
     return float(np.sum(Yt.T * G))
+
+
+# ---------------------------------------------------------------------------
+# Multilayer perceptron (Section 4: a neural network trained with SGEMM as the
+# kernel).  The paper names no architecture, loss or update rule; this is the
+# reading used here: hidden layers H_l = tanh(H_{l-1} W_l), a linear output
+# layer, loss 0.5/B * ||H_L - T||_F^2 over a batch of B rows, and one step of
+# plain gradient descent W_l <- W_l - lr dL/dW_l.  Row-major arrays, FP64,
+# numpy products; nothing here is blocked or fused.
+# ---------------------------------------------------------------------------
+def mlp_forward(Ws, X):
+    """[H_0 = X, H_1, ..., H_L] in FP64."""
+    H = [np.asarray(X, dtype=np.float64)]
+    for l, W in enumerate(Ws):
+        Z = H[-1] @ np.asarray(W, dtype=np.float64)
+        H.append(np.tanh(Z) if l + 1 < len(Ws) else Z)
+    return H
+
+
+def mlp_loss(Ws, X, T):
+    """0.5 / B * sum((H_L - T)^2) in FP64."""
+    H = mlp_forward(Ws, X)
+    E = H[-1] - np.asarray(T, dtype=np.float64)
+    return 0.5 * float(np.sum(E * E)) / E.shape[0]
+
+
+def mlp_grads(Ws, X, T):
+    """(loss, [dL/dW_1, ..., dL/dW_L]) by backpropagation in FP64.
+
+    G_L = (H_L - T) / B; dL/dW_l = H_{l-1}^T G_l; and, below the top layer,
+    G_{l-1} = (G_l W_l^T) o (1 - H_{l-1}^2), the derivative of tanh.
+    """
+    H = mlp_forward(Ws, X)
+    E = H[-1] - np.asarray(T, dtype=np.float64)
+    B = E.shape[0]
+    loss = 0.5 * float(np.sum(E * E)) / B
+    G = E / B
+    dWs = [None] * len(Ws)
+    for l in range(len(Ws) - 1, -1, -1):
+        dWs[l] = H[l].T @ G
+        if l > 0:
+            G = (G @ np.asarray(Ws[l], dtype=np.float64).T) * (1.0 - H[l] * H[l])
+    return loss, dWs
+
+
+def mlp_step(Ws, X, T, lr):
+    """(loss before the step, [W_l - lr dL/dW_l]) in FP64."""
+    loss, dWs = mlp_grads(Ws, X, T)
+    return loss, [np.asarray(W, dtype=np.float64) - lr * dW for W, dW in zip(Ws, dWs)]

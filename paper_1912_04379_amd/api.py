@@ -129,18 +129,21 @@ def colmajor_view(T):
     return _view(tuple(T.shape), tuple(T.stride()))
 
 
-def matmul(X, W, *, precision="fp32", config=-1, out=None, stream=None):
-    """Y = X @ W for 2-D float32 device tensors; Y is a new (or the given
-    contiguous) row-major (b x o) tensor.  One library call."""
+def matmul(X, W, *, alpha=1.0, beta=0.0, precision="fp32", config=-1, out=None, stream=None):
+    """Y = alpha X @ W + beta Y for 2-D float32 device tensors; Y is a new
+    (or the given contiguous) row-major (b x o) tensor.  beta != 0 needs
+    ``out``, whose values it scales.  One library call."""
     import torch
     ta, tb, M, N, K, lda, ldb, ldc = matmul_args(tuple(X.shape), tuple(X.stride()),
                                                  tuple(W.shape), tuple(W.stride()))
     b, o = X.shape[0], W.shape[1]
     if out is None:
+        if beta != 0.0:
+            raise ValueError("beta != 0 needs out")
         out = torch.empty((b, o), dtype=torch.float32, device=X.device)
     elif tuple(out.shape) != (b, o) or (b > 1 and o > 0 and out.stride() != (o, 1)):
         raise ValueError("out must be a contiguous (b x o) tensor")
-    sgemm(ta, tb, M, N, K, 1.0, W, lda, X, ldb, 0.0, out, ldc,
+    sgemm(ta, tb, M, N, K, alpha, W, lda, X, ldb, beta, out, ldc,
           precision=precision, config=config, stream=stream)
     return out
 

@@ -123,6 +123,23 @@ def dense_layer(seed, batch, n_in, n_out):
     return X, W, G
 
 
+def mlp_case(seed, batch, widths):
+    """Inputs of a multilayer-perceptron training step, row-major float32,
+    drawn in the order X, T, W_1 .. W_L.
+
+    X (batch x widths[0]) and the targets T (batch x widths[-1]) are
+    uniform on [-1, 1); W_l (widths[l-1] x widths[l]) is uniform on
+    [-1, 1) times sqrt(3 / widths[l-1]), so each unit's input has about the
+    variance of one input value and tanh is not saturated.
+    """
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-1.0, 1.0, size=(batch, widths[0])).astype(np.float32)
+    T = rng.uniform(-1.0, 1.0, size=(batch, widths[-1])).astype(np.float32)
+    Ws = [(rng.uniform(-1.0, 1.0, size=(a, b)) * np.sqrt(3.0 / a)).astype(np.float32)
+          for a, b in zip(widths[:-1], widths[1:])]
+    return X, T, Ws
+
+
 def sample_entries(seed, M, N, count):
     """Seeded (row, col) positions for checking single outputs of a large
     product: the four corners and the last row/column are always included
