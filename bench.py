@@ -163,6 +163,7 @@ def main():
     ap.add_argument("--cold-reps", type=int, default=7)
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-vendor", action="store_true",
                     help="skip the ROCm BLAS (torch.addmm) comparison")
     ap.add_argument("--no-wide-range", action="store_true",
@@ -303,6 +304,8 @@ def main():
         line["grouped"] = bench_grouped(args, mg, torch)
     if not args.no_dense:
         line["dense_layer"] = bench_dense(args, mg, torch)
+    if not args.no_mlp:
+        line["mlp_training"] = bench_mlp(args, mg, torch)
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(oracle, case, n, alpha, beta, ld)
@@ -530,6 +533,32 @@ def bench_dense(args, mg, torch):
     return out
 
 
+def bench_mlp(args, mg, torch):
+    """Sustained rate of multilayer-perceptron training (the paper's
+    application, Section 4): batch 8192, widths 1024 -> 4096 -> 4096 ->
+    1024, tanh hidden layers, squared-error loss, one gradient-descent step
+    per batch with the update fused into the weight-gradient products.  The
+    rate counts the products' flops; the step's time includes the
+    elementwise work."""
+    import synth
+    batch, widths, lr = 8192, [1024, 4096, 4096, 1024], 1e-3
+    X, T, Ws = synth.mlp_case(0, batch, widths)
+    Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
+    flops = mg.mlp_step_flops(batch, widths)
+    out = {"workload": "MLP batch 8192, widths 1024-4096-4096-1024, tanh, MSE, SGD lr 1e-3",
+           "gflop_per_step": round(flops / 1e9, 3)}
+    stream = torch.cuda.current_stream()
+    for prec in ("fp32", "bf16x3"):
+        net = mg.MLP([torch.from_numpy(W).cuda() for W in Ws], precision=prec)
+        first = float(net.step(Xd, Td, lr))
+        ms = timed(lambda: net.step(Xd, Td, lr), max(5, args.steps // 2), 2, stream)
+        last = float(net.step(Xd, Td, lr))
+        out[prec] = {"ms_per_step": round(ms, 4), "tflops": round(flops / ms / 1e9, 3),
+                     "loss_first": round(first, 6), "loss_last": round(last, 6)}
+        log("mlp %s: %.3f ms per step (%.1f TFLOP/s), loss %.5f -> %.5f"
+            % (prec, ms, flops / ms / 1e9, first, last))
+        del net
+    return out
 
 
 if __name__ == "__main__":
