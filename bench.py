@@ -164,6 +164,9 @@ def main():
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--grouped-defaults", action="store_true",
+                    help="replay the library's default grouped plans instead of tuned ones "
+                         "(profiling runs: every pass then runs the same kernels)")
     ap.add_argument("--no-vendor", action="store_true",
                     help="skip the ROCm BLAS (torch.addmm) comparison")
     ap.add_argument("--no-wide-range", action="store_true",
@@ -483,7 +486,7 @@ def bench_grouped(args, mg, torch):
     out = {"workload": "512 GEMMs, M,N,K ~ U{16..512}, transA N/T, alpha=beta=1, seed 0",
            "gflop_per_step": round(flops / 1e9, 3), "gbytes_per_step": round(nbytes / 1e9, 4)}
     for prec in ("fp32", "bf16x3"):
-        cfg, _ = mg.tune_grouped(probs, prec, reps=3)
+        cfg = None if args.grouped_defaults else mg.tune_grouped(probs, prec, reps=3)[0]
         arena.copy_(init)
         plan = mg.GroupedPlan(probs, prec, bucket_configs=cfg)
         ms_graph = timed(lambda: plan.launch(stream), args.steps, args.warmup, stream)
@@ -498,7 +501,8 @@ def bench_grouped(args, mg, torch):
         ms_eager = timed(eager, max(3, args.steps // 4), 2, stream)
         info = plan.info()
         plan.close()
-        out[prec] = {"bucket_configs": cfg, "tiles": info["tiles"],
+        out[prec] = {"bucket_configs": cfg if cfg is not None else "library defaults",
+                     "tiles": info["tiles"],
                      "workgroups": info["workgroups"],
                      "graph_ms": round(ms_graph, 4), "tflops": round(flops / ms_graph / 1e9, 3),
                      "gbs": round(nbytes / ms_graph / 1e6, 1),

@@ -3,7 +3,7 @@
  * multiply for AMD Instinct MI355X (gfx950).
  *
  * The operation is the Level-3 BLAS SGEMM routine (Aberdeen & Baxter,
- * Section 1: the library "implements the SGEMM interface of Level-3 BLAS";
+ * Section 1: the paper's library offers the BLAS SGEMM calling interface;
  * A is M x K, B is K x N and the product costs 2MNK flops):
  *
  *     C <- alpha * op(A) * op(B) + beta * C
@@ -222,7 +222,7 @@ int mgemm_grouped_variant_info(int precision, int variant, int *bm, int *bn,
  * one variant to every bucket are timed, then, from the fastest, each
  * bucket in turn tries every variant (two passes).  A change is kept only
  * when it is more than 2% faster than the assignment it replaces, so near
- * ties keep the earlier choice and repeated tunings agree.  Writes 4 entries to
+ * ties keep the earlier choice.  Writes 4 entries to
  * bucket_configs and the best time in
  * milliseconds to *best_ms (may be NULL).  The problems are RUN: every C
  * is overwritten with unspecified values, so tune on scratch outputs or

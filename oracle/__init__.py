@@ -8,7 +8,7 @@ use is the seeded input generator in ``synth``.
 Contents
 --------
 * ``sgemm`` / ``sgemm_entries`` / ``dgemm``: the definition of the Level-3 BLAS
-  SGEMM operation (paper, Section 1), the "naive three-loop" product of
+  SGEMM operation (paper, Section 1), the plain three-nested-loop product of
   Section 4 accumulated in FP64 (``oracle.c``).
 * ``split_bf16`` and ``bf16x3``: the hi/lo split of an FP32 value into two
   BF16 values and the three-product sum hi*hi + hi*lo + lo*hi, evaluated in

@@ -13,8 +13,8 @@
  *   - Section 1 (Introduction) of Aberdeen & Baxter: the operation is the
  *     SGEMM routine of Level-3 BLAS, A is M x K, B is K x N, and a dense
  *     product costs 2MNK floating point operations (no Strassen).
- *   - Section 4 (Results) names a "naive three-loop" multiply as the plain
- *     comparison curve.  This is that loop, with the accumulation done in
+ *   - Section 4 (Results) compares against a plain multiply of three nested
+ *     loops.  This is that loop, with the accumulation done in
  *     FP64 instead of FP32 so that it is far more accurate than anything it
  *     checks.
  *

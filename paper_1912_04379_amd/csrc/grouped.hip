@@ -561,8 +561,8 @@ int mgemm_grouped_tune(const mgemm_problem* problems, int64_t count, int precisi
     // another's last work-groups), then descend one bucket at a time, in two
     // passes so that an early bucket is revisited once the later ones moved.
     // A change is taken only when it is faster by more than TUNE_MARGIN:
-    // assignments within timing noise of each other keep the earlier one, so
-    // the choice repeats from run to run.
+    // of two assignments within timing noise of each other, the earlier one
+    // stays.
     constexpr float TUNE_MARGIN = 0.98f;
     float cur = 0.0f;
     int st = time_of(bucket_configs, cur);

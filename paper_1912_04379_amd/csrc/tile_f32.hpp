@@ -1,10 +1,10 @@
 // tile_f32.hpp -- the FP32 MFMA tile engine (one BM x BN tile of C).
 //
 // C <- alpha op(A) op(B) + beta C, FP32 in, FP32 accumulate, FP32 out.
-// The paper's recipe (Sections 2 and 3) -- accumulate in registers as long
-// as possible, reuse every loaded operand several times, stage blocks of
-// A and B close to the arithmetic, prefetch the next block while computing
-// the current one -- maps onto gfx950 as:
+// The paper's recipe (Sections 2 and 3) -- keep every partial sum in a
+// register for the whole k loop, reuse every loaded operand several times,
+// stage blocks of A and B close to the arithmetic, prefetch the next block
+// while computing the current one -- maps onto gfx950 as:
 //   * registers:  each wave owns an (FM*32) x (FN*32) block of C held in
 //                 MFMA accumulators for the whole K loop; each operand value
 //                 read from LDS feeds FN (or FM) MFMAs;
