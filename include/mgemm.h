@@ -93,6 +93,13 @@ int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  *     large products): the operands packed once, 2 bytes per element of A
  *     and of B for FP16, 4 bytes (hi and lo) for BF16x3 -- 512 MB at
  *     M = N = K = 8192.
+ * FP32 configuration 11 (split-K: the k range cut into S pieces whose
+ * partial products are added in a fixed order by a second kernel), which
+ * the library's choice takes for products with at most one 128 x 128 tile
+ * per CU and K of about 2048 and up, takes S*M*N*4 bytes from the same
+ * pool (at most 1 GiB; larger products, and leading dimensions beyond the
+ * 32-bit buffer path, run configuration 0 instead).  The other FP32
+ * configurations take no workspace.
  * An allocation failure returns MGEMM_ERR_ALLOC before anything runs.  A
  * packed configuration that the product cannot use (K too long for 32-bit
  * block offsets, or an LDS ring larger than a CU) runs configuration 0.

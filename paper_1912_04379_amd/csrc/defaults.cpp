@@ -22,6 +22,26 @@ static double slot_share(int64_t M, int64_t N, int bm, int bn) {
 }
 
 int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
+    // At most one 128x128 tile per CU and a long enough k range: split-K
+    // (configuration 11).  Measured NN on MI355X, TFLOP/s, split-K against
+    // the best unsplit choice: 256 x 256 x 65536, 85 against 18 (the
+    // small-product kernel); 512 x 512 x 2048, 37 against 22 (64x64
+    // tiles); 1000 x 1000 x 4000, 93 against 82; 1024 x 1024 x 3072, 92
+    // against 88; 1024 x 4096 x 8192, 133 against 124; 2048 x 2048 x 4096,
+    // 123 against 119.  The pieces get too short below K = 2048 for products
+    // split into 64x64 tiles, below 3072 for 128x128 tiles (1024^2 x 2048:
+    // 76 against 87), and below 4096 where the small-product kernel applies
+    // (256 x 256 x 2048: 7 against 14).
+    {
+        const int64_t t128 = tile_count(M, N, 128, 128), t64 = tile_count(M, N, 64, 64);
+        const int64_t kmin = t64 <= 32 ? 4096 : (t128 * 4 < NUM_CUS ? 2048 : 3072);
+        if (t128 <= NUM_CUS && K >= kmin) {
+            const SplitKPlan p = f32_splitk_plan(M, N, K, (int)NUM_CUS);
+            if (p.splits >= 2 && f32_splitk_workspace_bytes(p, M, N) <= F32_SPLITK_MAX_WORKSPACE)
+                return F32_SPLITK_CONFIG;
+        }
+    }
+
     // Few 64x64 tiles and a k range worth splitting: the small-product
     // kernel (16x16 tiles, k split over 4 waves).  Measured kernel times:
     // 5.7 us vs 8.9 us for 64x64 tiles at 256^3, 34 us vs 89 us at

@@ -26,6 +26,24 @@ hipError_t launch_small(bool transA, bool transB, const GemmDesc& d, hipStream_t
 constexpr int F32_TAIL_CONFIG = 10;
 hipError_t launch_f32_tail(bool transA, bool transB, const GemmDesc& d, int cus,
                            hipStream_t stream);
+// FP32 configuration 11: split-K.  The k range is cut into S pieces of kc
+// (the last one shorter); piece s of every tile is an ordinary tile product
+// written to workspace + s*M*N (column-major, ld M), and a second kernel
+// adds the S partial products in order s = 0..S-1 and applies alpha, beta.
+constexpr int F32_SPLITK_CONFIG = 11;
+struct SplitKPlan {
+    int small_tile;   // 0: 128 x 128 x 16 tiles, 1: 64 x 64 x 16
+    int splits;       // S >= 2, or 0 when splitting does not apply
+    int64_t kc;       // k per piece, a multiple of 32
+};
+SplitKPlan f32_splitk_plan(int64_t M, int64_t N, int64_t K, int cus);
+// Largest split-K workspace taken (1 GiB); larger products run unsplit.
+constexpr int64_t F32_SPLITK_MAX_WORKSPACE = 1LL << 30;
+int64_t f32_splitk_workspace_bytes(const SplitKPlan& p, int64_t M, int64_t N);
+// Needs buffer_path_ok(d), p.splits >= 2 and f32_splitk_workspace_bytes()
+// of workspace.
+hipError_t launch_f32_splitk(bool transA, bool transB, const GemmDesc& d, const SplitKPlan& p,
+                             float* workspace, hipStream_t stream);
 
 // BF16x3 split path.
 int bf16x3_config_count();

@@ -230,6 +230,29 @@ static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K,
                               : launch_f32(0, ta, tb, d, s);
         return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
     }
+    if (precision == MGEMM_PREC_FP32 && cfg == F32_SPLITK_CONFIG) {
+        // Split-K needs a workspace of S partial products; where it does
+        // not apply (short k, 64-bit address path), 128 x 128 tiles.
+        const SplitKPlan plan = f32_splitk_plan(M, N, K, device_cus(dev));
+        const int64_t bytes = f32_splitk_workspace_bytes(plan, M, N);
+        if (plan.splits < 2 || !buffer_path_ok(d) || M > MAX_BUF_LD ||
+            bytes > F32_SPLITK_MAX_WORKSPACE) {
+            e = launch_f32(0, ta, tb, d, s);
+            return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
+        }
+        hipMemPool_t pool = nullptr;
+        float* ws = nullptr;
+        e = workspace_pool(dev, &pool);
+        if (e == hipSuccess) e = hipMallocFromPoolAsync((void**)&ws, (size_t)bytes, pool, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MGEMM_ERR_ALLOC, "stream-ordered split-K workspace");
+        }
+        e = launch_f32_splitk(ta, tb, d, plan, ws, s);
+        const hipError_t e2 = hipFreeAsync(ws, s);
+        if (e == hipSuccess) e = e2;
+        return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
+    }
     if (precision == MGEMM_PREC_FP32) {
         e = launch_f32(cfg, ta, tb, d, s);
         return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");

@@ -126,11 +126,127 @@ hipError_t launch_f32_tail(bool ta, bool tb, const GemmDesc& d, int cus, hipStre
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Configuration 11: split-K.  A product with few tiles and a long k range
+// leaves most CUs idle and runs each tile's K/2 MFMAs as one serial chain.
+// Cutting k into S pieces gives S times the work-groups and chains S times
+// shorter; each piece is an ordinary tile (alpha 1, beta 0) into its own
+// slice of a workspace, and a second kernel adds the slices in a fixed
+// order and applies the epilogue, so results do not depend on timing.
+// ---------------------------------------------------------------------------
+template <class Cfg, bool AK, bool BKC>
+__global__ __launch_bounds__(Cfg::NT, Cfg::WPE) void sgemm_f32_splitk_kernel(
+    GemmDesc d, uint32_t tiles_m, uint32_t tiles_n, int64_t kc, float* ws) {
+    __shared__ __attribute__((aligned(16))) float smem[Cfg::SMEM_FLOATS];
+    // Logical id -> (piece, tile): the work-groups of one XCD take
+    // consecutive tiles of one piece, which share panels of A and B.
+    const uint32_t id = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t tiles = tiles_m * tiles_n;
+    const uint32_t s = id / tiles;
+    uint32_t tm, tn;
+    grouped_tile<8>(id - s * tiles, tiles_m, tiles_n, tm, tn);
+    const int64_t k0 = (int64_t)s * kc;
+    GemmDesc p = d;
+    // op(A)'s k runs along columns of A 'N' and rows of A 'T'; op(B)'s along
+    // rows of B 'N' and columns of B 'T'.
+    p.A = d.A + (AK ? k0 : k0 * d.lda);
+    p.B = d.B + (BKC ? k0 : k0 * d.ldb);
+    p.K = d.K - k0 < kc ? d.K - k0 : kc;
+    p.C = ws + (int64_t)s * d.M * d.N;
+    p.ldc = d.M;
+    p.alpha = 1.0f;
+    p.beta = 0.0f;
+    tile_f32<Cfg, AK, BKC, true>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
+}
+
+// C <- alpha * sum_s ws[s] + beta * C, s in increasing order; beta == 0
+// never reads C.  Grid-stride over the M*N outputs, m fastest.
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ ws,
+                                                            int splits, int64_t M, int64_t N,
+                                                            float* C, int64_t ldc, float alpha,
+                                                            float beta) {
+    const int64_t mn = M * N;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < mn;
+         i += (int64_t)gridDim.x * 256) {
+        float sum = ws[i];
+        for (int s = 1; s < splits; ++s) sum += ws[(int64_t)s * mn + i];
+        const int64_t n = i / M, m = i - n * M;
+        float* c = C + m + n * ldc;
+        *c = beta == 0.0f ? alpha * sum : fmaf(beta, *c, alpha * sum);
+    }
+}
+
+SplitKPlan f32_splitk_plan(int64_t M, int64_t N, int64_t K, int cus) {
+    SplitKPlan p{0, 0, 0};
+    if (M < 1 || N < 1 || K < 1 || cus < 1) return p;
+    const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128);
+    const int64_t t64 = ((M + 63) / 64) * ((N + 63) / 64);
+    p.small_tile = t128 * 4 >= cus ? 0 : 1;
+    const int64_t tiles = p.small_tile ? t64 : t128;
+    // About two work-groups per CU, pieces of at least 256 k.
+    int64_t s = (2 * (int64_t)cus + tiles - 1) / tiles;
+    if (s > 32) s = 32;
+    int64_t kc = (K + s - 1) / s;
+    kc = (kc + 31) / 32 * 32;
+    if (kc < 256) kc = 256;
+    s = (K + kc - 1) / kc;
+    if (s < 2 || tiles * s > 0xffffffffLL) return p;
+    p.splits = (int)s;
+    p.kc = kc;
+    return p;
+}
+
+int64_t f32_splitk_workspace_bytes(const SplitKPlan& p, int64_t M, int64_t N) {
+    return (int64_t)p.splits * M * N * 4;
+}
+
+template <class Cfg>
+static void launch_splitk_pieces(bool ta, bool tb, const GemmDesc& d, const SplitKPlan& p,
+                                 float* ws, hipStream_t s) {
+    const uint32_t tm = (uint32_t)((d.M + Cfg::BM - 1) / Cfg::BM);
+    const uint32_t tn = (uint32_t)((d.N + Cfg::BN - 1) / Cfg::BN);
+    const dim3 grid(tm * tn * (uint32_t)p.splits), block(Cfg::NT);
+    if (!ta && !tb)
+        hipLaunchKernelGGL((sgemm_f32_splitk_kernel<Cfg, false, true>), grid, block,
+                           Cfg::PAD_BYTES, s, d, tm, tn, p.kc, ws);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((sgemm_f32_splitk_kernel<Cfg, false, false>), grid, block,
+                           Cfg::PAD_BYTES, s, d, tm, tn, p.kc, ws);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((sgemm_f32_splitk_kernel<Cfg, true, true>), grid, block,
+                           Cfg::PAD_BYTES, s, d, tm, tn, p.kc, ws);
+    else
+        hipLaunchKernelGGL((sgemm_f32_splitk_kernel<Cfg, true, false>), grid, block,
+                           Cfg::PAD_BYTES, s, d, tm, tn, p.kc, ws);
+}
+
+hipError_t launch_f32_splitk(bool ta, bool tb, const GemmDesc& d, const SplitKPlan& p,
+                             float* ws, hipStream_t s) {
+    // The workspace slices are the C of ordinary tiles: ld M within the
+    // buffer path's limit.
+    if (!buffer_path_ok(d) || p.splits < 2 || p.kc < 32 || d.M > MAX_BUF_LD || !ws)
+        return hipErrorInvalidValue;
+    if ((int64_t)(p.splits - 1) * p.kc >= d.K) return hipErrorInvalidValue;   // empty piece
+    if (p.small_tile)
+        launch_splitk_pieces<F32Cfg1>(ta, tb, d, p, ws, s);
+    else
+        launch_splitk_pieces<F32Cfg0>(ta, tb, d, p, ws, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t mn = d.M * d.N;
+    int64_t blocks = (mn + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, ws,
+                       p.splits, d.M, d.N, d.C, d.ldc, d.alpha, d.beta);
+    return hipGetLastError();
+}
+
 // Configuration 9 is the small-product kernel (sgemm_small.hip);
-// configuration 10 the 256 x 256 x 32 tile with a 128 x 128 tail (above).
+// configuration 10 the 256 x 256 x 32 tile with a 128 x 128 tail (above);
+// configuration 11 split-K (above).
 constexpr int F32_SMALL_CONFIG = 9;
 
-int f32_config_count() { return 11; }
+int f32_config_count() { return 12; }
 
 TileConfigInfo f32_config_info(int cfg) {
     switch (cfg) {
@@ -145,6 +261,7 @@ TileConfigInfo f32_config_info(int cfg) {
         case 8: return info_of<F32Cfg8>();
         case F32_SMALL_CONFIG: return {16, 16, 16, 256};
         case F32_TAIL_CONFIG: return info_of<BigCfg>();
+        case F32_SPLITK_CONFIG: return info_of<F32Cfg0>();   // 64 x 64 for few tiles
         default: return {0, 0, 0, 0};
     }
 }
@@ -168,7 +285,7 @@ hipError_t launch_f32(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t 
         case 7: return launch_cfg<F32Cfg7, true>(ta, tb, d, s);
         case 8: return launch_cfg<F32Cfg8, true>(ta, tb, d, s);
         case F32_SMALL_CONFIG: return launch_small(ta, tb, d, s);
-        default: return hipErrorInvalidValue;   // configuration 10: launch_f32_tail
+        default: return hipErrorInvalidValue;   // 10: launch_f32_tail, 11: launch_f32_splitk
     }
 }
 

@@ -48,7 +48,7 @@ def test_ragged_shapes(ta, tb, shape):
     full_check(c, run(c))
 
 
-@pytest.mark.parametrize("cfg", range(11))
+@pytest.mark.parametrize("cfg", range(12))
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_every_config(cfg, ta, tb):
     c = synth.sgemm_case(3, ta, tb, 300, 270, 77, alpha=1.5, beta=-0.5, pad=3)
@@ -56,7 +56,7 @@ def test_every_config(cfg, ta, tb):
     full_check(c, run(c, config=cfg))
 
 
-@pytest.mark.parametrize("cfg", range(11))
+@pytest.mark.parametrize("cfg", range(12))
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_every_config_sizes_multiple_of_4(cfg, ta, tb):
     """M and N multiples of 4 but of no tile edge, odd leading dimensions
@@ -67,7 +67,7 @@ def test_every_config_sizes_multiple_of_4(cfg, ta, tb):
     full_check(c, run(c, config=cfg))
 
 
-@pytest.mark.parametrize("cfg", range(11))
+@pytest.mark.parametrize("cfg", range(12))
 @pytest.mark.parametrize("K", [1, 17, 33])
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "T")])
 def test_short_k_every_config(cfg, K, ta, tb):
@@ -100,6 +100,39 @@ def test_big_tiles_with_small_tile_tail_full(ta, tb, shape):
     c = synth.sgemm_case(23, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=3)
     log("f32 big+tail %s %s%s" % (shape, ta, tb))
     full_check(c, run(c, config=10))
+
+
+@pytest.mark.parametrize("ta,tb", TRANS)
+@pytest.mark.parametrize("shape", [(300, 270, 5000), (64, 64, 20000), (257, 129, 3001),
+                                   (1000, 1000, 4000)])
+def test_split_k(ta, tb, shape):
+    """Configuration 11 on products with a long k range: 64 x 64 tiles
+    (few tiles) or 128 x 128 tiles (1000^2), k cut into pieces of a
+    multiple of 32 with a shorter last piece, partial products added in a
+    fixed order by the reduction kernel."""
+    M, N, K = shape
+    c = synth.sgemm_case(41, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=3)
+    log("f32 split-K %s %s%s" % (shape, ta, tb))
+    full_check(c, run(c, config=11))
+
+
+def test_split_k_beta_zero_ignores_nan_in_c():
+    c = synth.sgemm_case(42, "N", "T", 190, 200, 6000, pad=2)
+    c["C"] = np.where(c["C"] == synth.C_SENTINEL, c["C"], np.float32(np.nan)).astype(np.float32)
+    got = run(c, config=11)
+    assert np.all(np.isfinite(logical_c(got, c)))
+    assert padding_untouched(got, c)
+
+
+def test_split_k_integer_inputs_bitwise():
+    """Small integers: every partial sum, and the sum of the pieces, is an
+    exact integer in FP32, so split-K equals the oracle bitwise."""
+    c = synth.sgemm_case(43, "N", "N", 130, 120, 4100, alpha=1.0, beta=1.0, dist="int16",
+                         dist_c="int16")
+    got = logical_c(run(c, config=11), c)
+    ref = oracle.sgemm(*(c[k] for k in ("transA", "transB", "M", "N", "K", "alpha", "A",
+                                         "lda", "B", "ldb", "beta", "C", "ldc")))
+    assert np.array_equal(got, ref)
 
 
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "T")])
