@@ -164,6 +164,7 @@ def main():
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-mlp", action="store_true")
+    ap.add_argument("--no-splitk", action="store_true")
     ap.add_argument("--grouped-defaults", action="store_true",
                     help="replay the library's default grouped plans instead of tuned ones "
                          "(profiling runs: every pass then runs the same kernels)")
@@ -309,6 +310,8 @@ def main():
         line["dense_layer"] = bench_dense(args, mg, torch)
     if not args.no_mlp:
         line["mlp_training"] = bench_mlp(args, mg, torch)
+    if not args.no_splitk:
+        line["split_k"] = bench_splitk(args, mg, torch)
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(oracle, case, n, alpha, beta, ld)
@@ -562,6 +565,32 @@ def bench_mlp(args, mg, torch):
         log("mlp %s: %.3f ms per step (%.1f TFLOP/s), loss %.5f -> %.5f"
             % (prec, ms, flops / ms / 1e9, first, last))
         del net
+    return out
+
+
+def bench_splitk(args, mg, torch):
+    """Products with few tiles and a long k range (NN, ld = rows + 16, alpha
+    1.5, beta -0.5, uniform inputs): the library's choice (split-K) against
+    the same product unsplit on 64 x 64 tiles (configuration 1) and, at
+    256^2, the small-product kernel (configuration 9)."""
+    import synth
+    stream = torch.cuda.current_stream()
+    out = {}
+    for (M, N, K), other in (((1024, 1024, 8192), 1), ((512, 512, 16384), 1),
+                             ((256, 256, 65536), 9)):
+        c = synth.sgemm_case(0, "N", "N", M, N, K, alpha=1.5, beta=-0.5)
+        A, B, C = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
+        res = {"default_config": mg.default_config("fp32", "N", "N", M, N, K)}
+        for name, cfg in (("default", -1), ("unsplit_config_%d" % other, other)):
+            ms = timed(lambda: mg.sgemm("N", "N", M, N, K, 1.5, A, c["lda"], B, c["ldb"], -0.5, C,
+                                        c["ldc"], config=cfg), max(10, args.steps), 3, stream)
+            res[name] = {"ms": round(ms, 4), "tflops": round(2.0 * M * N * K / ms / 1e9, 3)}
+        res["speedup"] = round(res["unsplit_config_%d" % other]["ms"] / res["default"]["ms"], 3)
+        out["%dx%dx%d" % (M, N, K)] = res
+        log("split-K %dx%dx%d: %.1f TFLOP/s (config %d), unsplit %.1f" %
+            (M, N, K, res["default"]["tflops"], res["default_config"],
+             res["unsplit_config_%d" % other]["tflops"]))
+        del A, B, C
     return out
 
 
