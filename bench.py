@@ -165,6 +165,7 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-splitk", action="store_true")
+    ap.add_argument("--no-prepacked", action="store_true")
     ap.add_argument("--grouped-defaults", action="store_true",
                     help="replay the library's default grouped plans instead of tuned ones "
                          "(profiling runs: every pass then runs the same kernels)")
@@ -312,6 +313,8 @@ def main():
         line["mlp_training"] = bench_mlp(args, mg, torch)
     if not args.no_splitk:
         line["split_k"] = bench_splitk(args, mg, torch)
+    if not (args.no_prepacked or args.no_forms):
+        line["prepacked_b"] = bench_prepacked(args, mg, torch, n)
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(oracle, case, n, alpha, beta, ld)
@@ -591,6 +594,37 @@ def bench_splitk(args, mg, torch):
             (M, N, K, res["default"]["tflops"], res["default_config"],
              res["unsplit_config_%d" % other]["tflops"]))
         del A, B, C
+    return out
+
+
+def bench_prepacked(args, mg, torch, n):
+    """BF16x3 at n^3 NN with op(B) packed once (mgemm_pack_b) against the
+    ordinary call, which packs both operands every time; same inputs as the
+    headline product (alpha 1.5, beta -0.5)."""
+    import synth
+    c = synth.sgemm_case(0, "N", "N", n, n, n, alpha=1.5, beta=-0.5)
+    A, B, C = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
+    stream = torch.cuda.current_stream()
+    ld = c["lda"]
+    ms_call = timed(lambda: mg.sgemm("N", "N", n, n, n, 1.5, A, ld, B, ld, -0.5, C, ld,
+                                     precision="bf16x3"), args.steps, args.warmup, stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    pb = mg.PackedB("N", n, n, B, ld)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_pack = e0.elapsed_time(e1)
+    ms_packed = timed(lambda: pb.sgemm("N", n, 1.5, A, ld, -0.5, C, ld), args.steps,
+                      args.warmup, stream)
+    pb.close()
+    flops = 2.0 * n ** 3
+    out = {"workload": "bf16x3 NN %d^3, op(B) packed once" % n,
+           "ordinary_ms": round(ms_call, 4), "packed_b_ms": round(ms_packed, 4),
+           "packed_b_tflops": round(flops / ms_packed / 1e9, 3),
+           "speedup": round(ms_call / ms_packed, 3), "pack_once_ms": round(ms_pack, 4)}
+    log("pre-packed B bf16x3 %d^3: %.3f ms per call against %.3f (pack once %.3f ms)"
+        % (n, ms_packed, ms_call, ms_pack))
+    del A, B, C
     return out
 
 

@@ -239,6 +239,57 @@ int mgemm_grouped_tune(const mgemm_problem *problems, int64_t count,
                        int precision, void *stream, int reps,
                        int *bucket_configs, float *best_ms);
 
+/* ---- pre-packed B -------------------------------------------------------- */
+
+/*
+ * op(B) converted once and kept in the library's packed layout, for calls
+ * that reuse one B with many A (layer weights, a fixed operand).  The
+ * paper re-orders blocks of B into a buffer laid out for the kernel's
+ * accesses (Section 3, re-buffering); here that step runs once for the
+ * whole operand and its result is kept, so a call with a packed B packs
+ * only op(A).
+ *
+ * Built for MGEMM_PREC_BF16X3 only (the hi and lo bf16 halves of every
+ * element, 4 bytes per element of op(B), K rounded up to 16 and N to 32);
+ * other precisions return MGEMM_ERR_UNSUPPORTED.  Products run on the
+ * pipelined packed 256 x 256 tile when there are at least 144 such tiles,
+ * else on the pipelined 128 x 128 tile (16-bit configurations 10 and 11):
+ * their results equal mgemm_sgemm_ex with the same configuration bitwise.
+ *
+ * Argument errors are reported with the SGEMM number of the same argument
+ * (transB -2, N -4, K -5, B -9, ldb -10; transA -1, M -3, A -7, lda -8,
+ * C -12, ldc -13); a NULL or destroyed handle gives MGEMM_ERR_BAD_PLAN.
+ */
+typedef struct mgemm_packed_b mgemm_packed_b;
+
+/*
+ * Pack op(B) (K x N; B stored K x N for 'N', N x K for 'T'/'C', column-
+ * major at ldb) on `stream`.  The handle owns hipMalloc'ed device memory on
+ * the current device.  Packing is asynchronous on `stream`: calls on that
+ * stream may use the handle at once; B may change once that work is done.
+ * *out is NULL on any error.
+ */
+int mgemm_pack_b(char transB, int64_t K, int64_t N, const float *B, int64_t ldb,
+                 int precision, void *stream, mgemm_packed_b **out);
+
+/* K, N, precision and device bytes of a packed B (any pointer may be NULL). */
+int mgemm_packed_b_info(const mgemm_packed_b *Bp, int64_t *K, int64_t *N,
+                        int *precision, int64_t *bytes);
+
+/*
+ * C <- alpha op(A) op(B) + beta C with op(B) from Bp (K and N are Bp's).
+ * op(A) is M x K.  Same rules as mgemm_sgemm_ex for A, C, alpha, beta and
+ * the quick returns; op(A) is packed into a stream-ordered workspace from
+ * the library's pool (4 bytes per element).  Bp must stay alive until the
+ * call's work has run.
+ */
+int mgemm_sgemm_packed_b(char transA, int64_t M, float alpha, const float *A,
+                         int64_t lda, const mgemm_packed_b *Bp, float beta,
+                         float *C, int64_t ldc, void *stream);
+
+/* Free a packed B; waits for device work still reading it. */
+int mgemm_packed_b_destroy(mgemm_packed_b *Bp);
+
 /* ---- status ------------------------------------------------------------ */
 
 /* Static text for a status code. */

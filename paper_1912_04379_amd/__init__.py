@@ -11,6 +11,7 @@ current HIP stream.  PyTorch supplies device memory and streams.
   replayed from a HIP graph.
 * ``MLP``: multilayer-perceptron training steps whose products (and the
   weight update, fused into them) run in the library.
+* ``PackedB``: op(B) packed once (BF16x3 form) and reused by many products.
 """
 from ._lib import (MgemmError, PREC_BF16X3, PREC_FP16_SCALED, PREC_FP32, PRECISIONS,
                    check, lib)
@@ -27,8 +28,9 @@ def linear(X, W, precision="fp32"):
 
 from .grouped import GroupedPlan, tune as tune_grouped  # noqa: E402
 from .mlp import MLP, step_flops as mlp_step_flops  # noqa: E402
+from .packed import PackedB  # noqa: E402
 
-__all__ = ["GroupedPlan", "tune_grouped", "MLP", "mlp_step_flops", "MgemmError", "PREC_FP32", "PREC_BF16X3", "PREC_FP16_SCALED", "PRECISIONS",
+__all__ = ["GroupedPlan", "tune_grouped", "MLP", "mlp_step_flops", "PackedB", "MgemmError", "PREC_FP32", "PREC_BF16X3", "PREC_FP16_SCALED", "PRECISIONS",
            "sgemm", "matmul", "matmul_args", "linear", "config_count", "config_info",
            "default_config", "version", "lib", "check", "stream_handle", "tune_sgemm",
            "record_choice", "clear_choices", "trim_workspace"]

@@ -68,6 +68,11 @@ _SIGS = {
                                           ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "mgemm_grouped_tune": (_i32, [ctypes.POINTER(Problem), _i64, _i32, _vp, _i32,
                                   ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)]),
+    "mgemm_pack_b": (_i32, [_ch, _i64, _i64, _vp, _i64, _i32, _vp, ctypes.POINTER(_vp)]),
+    "mgemm_packed_b_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64),
+                                   ctypes.POINTER(_i32), ctypes.POINTER(_i64)]),
+    "mgemm_sgemm_packed_b": (_i32, [_ch, _i64, _f32, _vp, _i64, _vp, _f32, _vp, _i64, _vp]),
+    "mgemm_packed_b_destroy": (_i32, [_vp]),
     "mgemm_status_string": (ctypes.c_char_p, [_i32]),
     "mgemm_last_error": (ctypes.c_char_p, []),
     "mgemm_version": (_i32, []),

@@ -75,6 +75,18 @@ int64_t packed_workspace_bytes(bool bf16x3, int cfg, int64_t M, int64_t N, int64
 bool packed_supported(bool bf16x3, int cfg, int64_t M, int64_t N, int64_t K);
 hipError_t launch_packed(bool bf16x3, int cfg, bool transA, bool transB, const GemmDesc& d,
                          char* workspace, hipStream_t stream);
+// One operand packed on its own (the pre-packed B entry points): bytes of
+// op(X) as P x K in kw-deep blocks, the pack launch (kcontig: op(X) is
+// contiguous along k), the block depth of a packed configuration (0 for an
+// unknown one), and the main kernel with op(B) already packed.
+int64_t packed_operand_bytes(bool bf16x3, int kw, int64_t P, int64_t K);
+hipError_t launch_pack_operand(bool bf16x3, int kw, bool kcontig, const float* X, int64_t ld,
+                               int64_t P, int64_t K, char* hi, char* lo, const int* expo,
+                               hipStream_t stream);
+int packed_config_kw(int cfg);
+hipError_t launch_packed_b_ready(bool bf16x3, int cfg, bool transA, const GemmDesc& d,
+                                 char* a_workspace, const char* b_hi, const char* b_lo,
+                                 hipStream_t stream);
 
 // C <- beta*C (beta == 0 writes zeros without reading C).
 hipError_t launch_scale_c(const GemmDesc& d, hipStream_t stream);

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <unordered_set>
 
 #include "host_common.hpp"
 #include "kernels.hpp"
@@ -347,6 +348,156 @@ int mgemm_default_config(int precision, char transA, char transB, int64_t M, int
     const int ta = trans_code(transA), tb = trans_code(transB);
     if (ta < 0 || tb < 0) return -1;
     return default_config(precision, ta, tb, M, N, K);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Pre-packed op(B) (BF16x3).  The handle owns op(B) packed once in the
+// 16-deep blocks of the packed engine's pipelined configurations, hi then
+// lo halves; calls pack only op(A) and run the main kernel on both.
+// ---------------------------------------------------------------------------
+struct mgemm_packed_b {
+    int precision;
+    int device;
+    int64_t K, N;
+    char* hi;
+    char* lo;
+    int64_t bytes;
+};
+
+namespace mgemm {
+
+static constexpr int PACKED_B_KW = 16;
+// Packed configurations that read 16-deep blocks and fit the BF16x3 ring:
+// the pipelined 256 x 256 and 128 x 128 tiles (16-bit configurations 10, 11).
+static constexpr int PACKED_B_BIG = 6, PACKED_B_SMALL = 7;
+
+static std::mutex g_packed_mu;
+static std::unordered_set<const mgemm_packed_b*> g_packed;
+
+static bool packed_b_live(const mgemm_packed_b* p) {
+    std::lock_guard<std::mutex> lk(g_packed_mu);
+    return p && g_packed.count(p);
+}
+
+}  // namespace mgemm
+
+extern "C" {
+
+int mgemm_pack_b(char transB, int64_t K, int64_t N, const float* B, int64_t ldb, int precision,
+                 void* stream, mgemm_packed_b** out) {
+    if (!out) return fail(MGEMM_ERR_UNSUPPORTED, "out is NULL");
+    *out = nullptr;
+    const int tb = trans_code(transB);
+    if (tb < 0) return fail(-2, "transB must be N, T or C");
+    if (N < 0) return fail(-4, "N < 0");
+    if (K < 0) return fail(-5, "K < 0");
+    if (K > 0 && N > 0 && B == nullptr) return fail(-9, "B is NULL");
+    const int64_t rows_b = tb ? N : K;
+    if (ldb < (rows_b > 1 ? rows_b : 1)) return fail(-10, "ldb < max(1, stored rows of B)");
+    if (precision != MGEMM_PREC_BF16X3)
+        return fail(MGEMM_ERR_UNSUPPORTED, "pre-packed B is built for the BF16x3 form only");
+    if (!packed_supported(true, PACKED_B_BIG, 1, N, K) ||
+        !packed_supported(true, PACKED_B_SMALL, 1, N, K))
+        return fail(MGEMM_ERR_UNSUPPORTED, "K too long for the packed engine's 32-bit offsets");
+    int dev = 0;
+    const int st = check_device(&dev);
+    if (st) return st;
+    const int64_t bytes = packed_operand_bytes(true, PACKED_B_KW, N, K);
+    mgemm_packed_b* h = new mgemm_packed_b{precision, dev, K, N, nullptr, nullptr, bytes};
+    if (bytes > 0) {
+        hipError_t e = hipMalloc((void**)&h->hi, (size_t)bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete h;
+            return fail(MGEMM_ERR_ALLOC, "packed B buffer");
+        }
+        h->lo = h->hi + bytes / 2;
+        e = launch_pack_operand(true, PACKED_B_KW, !tb, B, ldb, N, K, h->hi, h->lo, nullptr,
+                                (hipStream_t)stream);
+        if (e != hipSuccess) {
+            (void)hipFree(h->hi);
+            delete h;
+            return hip_fail(e, "pack kernel launch");
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_packed_mu);
+        g_packed.insert(h);
+    }
+    *out = h;
+    return MGEMM_OK;
+}
+
+int mgemm_packed_b_info(const mgemm_packed_b* Bp, int64_t* K, int64_t* N, int* precision,
+                        int64_t* bytes) {
+    if (!packed_b_live(Bp)) return fail(MGEMM_ERR_BAD_PLAN, "packed B is NULL or destroyed");
+    if (K) *K = Bp->K;
+    if (N) *N = Bp->N;
+    if (precision) *precision = Bp->precision;
+    if (bytes) *bytes = Bp->bytes;
+    return MGEMM_OK;
+}
+
+int mgemm_sgemm_packed_b(char transA, int64_t M, float alpha, const float* A, int64_t lda,
+                         const mgemm_packed_b* Bp, float beta, float* C, int64_t ldc,
+                         void* stream) {
+    if (!packed_b_live(Bp)) return fail(MGEMM_ERR_BAD_PLAN, "packed B is NULL or destroyed");
+    const int64_t K = Bp->K, N = Bp->N;
+    // The SGEMM checks with op(B) standing in as a non-NULL 'N' operand.
+    std::string why;
+    const int bad = validate(transA, 'N', M, N, K, alpha, A, lda,
+                             reinterpret_cast<const float*>(Bp), K > 1 ? K : 1, beta, C, ldc, why);
+    if (bad) return fail(bad, why);
+    const int ta = trans_code(transA);
+    if (M == 0 || N == 0) return MGEMM_OK;
+    const bool no_product = alpha == 0.0f || K == 0;
+    if (no_product && beta == 1.0f) return MGEMM_OK;
+    if (!no_product) {
+        const uintptr_t alo = (uintptr_t)A,
+                        ahi = alo + (uintptr_t)((((ta ? M : K) - 1) * lda + (ta ? K : M)) * 4);
+        const uintptr_t clo = (uintptr_t)C, chi = clo + (uintptr_t)(((N - 1) * ldc + M) * 4);
+        if (alo < chi && clo < ahi) return fail(MGEMM_ERR_ALIAS, "C overlaps A");
+    }
+    int dev = 0;
+    int st = check_device(&dev);
+    if (st) return st;
+    if (dev != Bp->device) return fail(MGEMM_ERR_UNSUPPORTED, "B was packed on another device");
+    hipStream_t s = (hipStream_t)stream;
+    GemmDesc d{A, nullptr, C, M, N, K, lda, K > 1 ? K : 1, ldc, alpha, beta, nullptr, nullptr};
+    hipError_t e;
+    if (no_product) {
+        e = launch_scale_c(d, s);
+        return e == hipSuccess ? MGEMM_OK : hip_fail(e, "scale kernel launch");
+    }
+    const int64_t t256 = ((M + 255) / 256) * ((N + 255) / 256);
+    const int cfg = t256 >= 144 ? PACKED_B_BIG : PACKED_B_SMALL;
+    const int64_t bytes = packed_operand_bytes(true, PACKED_B_KW, M, K);
+    hipMemPool_t pool = nullptr;
+    char* ws = nullptr;
+    e = workspace_pool(dev, &pool);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync((void**)&ws, (size_t)bytes, pool, s);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MGEMM_ERR_ALLOC, "stream-ordered workspace for packed A");
+    }
+    e = launch_packed_b_ready(true, cfg, ta, d, ws, Bp->hi, Bp->lo, s);
+    const hipError_t e2 = hipFreeAsync(ws, s);
+    if (e == hipSuccess) e = e2;
+    return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
+}
+
+int mgemm_packed_b_destroy(mgemm_packed_b* Bp) {
+    {
+        std::lock_guard<std::mutex> lk(g_packed_mu);
+        if (!Bp || !g_packed.erase(Bp))
+            return fail(MGEMM_ERR_BAD_PLAN, "packed B is NULL or already destroyed");
+    }
+    hipError_t e = hipSuccess;
+    if (Bp->hi) e = hipFree(Bp->hi);   // waits for work still reading it
+    delete Bp;
+    return e == hipSuccess ? MGEMM_OK : hip_fail(e, "hipFree");
 }
 
 const char* mgemm_status_string(int status) {

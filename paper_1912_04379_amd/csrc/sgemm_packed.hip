@@ -307,4 +307,55 @@ hipError_t launch_packed(bool bf16x3, int cfg, bool ta, bool tb, const GemmDesc&
     });
 }
 
+// One packed operand: op(X) as P x K (P = M for A, N for B) in kw-deep
+// blocks, hi then lo (BF16x3), or the FP16 values (panel exponents `expo`).
+int64_t packed_operand_bytes(bool bf16x3, int kw, int64_t P, int64_t K) {
+    const int64_t kb = (K + kw - 1) / kw;
+    return (bf16x3 ? 2 : 1) * ((P + 31) / 32) * kb * 64LL * kw;
+}
+
+hipError_t launch_pack_operand(bool bf16x3, int kw, bool kcontig, const float* X, int64_t ld,
+                               int64_t P, int64_t K, char* hi, char* lo, const int* expo,
+                               hipStream_t s) {
+    if (kw != 16 && kw != 32) return hipErrorInvalidValue;
+    if (bf16x3)
+        return kw == 32 ? launch_pack<Form::BF16X3, 32>(kcontig, X, ld, P, K, hi, lo, nullptr, s)
+                        : launch_pack<Form::BF16X3, 16>(kcontig, X, ld, P, K, hi, lo, nullptr, s);
+    return kw == 32 ? launch_pack<Form::F16S, 32>(kcontig, X, ld, P, K, hi, nullptr, expo, s)
+                    : launch_pack<Form::F16S, 16>(kcontig, X, ld, P, K, hi, nullptr, expo, s);
+}
+
+int packed_config_kw(int cfg) {
+    return cfg >= 0 && cfg < PACKED_CONFIGS ? packed_kw(cfg) : 0;
+}
+
+// op(A) packed into a_ws (packed_operand_bytes(bf16x3, kw, M, K)), op(B)
+// already packed at b_hi / b_lo in the configuration's block depth; then
+// the main kernel.  d.B is not read.
+hipError_t launch_packed_b_ready(bool bf16x3, int cfg, bool ta, const GemmDesc& d, char* a_ws,
+                                 const char* b_hi, const char* b_lo, hipStream_t s) {
+    if (cfg < 0 || cfg >= PACKED_CONFIGS || !packed_fits(bf16x3, cfg)) return hipErrorInvalidValue;
+    const int kw = packed_kw(cfg);
+    const int64_t kb = (d.K + kw - 1) / kw, blk = 64LL * kw;
+    const int64_t pba = (d.M + 31) / 32, a = pba * kb * blk;
+    PackedArgs pk{};
+    pk.kb = kb;
+    pk.pb_a = pba;
+    pk.pb_b = (d.N + 31) / 32;
+    pk.a_hi = a_ws;
+    pk.a_lo = bf16x3 ? a_ws + a : nullptr;
+    pk.b_hi = b_hi;
+    pk.b_lo = b_lo;
+    hipError_t e = launch_pack_operand(bf16x3, kw, ta, d.A, d.lda, d.M, d.K, a_ws,
+                                       bf16x3 ? a_ws + a : nullptr, d.expA, s);
+    if (e != hipSuccess) return e;
+    return with_packed_cfg(cfg, [&](auto c) {
+        using C = decltype(c);
+        if constexpr (PackedStage<C, Form::BF16X3>::SMEM <= 160 * 1024) {
+            if (bf16x3) return launch_main<C, Form::BF16X3>(d, pk, s);
+        }
+        return launch_main<C, Form::F16S>(d, pk, s);
+    });
+}
+
 }  // namespace mgemm
