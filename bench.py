@@ -624,6 +624,16 @@ def bench_prepacked(args, mg, torch, n):
            "speedup": round(ms_call / ms_packed, 3), "pack_once_ms": round(ms_pack, 4)}
     log("pre-packed B bf16x3 %d^3: %.3f ms per call against %.3f (pack once %.3f ms)"
         % (n, ms_packed, ms_call, ms_pack))
+    # Scaled FP16: the handle also keeps op(B)'s panel exponents.
+    ms_f16 = timed(lambda: mg.sgemm("N", "N", n, n, n, 1.5, A, ld, B, ld, -0.5, C, ld,
+                                    precision="fp16s"), args.steps, args.warmup, stream)
+    with mg.PackedB("N", n, n, B, ld, precision="fp16s") as pf:
+        ms_f16p = timed(lambda: pf.sgemm("N", n, 1.5, A, ld, -0.5, C, ld), args.steps,
+                        args.warmup, stream)
+    out["fp16s"] = {"ordinary_ms": round(ms_f16, 4), "packed_b_ms": round(ms_f16p, 4),
+                    "packed_b_tflops": round(flops / ms_f16p / 1e9, 3),
+                    "speedup": round(ms_f16 / ms_f16p, 3)}
+    log("pre-packed B fp16s %d^3: %.3f ms per call against %.3f" % (n, ms_f16p, ms_f16))
     del A, B, C
     return out
 

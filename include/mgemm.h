@@ -249,12 +249,14 @@ int mgemm_grouped_tune(const mgemm_problem *problems, int64_t count,
  * whole operand and its result is kept, so a call with a packed B packs
  * only op(A).
  *
- * Built for MGEMM_PREC_BF16X3 only (the hi and lo bf16 halves of every
- * element, 4 bytes per element of op(B), K rounded up to 16 and N to 32);
- * other precisions return MGEMM_ERR_UNSUPPORTED.  Products run on the
- * pipelined packed 256 x 256 tile when there are at least 144 such tiles,
- * else on the pipelined 128 x 128 tile (16-bit configurations 10 and 11):
- * their results equal mgemm_sgemm_ex with the same configuration bitwise.
+ * Built for MGEMM_PREC_BF16X3 (the hi and lo bf16 halves of every
+ * element, 4 bytes per element of op(B), K rounded up to 16 and N to 32)
+ * and MGEMM_PREC_FP16_SCALED (2 bytes per element, scaled by the panel
+ * exponents of op(B), which the handle keeps); MGEMM_PREC_FP32 returns
+ * MGEMM_ERR_UNSUPPORTED.  Products run on the pipelined packed 256 x 256
+ * tile when there are at least 144 such tiles, else on the pipelined
+ * 128 x 128 tile (16-bit configurations 10 and 11): their results equal
+ * mgemm_sgemm_ex with the same precision and configuration bitwise.
  *
  * Argument errors are reported with the SGEMM number of the same argument
  * (transB -2, N -4, K -5, B -9, ldb -10; transA -1, M -3, A -7, lda -8,
@@ -280,8 +282,9 @@ int mgemm_packed_b_info(const mgemm_packed_b *Bp, int64_t *K, int64_t *N,
  * C <- alpha op(A) op(B) + beta C with op(B) from Bp (K and N are Bp's).
  * op(A) is M x K.  Same rules as mgemm_sgemm_ex for A, C, alpha, beta and
  * the quick returns; op(A) is packed into a stream-ordered workspace from
- * the library's pool (4 bytes per element).  Bp must stay alive until the
- * call's work has run.
+ * the library's pool (4 bytes per element for BF16x3, 2 for FP16, which
+ * also computes op(A)'s panel exponents there).  Bp must stay alive until
+ * the call's work has run.
  */
 int mgemm_sgemm_packed_b(char transA, int64_t M, float alpha, const float *A,
                          int64_t lda, const mgemm_packed_b *Bp, float beta,

@@ -361,8 +361,9 @@ struct mgemm_packed_b {
     int precision;
     int device;
     int64_t K, N;
-    char* hi;
-    char* lo;
+    char* hi;     // the allocation: packed values, then (FP16) exponents
+    char* lo;     // BF16x3 lo halves (NULL for FP16)
+    int* expB;    // FP16: panel exponents of op(B) (NULL for BF16x3)
     int64_t bytes;
 };
 
@@ -375,6 +376,15 @@ static constexpr int PACKED_B_BIG = 6, PACKED_B_SMALL = 7;
 
 static std::mutex g_packed_mu;
 static std::unordered_set<const mgemm_packed_b*> g_packed;
+
+static int64_t round256(int64_t b) { return (b + 255) / 256 * 256; }
+
+// FP16 exponent bytes for P rows (or columns) of panels: the exponents and
+// the pre-pass's partial maxima.
+static int64_t f16_exp_bytes(int64_t P, int64_t K) {
+    return round256((P + 31) / 32 * (int64_t)sizeof(int)) +
+           round256(f16_partial_floats(P, 0, K) * (int64_t)sizeof(float));
+}
 
 static bool packed_b_live(const mgemm_packed_b* p) {
     std::lock_guard<std::mutex> lk(g_packed_mu);
@@ -396,26 +406,40 @@ int mgemm_pack_b(char transB, int64_t K, int64_t N, const float* B, int64_t ldb,
     if (K > 0 && N > 0 && B == nullptr) return fail(-9, "B is NULL");
     const int64_t rows_b = tb ? N : K;
     if (ldb < (rows_b > 1 ? rows_b : 1)) return fail(-10, "ldb < max(1, stored rows of B)");
-    if (precision != MGEMM_PREC_BF16X3)
-        return fail(MGEMM_ERR_UNSUPPORTED, "pre-packed B is built for the BF16x3 form only");
-    if (!packed_supported(true, PACKED_B_BIG, 1, N, K) ||
-        !packed_supported(true, PACKED_B_SMALL, 1, N, K))
+    if (precision != MGEMM_PREC_BF16X3 && precision != MGEMM_PREC_FP16_SCALED)
+        return fail(MGEMM_ERR_UNSUPPORTED, "pre-packed B is built for the BF16x3 and FP16 forms");
+    const bool bf = precision == MGEMM_PREC_BF16X3;
+    if (!packed_supported(bf, PACKED_B_BIG, 1, N, K) ||
+        !packed_supported(bf, PACKED_B_SMALL, 1, N, K))
         return fail(MGEMM_ERR_UNSUPPORTED, "K too long for the packed engine's 32-bit offsets");
     int dev = 0;
     const int st = check_device(&dev);
     if (st) return st;
-    const int64_t bytes = packed_operand_bytes(true, PACKED_B_KW, N, K);
-    mgemm_packed_b* h = new mgemm_packed_b{precision, dev, K, N, nullptr, nullptr, bytes};
-    if (bytes > 0) {
+    const int64_t pack_bytes = packed_operand_bytes(bf, PACKED_B_KW, N, K);
+    const int64_t bytes = round256(pack_bytes) + (bf ? 0 : f16_exp_bytes(N, K));
+    mgemm_packed_b* h =
+        new mgemm_packed_b{precision, dev, K, N, nullptr, nullptr, nullptr, bytes};
+    if (N > 0 && bytes > 0) {
         hipError_t e = hipMalloc((void**)&h->hi, (size_t)bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             delete h;
             return fail(MGEMM_ERR_ALLOC, "packed B buffer");
         }
-        h->lo = h->hi + bytes / 2;
-        e = launch_pack_operand(true, PACKED_B_KW, !tb, B, ldb, N, K, h->hi, h->lo, nullptr,
-                                (hipStream_t)stream);
+        hipStream_t s = (hipStream_t)stream;
+        if (bf) {
+            h->lo = h->hi + pack_bytes / 2;
+        } else {
+            // op(B)'s panel exponents alone: the pre-pass with M = 0.
+            h->expB = reinterpret_cast<int*>(h->hi + round256(pack_bytes));
+            float* partial = reinterpret_cast<float*>(
+                h->hi + round256(pack_bytes) + round256((N + 31) / 32 * (int64_t)sizeof(int)));
+            const GemmDesc db{nullptr, B, nullptr, 0, N, K, 1, ldb, 1, 1.0f, 0.0f,
+                              nullptr, nullptr};
+            e = launch_f16_exponents(false, tb, db, nullptr, h->expB, partial, s);
+        }
+        if (e == hipSuccess)
+            e = launch_pack_operand(bf, PACKED_B_KW, !tb, B, ldb, N, K, h->hi, h->lo, h->expB, s);
         if (e != hipSuccess) {
             (void)hipFree(h->hi);
             delete h;
@@ -471,9 +495,11 @@ int mgemm_sgemm_packed_b(char transA, int64_t M, float alpha, const float* A, in
         e = launch_scale_c(d, s);
         return e == hipSuccess ? MGEMM_OK : hip_fail(e, "scale kernel launch");
     }
+    const bool bf = Bp->precision == MGEMM_PREC_BF16X3;
     const int64_t t256 = ((M + 255) / 256) * ((N + 255) / 256);
     const int cfg = t256 >= 144 ? PACKED_B_BIG : PACKED_B_SMALL;
-    const int64_t bytes = packed_operand_bytes(true, PACKED_B_KW, M, K);
+    const int64_t pack_bytes = round256(packed_operand_bytes(bf, PACKED_B_KW, M, K));
+    const int64_t bytes = pack_bytes + (bf ? 0 : f16_exp_bytes(M, K));
     hipMemPool_t pool = nullptr;
     char* ws = nullptr;
     e = workspace_pool(dev, &pool);
@@ -482,7 +508,19 @@ int mgemm_sgemm_packed_b(char transA, int64_t M, float alpha, const float* A, in
         (void)hipGetLastError();
         return fail(MGEMM_ERR_ALLOC, "stream-ordered workspace for packed A");
     }
-    e = launch_packed_b_ready(true, cfg, ta, d, ws, Bp->hi, Bp->lo, s);
+    if (!bf) {
+        // op(A)'s panel exponents alone (the pre-pass with N = 0); op(B)'s
+        // are the handle's.
+        int* expA = reinterpret_cast<int*>(ws + pack_bytes);
+        d.expA = expA;
+        d.expB = Bp->expB;
+        GemmDesc da = d;
+        da.N = 0;
+        float* partial = reinterpret_cast<float*>(
+            ws + pack_bytes + round256((M + 31) / 32 * (int64_t)sizeof(int)));
+        e = launch_f16_exponents(ta, false, da, expA, nullptr, partial, s);
+    }
+    if (e == hipSuccess) e = launch_packed_b_ready(bf, cfg, ta, d, ws, Bp->hi, Bp->lo, s);
     const hipError_t e2 = hipFreeAsync(ws, s);
     if (e == hipSuccess) e = e2;
     return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");

@@ -1,7 +1,7 @@
 """Pre-packed op(B): packed once by the library, reused by many products.
 
 Argument marshalling only: the packing and the products run in libmgemm
-(``mgemm_pack_b``, ``mgemm_sgemm_packed_b``; BF16x3 form).
+(``mgemm_pack_b``, ``mgemm_sgemm_packed_b``; BF16x3 and scaled-FP16 forms).
 """
 import ctypes
 

@@ -1,7 +1,8 @@
-"""Pre-packed op(B) (BF16x3): products with a packed B equal the ordinary
-BF16x3 call on the same packed configuration bitwise (the same packed
-values reach the same kernel), and the FP64 oracle within the BF16x3 bar;
-one handle serves several products."""
+"""Pre-packed op(B) (BF16x3 and scaled FP16): products with a packed B
+equal the ordinary call of the same form on the same packed configuration
+bitwise (the same packed values and exponents reach the same kernel), and
+the FP64 oracle within the form's bar (1e-5 BF16x3, 1e-3 FP16); one handle
+serves several products."""
 import numpy as np
 import pytest
 
@@ -13,6 +14,8 @@ from gpu_util import log, logical_c, oracle_args, to_dev
 pytestmark = pytest.mark.gpu
 
 TRANS = [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")]
+PRECS = ["bf16x3", "fp16s"]
+BAR = {"bf16x3": 1e-5, "fp16s": 1e-3}
 
 
 def packed_config(M, N):
@@ -21,72 +24,77 @@ def packed_config(M, N):
     return 10 if ((M + 255) // 256) * ((N + 255) // 256) >= 144 else 11
 
 
-def both(c):
-    """(result of the ordinary BF16x3 call, result with a packed B), whole
-    C buffers."""
+def both(c, prec):
+    """(result of the ordinary call, result with a packed B), whole C
+    buffers."""
     import torch
     A, B = to_dev(c["A"]), to_dev(c["B"])
     C1, C2 = to_dev(c["C"]), to_dev(c["C"])
     M, N, K = c["M"], c["N"], c["K"]
     mg.sgemm(c["transA"], c["transB"], M, N, K, float(c["alpha"]), A, c["lda"], B, c["ldb"],
-             float(c["beta"]), C1, c["ldc"], precision="bf16x3", config=packed_config(M, N))
-    with mg.PackedB(c["transB"], K, N, B, c["ldb"]) as pb:
+             float(c["beta"]), C1, c["ldc"], precision=prec, config=packed_config(M, N))
+    with mg.PackedB(c["transB"], K, N, B, c["ldb"], precision=prec) as pb:
         pb.sgemm(c["transA"], M, float(c["alpha"]), A, c["lda"], float(c["beta"]), C2, c["ldc"])
     torch.cuda.synchronize()
     return C1.cpu().numpy(), C2.cpu().numpy()
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("ta,tb", TRANS)
 @pytest.mark.parametrize("shape", [(300, 270, 77), (513, 257, 1000), (33, 65, 7), (1, 1, 1)])
-def test_equals_ordinary_call_and_oracle(ta, tb, shape):
+def test_equals_ordinary_call_and_oracle(prec, ta, tb, shape):
     M, N, K = shape
     c = synth.sgemm_case(51, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=3)
-    log("packed B %s %s%s" % (shape, ta, tb))
-    ref_buf, got_buf = both(c)
+    log("packed B %s %s %s%s" % (prec, shape, ta, tb))
+    ref_buf, got_buf = both(c, prec)
     assert np.array_equal(ref_buf, got_buf, equal_nan=True)
     err = oracle.normwise_rel_err(logical_c(got_buf, c), oracle.sgemm(*oracle_args(c)))
-    assert err <= 1e-5
+    assert err <= BAR[prec]
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "T")])
-def test_big_tile_equals_ordinary_call(ta, tb):
+def test_big_tile_equals_ordinary_call(prec, ta, tb):
     """3072 x 3072: 144 tiles of 256 x 256, the big packed tile."""
     c = synth.sgemm_case(52, ta, tb, 3072, 3072, 320, alpha=1.0, beta=0.0, pad=16)
-    log("packed B 3072^2 x 320 %s%s" % (ta, tb))
-    ref_buf, got_buf = both(c)
+    log("packed B %s 3072^2 x 320 %s%s" % (prec, ta, tb))
+    ref_buf, got_buf = both(c, prec)
     assert np.array_equal(ref_buf, got_buf, equal_nan=True)
 
 
-def test_one_handle_many_products():
+@pytest.mark.parametrize("prec", PRECS)
+def test_one_handle_many_products(prec):
     """One packed B, three products with different A (M 500, 100, 1);
     each equals the ordinary call."""
     import torch
     K, N = 700, 300
     cb = synth.sgemm_case(53, "N", "N", 8, N, K, pad=5)
     B = to_dev(cb["B"])
-    with mg.PackedB("N", K, N, B, cb["ldb"]) as pb:
+    with mg.PackedB("N", K, N, B, cb["ldb"], precision=prec) as pb:
         info = pb.info()
-        assert (info["K"], info["N"], info["precision"]) == (K, N, mg.PREC_BF16X3)
-        assert info["bytes"] == 2 * ((N + 31) // 32) * ((K + 15) // 16) * 64 * 16
+        assert (info["K"], info["N"], info["precision"]) == (K, N, mg.PRECISIONS[prec])
+        packed = ((N + 31) // 32) * ((K + 15) // 16) * 64 * 16 * (2 if prec == "bf16x3" else 1)
+        assert info["bytes"] == packed if prec == "bf16x3" else info["bytes"] > packed
         for i, M in enumerate((500, 100, 1)):
             ca = synth.sgemm_case(60 + i, "T", "N", M, N, K, alpha=0.75, beta=0.25, pad=2)
             A, C1, C2 = to_dev(ca["A"]), to_dev(ca["C"]), to_dev(ca["C"])
             mg.sgemm("T", "N", M, N, K, 0.75, A, ca["lda"], B, cb["ldb"], 0.25, C1, ca["ldc"],
-                     precision="bf16x3", config=packed_config(M, N))
+                     precision=prec, config=packed_config(M, N))
             pb.sgemm("T", M, 0.75, A, ca["lda"], 0.25, C2, ca["ldc"])
             torch.cuda.synchronize()
             log("packed B reuse M=%d" % M)
             assert torch.equal(C1, C2)
 
 
+@pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("K,alpha", [(0, 1.5), (40, 0.0)])
-def test_no_product_scales_c(K, alpha):
+def test_no_product_scales_c(prec, K, alpha):
     """K = 0 (a handle with no packed data) or alpha = 0: C <- beta C."""
     import torch
     c = synth.sgemm_case(54, "N", "N", 50, 40, K, alpha=alpha, beta=-2.0, pad=2)
     B = to_dev(c["B"]) if c["B"].size else torch.empty(1, device="cuda")
     C = to_dev(c["C"])
-    with mg.PackedB("N", K, 40, B, c["ldb"]) as pb:
+    with mg.PackedB("N", K, 40, B, c["ldb"], precision=prec) as pb:
         pb.sgemm("N", 50, alpha, to_dev(c["A"]) if c["A"].size else None, c["lda"], -2.0, C,
                  c["ldc"])
     torch.cuda.synchronize()
