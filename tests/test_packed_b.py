@@ -9,7 +9,7 @@ import pytest
 import oracle
 import synth
 import paper_1912_04379_amd as mg
-from gpu_util import log, logical_c, oracle_args, to_dev
+from gpu_util import full_check, log, logical_c, oracle_args, to_dev, wide_ldc_case
 
 pytestmark = pytest.mark.gpu
 
@@ -100,3 +100,14 @@ def test_no_product_scales_c(prec, K, alpha):
     torch.cuda.synchronize()
     got = logical_c(C.cpu().numpy(), c)
     assert np.array_equal(got, -2.0 * logical_c(c["C"], c).astype(np.float64))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_wide_ldc(prec):
+    """ldc above the 32-bit buffer path's limit: the packed kernel's 64-bit
+    epilogue; equal to the ordinary call and within the form's bar."""
+    c = wide_ldc_case(55, "T", "N", 300, 6, 200, alpha=1.5, beta=-0.5)
+    log("packed B %s wide ldc" % prec)
+    ref_buf, got_buf = both(c, prec)
+    assert np.array_equal(ref_buf, got_buf, equal_nan=True)
+    full_check(c, got_buf, bound_fn=None, normwise=BAR[prec])

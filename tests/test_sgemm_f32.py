@@ -116,6 +116,15 @@ def test_split_k(ta, tb, shape):
     full_check(c, run(c, config=11))
 
 
+def test_split_k_wide_ldc_runs_unsplit():
+    """ldc above the buffer path's limit with a long k range: split-K does
+    not apply (the 64-bit path runs 128 x 128 tiles) and the result is
+    still correct."""
+    c = wide_ldc_case(44, "N", "N", 200, 6, 5000, alpha=1.5, beta=-0.5)
+    log("f32 split-K wide ldc")
+    full_check(c, run(c, config=11))
+
+
 def test_split_k_beta_zero_ignores_nan_in_c():
     c = synth.sgemm_case(42, "N", "T", 190, 200, 6000, pad=2)
     c["C"] = np.where(c["C"] == synth.C_SENTINEL, c["C"], np.float32(np.nan)).astype(np.float32)
@@ -146,7 +155,7 @@ def test_big_tiles_whole_round_and_tail_sampled(ta, tb):
     sampled_check(c, run(c, config=10))
 
 
-@pytest.mark.parametrize("cfg", [-1, 1, 5, 8, 9, 10])
+@pytest.mark.parametrize("cfg", [-1, 1, 5, 8, 9, 10, 11])
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_leading_dimension_beyond_32bit_offsets(cfg, ta, tb):
     """ldc above 2**21 floats: the 64-bit address path runs, whichever
