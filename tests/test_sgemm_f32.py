@@ -208,6 +208,43 @@ def test_single_calls_captured_in_a_graph():
             assert torch.equal(C, ref), "replay %d differs from the eager result" % rep
 
 
+def test_split_k_captured_in_a_graph():
+    """Split-K takes its workspace stream-ordered from the library's pool
+    (hipMallocFromPoolAsync / hipFreeAsync), which a graph records as memory
+    nodes: a captured split-K call replayed three times, with eager work and
+    a synchronisation between replays, equals the eager result bitwise."""
+    import torch
+    from gpu_util import to_dev
+    c = synth.sgemm_case(45, "N", "T", 300, 270, 5000, alpha=1.5, beta=0.0, pad=3)
+    A, B, C = (to_dev(c[k]) for k in ("A", "B", "C"))
+
+    def call():
+        mg.sgemm(c["transA"], c["transB"], c["M"], c["N"], c["K"], 1.5, A, c["lda"], B,
+                 c["ldb"], 0.0, C, c["ldc"], config=11)
+
+    log("f32 split-K graph capture: eager")
+    call()
+    torch.cuda.synchronize()
+    eager = C.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        call()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    log("f32 split-K graph capture: capture")
+    with torch.cuda.graph(g):
+        call()
+    for rep in range(3):
+        C[:c["N"] * c["ldc"]].view(c["N"], c["ldc"])[:, :c["M"]].fill_(float("nan"))
+        torch.cuda.synchronize()
+        log("f32 split-K graph capture: replay %d" % rep)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(C, eager), "replay %d differs from the eager result" % rep
+
+
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_integer_inputs_bitwise(ta, tb):
     """Integer inputs in [-16, 16]: every partial sum is an exact integer in
