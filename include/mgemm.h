@@ -269,7 +269,7 @@ typedef struct mgemm_packed_b mgemm_packed_b;
  * major at ldb) on `stream`.  The handle owns hipMalloc'ed device memory on
  * the current device.  Packing is asynchronous on `stream`: calls on that
  * stream may use the handle at once; B may change once that work is done.
- * *out is NULL on any error.
+ * *out is NULL on any error; out == NULL returns MGEMM_ERR_UNSUPPORTED.
  */
 int mgemm_pack_b(char transB, int64_t K, int64_t N, const float *B, int64_t ldb,
                  int precision, void *stream, mgemm_packed_b **out);

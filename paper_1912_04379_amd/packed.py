@@ -48,6 +48,14 @@ class PackedB:
             check(lib().mgemm_packed_b_destroy(self._h))
         self._h = None
 
+    def __del__(self):
+        # A handle left open frees its device copy when collected (the
+        # library may already be unloaded at interpreter exit).
+        try:
+            self.close()
+        except Exception:
+            pass
+
     def __enter__(self):
         return self
 
