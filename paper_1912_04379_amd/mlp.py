@@ -87,8 +87,10 @@ class MLP:
         return loss, dWs
 
     def _backward_input(self, G, l, H):
+        # (G W_l^T) o (1 - H_{l-1}^2): the product in the library, the tanh
+        # derivative in one elementwise pass (torch's fused tanh backward).
         Gp = matmul(G, self.weights[l].t(), precision=self.precision)
-        return Gp.mul_(1.0 - H[l] * H[l])
+        return torch.ops.aten.tanh_backward(Gp, H[l])
 
     def step(self, X, T, lr):
         """One gradient-descent step on the batch (X, T); returns the loss
