@@ -8,17 +8,18 @@ namespace mgemm {
 
 // Default-configuration model.  A tile configuration that runs at `rate` once
 // every CU is busy delivers, on an M x N product, rate x (useful share of the
-// work-group slots it occupies): M*N over rounds x CUs x BM*BN, where a round
-// is one work-group per CU.  This counts both the CUs left idle in the last
-// round and the padding of edge tiles.  MI355X has 256 CUs.
+// work-group slots it occupies): M*N over rounds x slots x BM*BN, where a
+// round fills every slot once (one work-group per CU unless stated).  This
+// counts both the slots left idle in the last round and the padding of edge
+// tiles.  MI355X has 256 CUs.
 static constexpr int64_t NUM_CUS = 256;
 static int64_t tile_count(int64_t M, int64_t N, int bm, int bn) {
     return ((M + bm - 1) / bm) * ((N + bn - 1) / bn);
 }
-static double slot_share(int64_t M, int64_t N, int bm, int bn) {
-    const int64_t rounds = (tile_count(M, N, bm, bn) + NUM_CUS - 1) / NUM_CUS;
+static double slot_share(int64_t M, int64_t N, int bm, int bn, int64_t slots = NUM_CUS) {
+    const int64_t rounds = (tile_count(M, N, bm, bn) + slots - 1) / slots;
     return rounds == 0 ? 0.0
-                       : (double)M * (double)N / ((double)rounds * NUM_CUS * bm * bn);
+                       : (double)M * (double)N / ((double)rounds * slots * bm * bn);
 }
 
 int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
@@ -114,15 +115,27 @@ int bf16x3_default_config(int64_t M, int64_t N, int64_t K) {
     // 128x128 tile.  Pre-packing costs one extra read of A and B and a write
     // of their two halves: repaid once both M and N reach ~4.5k, where the
     // 256x256 tile wins if its tiles fill the chip evenly and K is deep
-    // enough for its longer prologue, and the 128x128 tile otherwise.  Below that the in-staging 256x256 tile is fastest on
-    // a chip's worth of its tiles; then, by tile count, packed 128x128 for
-    // deep products, in-staging 128x128 for shallow ones, in-staging 64x64
-    // below one round of 128x128 tiles.
+    // enough for its longer prologue, and the 128x128 tile otherwise.  Below
+    // that, from 144 tiles of 256x256, the in-staging 256x256 tile or the
+    // packed 128x128 tile by slot share; then, by tile count, packed 128x128
+    // for deep products, in-staging 128x128 for shallow ones, in-staging
+    // 64x64 below one round of 128x128 tiles.
     const int64_t t256 = tile_count(M, N, 256, 256), t128 = tile_count(M, N, 128, 128);
     if (t256 >= NUM_CUS && (M < N ? M : N) >= 4608 && K >= 512)
         return K >= 2048 && slot_share(M, N, 256, 256) >= 0.85 ? LOWP_INSTAGE_CONFIGS + 6
                                                                : LOWP_INSTAGE_CONFIGS + 7;
-    if (t256 >= 144) return 0;
+    if (t256 >= 144) {
+        // In-staging 256x256 (one work-group per CU, 400 TFLOP/s in full
+        // rounds) against the pipelined packed 128x128 (two per CU, 377), by
+        // slot share.  Measured: 6144 x 3072 x 3072, 288 tiles of 256x256
+        // (a round and an eighth), 258 against 339; 3072^2 x 8192, 144 tiles
+        // (one part-filled round for both), 300 against 293; 12288 x 1024 x
+        // 4096, 347 against 308.
+        if (K >= 512 && 377.0 * slot_share(M, N, 128, 128, 2 * NUM_CUS) >
+                            400.0 * slot_share(M, N, 256, 256))
+            return LOWP_INSTAGE_CONFIGS + 7;
+        return 0;
+    }
     if (t128 >= 192 && K >= 512) return LOWP_INSTAGE_CONFIGS + 7;
     if (t128 > NUM_CUS) return 1;
     return 3;
