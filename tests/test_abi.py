@@ -223,3 +223,32 @@ def test_tensor_extent_is_checked_before_any_call():
     # alpha == 0: A and B are not referenced, so an empty A is fine
     check_operands("N", "N", 64, 64, 64, 0.0, _FakeTensor(FA, 0), 64, _FakeTensor(FB, 0), 64,
                    _FakeTensor(FC, 4 * 64 * 64), 64)
+
+
+@pytest.mark.parametrize("shape,cfg", [
+    ((1024, 1024, 8192), 11), ((512, 512, 2048), 11), ((256, 256, 65536), 11),
+    ((1000, 1000, 4000), 11), ((2048, 2048, 4096), 11),
+    ((1024, 1024, 2048), None),      # pieces too short for 128 x 128 tiles
+    ((256, 256, 2048), 9),           # the small-product kernel
+    ((3072, 3072, 8192), None),      # more than one 128 x 128 tile per CU
+    ((8192, 8192, 8192), 8)])
+def test_fp32_default_rule_split_k(shape, cfg):
+    """The FP32 rule as documented: split-K (configuration 11) for at most one
+    128 x 128 tile per CU and a long enough k range; otherwise another
+    configuration."""
+    got = mg.default_config("fp32", "N", "N", *shape)
+    if cfg is None:
+        assert got != 11
+    else:
+        assert got == cfg
+
+
+@pytest.mark.parametrize("shape,cfg", [
+    ((6144, 3072, 3072), 11), ((3072, 6144, 2048), 11),   # 288 tiles of 256 x 256
+    ((4096, 4096, 4096), 0), ((12288, 1024, 4096), 0), ((3072, 3072, 8192), 0),
+    ((8192, 8192, 8192), 10)])
+def test_bf16x3_default_rule_slot_share(shape, cfg):
+    """From 144 tiles of 256 x 256 (below the pre-packing size), the
+    in-staging 256 x 256 tile (0) or the packed 128 x 128 tile (11) by slot
+    share; 8192^3 takes the pipelined packed 256 x 256 tile (10)."""
+    assert mg.default_config("bf16x3", "N", "N", *shape) == cfg
