@@ -15,6 +15,8 @@ Contents
   FP64 (an emulation of the split-precision form; not in the paper).
 * ``f16_exponents`` and ``f16_scaled``: power-of-two panel scaling into FP16
   and the scaled product, evaluated in FP64 (not in the paper).
+* ``bf16x3_entries`` / ``f16_scaled_entries``: single entries of the two
+  forms, for products too large to evaluate whole.
 * ``normwise_rel_err`` and ``elementwise_ratio``: error metrics.
 * ``dense_grads``: gradients of L = sum((X W) o G) for the dense layer.
 * ``mlp_forward`` / ``mlp_loss`` / ``mlp_grads`` / ``mlp_step``: one
@@ -198,6 +200,25 @@ def bf16x3(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C0, ldc):
     return out
 
 
+def _c0_entries(C0, ldc, rows, cols):
+    return np.asarray(C0)[np.asarray(rows, np.int64) + np.asarray(cols, np.int64) * ldc]
+
+
+def bf16x3_entries(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C0, ldc, rows, cols):
+    """Only the entries (rows[e], cols[e]) of ``bf16x3``, for products too
+    large to evaluate whole; the same operations on each entry."""
+    alpha, beta = float(np.float32(alpha)), float(np.float32(beta))
+    Ah, Al = _split_stored(A)
+    Bh, Bl = _split_stored(B)
+    e = lambda X, Y: sgemm_entries(transA, transB, M, N, K, 1.0, X, lda, Y, ldb, 0.0, None,
+                                   ldc, rows, cols)
+    s = e(Ah, Bh) + e(Ah, Bl) + e(Al, Bh)
+    out = alpha * s if (alpha != 0.0 and K > 0) else np.zeros(len(rows))
+    if beta != 0.0:
+        out = out + beta * _c0_entries(C0, ldc, rows, cols).astype(np.float64)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Scaled FP16 form: power-of-two scale per 32-row panel of op(A) and per
 # 32-column panel of op(B), taken over the whole K extent
@@ -248,26 +269,52 @@ def f16_exponents(transA, transB, M, N, K, A, lda, B, ldb):
     return eA, eB
 
 
+def _f16_quantised(transA, transB, M, N, K, A, lda, B, ldb):
+    """fp16(op(A) 2**eA) and fp16(op(B) 2**eB) as column-major float32
+    buffers (leading dimensions M and K), with the per-row exponents of
+    op(A) and per-column exponents of op(B).  fp16() rounds to nearest,
+    ties to even (numpy's float32 -> float16 conversion)."""
+    eA, eB = f16_exponents(transA, transB, M, N, K, A, lda, B, ldb)
+    rA = np.repeat(eA, PANEL)[:M]
+    cB = np.repeat(eB, PANEL)[:N]
+    opA = op_matrix(A, lda, transA, M, K)
+    opB = op_matrix(B, ldb, transB, K, N)
+    qA = (opA * np.exp2(rA)[:, None].astype(np.float32)).astype(np.float16)
+    qB = (opB * np.exp2(cB)[None, :].astype(np.float32)).astype(np.float16)
+    qa = np.asfortranarray(qA.astype(np.float32)).ravel(order="F")
+    qb = np.asfortranarray(qB.astype(np.float32)).ravel(order="F")
+    return qa, qb, rA, cB
+
+
 def f16_scaled(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C0, ldc):
     """alpha * 2**-(eA+eB) * fp16(op(A) 2**eA) fp16(op(B) 2**eB) + beta*C0,
-    products summed exactly in FP64.  fp16() rounds to nearest, ties to
-    even (numpy's float32 -> float16 conversion)."""
+    products summed exactly in FP64."""
     alpha, beta = float(np.float32(alpha)), float(np.float32(beta))
     out = np.zeros((M, N), dtype=np.float64, order="F")
     if alpha != 0.0 and K > 0 and M > 0 and N > 0:
-        eA, eB = f16_exponents(transA, transB, M, N, K, A, lda, B, ldb)
-        rA = np.repeat(eA, PANEL)[:M]
-        cB = np.repeat(eB, PANEL)[:N]
-        opA = op_matrix(A, lda, transA, M, K)
-        opB = op_matrix(B, ldb, transB, K, N)
-        qA = (opA * np.exp2(rA)[:, None].astype(np.float32)).astype(np.float16)
-        qB = (opB * np.exp2(cB)[None, :].astype(np.float32)).astype(np.float16)
-        qa = np.asfortranarray(qA.astype(np.float32)).ravel(order="F")
-        qb = np.asfortranarray(qB.astype(np.float32)).ravel(order="F")
+        qa, qb, rA, cB = _f16_quantised(transA, transB, M, N, K, A, lda, B, ldb)
         s = sgemm("N", "N", M, N, K, 1.0, qa, max(1, M), qb, max(1, K), 0.0, None, max(1, M))
         out = alpha * s * np.exp2(-(rA[:, None] + cB[None, :]).astype(np.float64))
     if beta != 0.0:
         out = out + beta * _logical(C0, ldc, M, N).astype(np.float64)
+    return out
+
+
+def f16_scaled_entries(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C0, ldc,
+                       rows, cols):
+    """Only the entries (rows[e], cols[e]) of ``f16_scaled`` (the exponents
+    still come from the whole panels); the same operations on each entry."""
+    alpha, beta = float(np.float32(alpha)), float(np.float32(beta))
+    rows = np.asarray(rows, np.int64)
+    cols = np.asarray(cols, np.int64)
+    out = np.zeros(rows.size, dtype=np.float64)
+    if alpha != 0.0 and K > 0 and M > 0 and N > 0:
+        qa, qb, rA, cB = _f16_quantised(transA, transB, M, N, K, A, lda, B, ldb)
+        s = sgemm_entries("N", "N", M, N, K, 1.0, qa, max(1, M), qb, max(1, K), 0.0, None,
+                          max(1, M), rows, cols)
+        out = alpha * s * np.exp2(-(rA[rows] + cB[cols]).astype(np.float64))
+    if beta != 0.0:
+        out = out + beta * _c0_entries(C0, ldc, rows, cols).astype(np.float64)
     return out
 
 

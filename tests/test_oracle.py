@@ -202,6 +202,21 @@ def test_entries_match_full_result():
     assert np.array_equal(part, full[r, cc])
 
 
+@pytest.mark.parametrize("form", ["bf16x3", "f16_scaled"])
+def test_form_entries_match_full_result(form):
+    """The entry-wise evaluations of the two forms equal the whole-matrix
+    ones bitwise, sampled corners and ragged panels included."""
+    full_fn = getattr(oracle, form)
+    part_fn = getattr(oracle, form + "_entries")
+    for ta, tb in TRANS:
+        c = synth.sgemm_case(16, ta, tb, 70, 41, 23, alpha=1.5, beta=-0.5, dist="loguni")
+        a = (ta, tb, 70, 41, 23, c["alpha"], c["A"], c["lda"], c["B"], c["ldb"], c["beta"],
+             c["C"], c["ldc"])
+        full = full_fn(*a)
+        r, cc = synth.sample_entries(1, 70, 41, 60)
+        assert np.array_equal(part_fn(*a, r, cc), full[r, cc])
+
+
 def test_dgemm_equals_sgemm_on_float32_values():
     c = synth.sgemm_case(15, "N", "T", 16, 18, 20, alpha=1.5, beta=-0.5)
     s = oracle.sgemm("N", "T", 16, 18, 20, c["alpha"], c["A"], c["lda"], c["B"], c["ldb"],

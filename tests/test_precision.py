@@ -1,19 +1,23 @@
 """BF16x3 and scaled-FP16 forms on the GPU against the FP64 oracle.
 
-Two checks per case:
+Three checks per case:
 * against the exact product: normwise error within the stated tolerance
   (BF16x3 <= 1e-5, FP16s <= 1e-3);
 * against the oracle's FP64 evaluation of the same form (same splits and
   scalings, exact sums): the difference must be pure FP32 accumulation
-  error, gamma_n |terms| elementwise.  A dropped or doubled correction
-  term, a wrong scale or a wrong rounding mode fails this by orders of
-  magnitude.
+  error, gamma_n |terms| elementwise (any order, any rounding inside the
+  MFMA), and, normwise, within the statistical bar of form_bars.stat_bar
+  for round-to-nearest accumulation.  A dropped correction term, a wrong
+  scale or a truncating conversion fails the elementwise bar by orders of
+  magnitude; a truncating split or a kept lo*lo (K <= 2048) fails the
+  statistical one.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
+from form_bars import stat_bar
 from gpu_util import log, logical_c, padding_untouched, run, sampled_check, wide_ldc_case
 
 # Tile configurations of the 16-bit forms: 0..3 split while staging, the
@@ -25,6 +29,7 @@ pytestmark = pytest.mark.gpu
 
 TRANS = [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")]
 FORMS = {"bf16x3": (oracle.bf16x3, 1e-5), "fp16s": (oracle.f16_scaled, 1e-3)}
+ENTRIES = {"bf16x3": oracle.bf16x3_entries, "fp16s": oracle.f16_scaled_entries}
 
 
 def args_of(c):
@@ -63,7 +68,16 @@ def check_form(c, prec, got_buf):
     bad = np.abs(got - emu) > bound
     assert not bad.any(), "%s differs from its FP64 emulation beyond FP32 rounding at %s" % (
         prec, np.argwhere(bad)[:4])
+    check_stat(prec, got, emu, c["K"])
     return err
+
+
+def check_stat(prec, got, emu, K):
+    """Normwise distance to the form's emulation within the statistical bar."""
+    d = oracle.normwise_rel_err(got, emu)
+    log("  %s vs emulation %.3e (%.2f of the bar)" % (prec, d, d / stat_bar(K)))
+    assert d <= stat_bar(K), "%s normwise %.3e from its emulation > bar %.3e" % (
+        prec, d, stat_bar(K))
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
@@ -97,11 +111,26 @@ def test_wide_range_inputs_2048(prec):
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
 def test_wide_range_inputs_8192_sampled(prec):
+    """The full-size precision-form product, in the launch the benchmark
+    times: sampled entries against the exact product (normwise) and against
+    the form's emulation (elementwise and statistical bars)."""
     c = synth.sgemm_case(0, "N", "N", 8192, 8192, 8192, dist="loguni")
     log("%s 8192^3 loguni (sampled)" % prec)
-    err = sampled_check(c, run(c, precision=prec), count=1500, bound_fn=None,
-                        normwise=FORMS[prec][1])
+    got_buf = run(c, precision=prec)
+    err = sampled_check(c, got_buf, count=1500, bound_fn=None, normwise=FORMS[prec][1])
     log("sampled normwise %.3e" % err)
+    rows, cols = synth.sample_entries(0, 8192, 8192, 1500)
+    got = got_buf.reshape(8192, c["ldc"])[cols, rows].astype(np.float64)
+    emu = ENTRIES[prec](*args_of(c), rows, cols)
+    if prec == "fp16s":
+        mag = ENTRIES[prec](*args_of(abs_case(c)), rows, cols)
+        nterms = c["K"] + 2
+    else:
+        a = abs_case(c)
+        mag = (1 + 2.0 ** -6) * oracle.sgemm_entries(*args_of(a), rows, cols)
+        nterms = 3 * c["K"] + 2
+    assert np.all(np.abs(got - emu) <= oracle.gamma(nterms, 2.0 ** -23) * mag)
+    check_stat(prec, got, emu, c["K"])
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
@@ -235,3 +264,43 @@ def test_workspace_pool_across_streams_and_trim(prec):
                 got = run(c, precision=prec, config=4, stream=0)
             check_form(c, prec, got)
         mg.trim_workspace()
+
+
+def test_fp16s_nan_in_a_row_reaches_that_row_only():
+    """A NaN in row i of op(A): its panel's exponent is 0 (reading of the
+    scale rule), row i of C is NaN, and every other row, including the rest
+    of that panel computed unscaled, matches the form's emulation."""
+    c = synth.sgemm_case(37, "N", "N", 150, 90, 120)
+    A = c["A"].copy()
+    A[40 + 7 * c["lda"]] = np.nan            # op(A)[40, 7], panel 1
+    c["A"] = A
+    log("fp16s NaN row")
+    got = logical_c(run(c, precision="fp16s"), c)
+    assert np.all(np.isnan(got[40, :]))
+    rest = np.r_[0:40, 41:150]
+    assert np.all(np.isfinite(got[rest, :]))
+    emu = oracle.f16_scaled(*args_of(c))
+    assert np.all(np.isnan(emu[40, :]))
+    mag = oracle.f16_scaled(*args_of(abs_case(c)))
+    bound = oracle.gamma(c["K"] + 2, 2.0 ** -23) * mag[rest, :]
+    assert np.all(np.abs(got[rest, :] - emu[rest, :]) <= bound)
+
+
+@pytest.mark.parametrize("ta", ["N", "T"])
+def test_fp16s_panel_grouping_on_subnormals(ta):
+    """op(A) 40 x 1 (K = 1), op(B) = [1 1]: rows 0-15 are 32, rows 16-39 are
+    a = 2^-25 (1 + 3*2^-10).  Rows 16-31 share the first 32-row panel with
+    the 32s, are scaled by 2^9 into FP16's subnormal range and round to
+    257 * 2^-24, so C = 2^-25 + 2^-33; rows 32-39 form the second panel,
+    scaled by 2^39, where a is an FP16 value, so C = a.  Each value is
+    worked out by hand and must be reproduced bitwise."""
+    a = np.float32(2.0 ** -25 * (1 + 3 * 2.0 ** -10))
+    Avals = np.array([32.0] * 16 + [a] * 24, dtype=np.float32)
+    want_col = np.array([32.0] * 16 + [2.0 ** -25 + 2.0 ** -33] * 16 + [float(a)] * 8)
+    c = dict(transA=ta, transB="N", M=40, N=2, K=1, alpha=np.float32(1), beta=np.float32(0),
+             A=Avals, lda=40 if ta == "N" else 1, B=np.ones(2, dtype=np.float32), ldb=1,
+             C=np.zeros(80, dtype=np.float32), ldc=40)
+    for cfg in (-1, 0, 4):
+        log("fp16s subnormal panels %s cfg %d" % (ta, cfg))
+        got = logical_c(run(c, precision="fp16s", config=cfg), c)
+        assert np.array_equal(got, np.stack([want_col, want_col], axis=1)), cfg
