@@ -175,6 +175,8 @@ def main():
                     help="skip the three paths on wide-range (2^U[-8,8]) inputs")
     ap.add_argument("--no-clock", action="store_true",
                     help="do not sample the engine clock with amd-smi")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the size sweep (all trans pairs) and the 2048^3 forms")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -283,7 +285,16 @@ def main():
     line["roofline"] = {"bound": "mfma", "achieved": round(f32["tflops"], 3),
                         "peak": PEAK["fp32"], "unit": "TFLOP/s",
                         "frac": round(f32["tflops"] / PEAK["fp32"], 4),
-                        "traffic": traffic}
+                        "traffic": traffic,
+                        "kernel": "sgemm_f32_kernel (one launch per step)",
+                        "source": "2MNK / ms_per_step: HIP events on the launch stream around "
+                                  "the K timed back-to-back launches (warm L2 and MALL)"}
+    if f32["cold_ms"]:
+        line["roofline"]["cold"] = {
+            "ms": round(f32["cold_ms"], 4), "achieved": round(flops / f32["cold_ms"] / 1e9, 3),
+            "frac": round(flops / f32["cold_ms"] / 1e9 / PEAK["fp32"], 4),
+            "source": "median of %d single launches, each after 512 MB are written "
+                      "(L2 and MALL flushed, the paper's cache-flushed method)" % args.cold_reps}
     if "bf16x3" in results:
         b = results["bf16x3"]
         line["bf16x3"] = {"tflops": round(b["tflops"], 3), "ms": round(b["ms"], 4),
@@ -315,6 +326,10 @@ def main():
         line["split_k"] = bench_splitk(args, mg, torch)
     if not (args.no_prepacked or args.no_forms):
         line["prepacked_b"] = bench_prepacked(args, mg, torch, n)
+    if not args.no_sweep:
+        line["config2"] = bench_sweep(args, mg, torch, oracle, synth)
+    if not (args.no_sweep or args.no_forms):
+        line["config3_2048"] = bench_forms_2048(args, mg, torch, oracle, synth)
 
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(oracle, case, n, alpha, beta, ld)
@@ -339,7 +354,45 @@ def cpu_baseline(oracle, case, n, alpha, beta, ld, target_s=12.0):
     return {"value": round(2.0 * n * n * J / dt / 1e12, 6), "unit": "TFLOP/s",
             "cores": oracle.num_threads(), "kind": "oracle",
             "sample": "FP64 oracle, columns 0..%d of the same %d^3 NN product "
-                      "(%d x %d outputs), %.1f s" % (J - 1, n, n, J, dt)}
+                      "(%d x %d outputs), %.1f s" % (J - 1, n, n, J, dt),
+            "host": host_info()}
+
+
+def host_info():
+    """The host the oracle ran on: CPU model, logical CPUs, the CPUs this
+    process may run on, and the oracle's OpenMP thread count."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for l in f:
+                if l.startswith("model name"):
+                    model = l.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": affinity,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
+def oracle_gflops(oracle, c, target_s=0.6):
+    """The FP64 oracle's rate on columns 0..J-1 of case c (J from a pilot
+    for about target_s seconds); the whole op(A) is still converted."""
+    M, N, K = c["M"], c["N"], c["K"]
+
+    def run(J):
+        t0 = time.perf_counter()
+        oracle.sgemm(c["transA"], c["transB"], M, J, K, c["alpha"], c["A"], c["lda"], c["B"],
+                     c["ldb"], c["beta"], c["C"], c["ldc"])
+        return time.perf_counter() - t0
+    pilot = min(N, 32)
+    t = run(pilot)
+    J = int(max(pilot, min(N, pilot * target_s / max(t, 1e-3))))
+    dt = run(J)
+    return round(2.0 * M * J * K / dt / 1e9, 3)
 
 
 def cpu_single_thread(oracle, synth, n=1024):
@@ -594,6 +647,77 @@ def bench_splitk(args, mg, torch):
             (M, N, K, res["default"]["tflops"], res["default_config"],
              res["unsplit_config_%d" % other]["tflops"]))
         del A, B, C
+    return out
+
+
+def bench_sweep(args, mg, torch, oracle, synth):
+    """The FP32 path over the sweep of square sizes {1000, 1024, 2048, 3001,
+    4096, 4097} in all four trans pairs: ld = stored rows + 16 (the fixed
+    stride of the paper's Section 4 method), alpha 1.5, beta -0.5, uniform
+    inputs from seed 0 (square operands, so one set of arrays serves every
+    trans pair).  Per product: warm TFLOP/s over a few launches, sampled
+    normwise error against the oracle; per size: the oracle's own rate on
+    this host."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    out = {"workload": "sgemm M=N=K in {1000,1024,2048,3001,4096,4097} x NN/NT/TN/TT, "
+                       "ld = rows + 16, alpha 1.5, beta -0.5, uniform[-1,1) seed 0"}
+    steps, warmup = max(5, args.steps // 2), 3
+    for n in (1000, 1024, 2048, 3001, 4096, 4097):
+        c = synth.sgemm_case(0, "N", "N", n, n, n, alpha=1.5, beta=-0.5)
+        ld = c["lda"]
+        A, B, C0 = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
+        C = C0.clone()
+        rows, cols = synth.sample_entries(3, n, n, 256)
+        res = {"oracle_gflops": oracle_gflops(oracle, c)}
+        for ta, tb in (("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")):
+            fn = lambda: mg.sgemm(ta, tb, n, n, n, 1.5, A, ld, B, ld, -0.5, C, ld)
+            C.copy_(C0)
+            fn()
+            torch.cuda.synchronize()
+            got = C.view(n, ld)[torch.from_numpy(cols).cuda(), torch.from_numpy(rows).cuda()]
+            ref = oracle.sgemm_entries(ta, tb, n, n, n, 1.5, c["A"], ld, c["B"], ld, -0.5, c["C"],
+                                       ld, rows, cols)
+            err = oracle.normwise_rel_err(got.double().cpu().numpy(), ref)
+            ms = timed(fn, steps, warmup, stream)
+            res[ta + tb] = {"ms": round(ms, 4), "tflops": round(2.0 * n ** 3 / ms / 1e9, 3),
+                            "normwise_err": float("%.3e" % err),
+                            "tile_config": mg.default_config("fp32", ta, tb, n, n, n)}
+        out[str(n)] = res
+        log("sweep %d: %s" % (n, " ".join("%s %.1f" % (k, v["tflops"]) for k, v in res.items()
+                                          if isinstance(v, dict))))
+        del A, B, C0, C
+    return out
+
+
+def bench_forms_2048(args, mg, torch, oracle, synth):
+    """The precision-form shapes at 2048^3: NN, ld 2064, alpha 1, beta 0,
+    sign-random magnitudes 2**U[-8, 8]; the three paths' time and sampled
+    normwise error, and the oracle's rate on the same product."""
+    n = 2048
+    c = synth.sgemm_case(0, "N", "N", n, n, n, dist="loguni")
+    ld = c["lda"]
+    A, B = torch.from_numpy(c["A"]).cuda(), torch.from_numpy(c["B"]).cuda()
+    C = torch.zeros(c["C"].size, dtype=torch.float32, device="cuda")
+    rows, cols = synth.sample_entries(4, n, n, 1024)
+    ref = oracle.sgemm_entries("N", "N", n, n, n, 1.0, c["A"], ld, c["B"], ld, 0.0, c["C"], ld,
+                               rows, cols)
+    stream = torch.cuda.current_stream()
+    out = {"workload": "sgemm NN 2048^3 ld 2064 alpha 1 beta 0, sign-random 2**U[-8,8], seed 0",
+           "oracle_gflops": oracle_gflops(oracle, c)}
+    for prec in ("fp32", "bf16x3", "fp16s"):
+        fn = lambda: mg.sgemm("N", "N", n, n, n, 1.0, A, ld, B, ld, 0.0, C, ld, precision=prec)
+        fn()
+        torch.cuda.synchronize()
+        got = C.view(n, ld)[torch.from_numpy(cols).cuda(), torch.from_numpy(rows).cuda()]
+        err = oracle.normwise_rel_err(got.double().cpu().numpy(), ref)
+        ms = timed(fn, max(10, args.steps), args.warmup, stream)
+        out[prec] = {"ms": round(ms, 4), "tflops": round(2.0 * n ** 3 / ms / 1e9, 3),
+                     "normwise_err": float("%.3e" % err)}
+    for prec in ("bf16x3", "fp16s"):
+        out[prec]["speedup_vs_fp32"] = round(out["fp32"]["ms"] / out[prec]["ms"], 3)
+    log("forms 2048^3: %s" % {k: v for k, v in out.items() if isinstance(v, dict)})
+    del A, B, C
     return out
 
 
