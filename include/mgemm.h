@@ -156,6 +156,21 @@ int mgemm_record_choice(int precision, char transA, char transB,
 /* Forget every recorded choice. */
 int mgemm_clear_choices(void);
 
+/*
+ * Persist the recorded single-call choices: mgemm_save_choices appends one
+ * line per choice, `mgemm-tune v1 single <arch> <cus> <version>
+ * <precision> <trans pair> <M> <N> <K> <config>`, stamped with the current
+ * device's architecture and CU count ("nodevice" and 0 when none is
+ * visible) and the library version; mgemm_load_choices records every line
+ * of the file that matches the current device and version (the last of
+ * several for one product wins) and writes how many to *loaded (may be
+ * NULL).  A file that cannot be written or read returns
+ * MGEMM_ERR_UNSUPPORTED.  The same file may hold grouped entries
+ * (mgemm_grouped_plan_create).
+ */
+int mgemm_save_choices(const char *path);
+int mgemm_load_choices(const char *path, int64_t *loaded);
+
 /* ---- many independent products in one persistent launch ---------------- */
 
 /*
@@ -177,25 +192,54 @@ typedef struct mgemm_plan mgemm_plan;
  * Build a plan for `count` problems (host array, copied).  Precision is
  * MGEMM_PREC_FP32 or MGEMM_PREC_BF16X3.  Every problem is validated with
  * the rules above; on failure the call returns MGEMM_ERR_BAD_PROBLEM with
- * *bad_index set to the problem and *bad_status to its BLAS-style code
- * (or MGEMM_ERR_ALIAS / MGEMM_ERR_UNSUPPORTED).  No C may overlap another
- * problem's C, A or B.  Leading dimensions must not exceed 2^21 - 64.
+ * *bad_index (may be NULL) set to the problem; mgemm_last_error() names
+ * the rule.  No C may overlap another problem's C, A or B.  Leading
+ * dimensions must not exceed 2^21 - 64.
+ *
  * Problems are sorted into four size buckets (mgemm_grouped_bucket); each
- * bucket uses one tile variant (0 .. mgemm_grouped_variant_count()-1) from
- * `bucket_configs` (4 entries, e.g. from mgemm_grouped_tune; NULL = the
- * library defaults, one variant for every bucket: FP32 64x64x16, BF16x3
- * 128x128).  The plan uploads to device memory it owns a
- * descriptor table and, per tile variant in use, a schedule: every tile
- * assigned to one work-group of that variant's persistent kernel, largest
- * tiles first, each to the least-loaded work-group.  It records the
- * launches (one per variant in use, costliest first) into a HIP graph on a
- * private stream; `stream` is unused and may be NULL.  Results are bitwise
- * reproducible: every tile of C is written by one work-group, no atomics.
+ * bucket uses one tile variant.  `tune_cache` chooses them:
+ *   - NULL: the library defaults (one variant for every bucket: FP32
+ *     64x64x16, BF16x3 128x128);
+ *   - a file path: the variants recorded in that file for this device
+ *     (architecture and CU count), library version, precision and batch
+ *     (the problems' trans flags and sizes, in order).  When the file has
+ *     no such entry (or does not exist), the batch is tuned on `stream` as
+ *     by mgemm_grouped_tune (best of 3 timed runs per assignment), with
+ *     every C saved before and restored after (device memory of the C
+ *     extents, freed before return), and the result is appended to the
+ *     file.  That first call synchronises `stream`; later calls only read
+ *     the file.  File format: lines of `mgemm-tune v1 grouped <arch>
+ *     <cus> <version> <precision> <batch hash> <c0>,<c1>,<c2>,<c3>`; the
+ *     last matching line wins; other lines are ignored.  A file that
+ *     cannot be written returns MGEMM_ERR_UNSUPPORTED.
+ * The paper sets its block sizes by experiment on the target machine
+ * (Section 3); the cache keeps such experiments across processes.
+ *
+ * The plan uploads to device memory it owns a descriptor table and, per
+ * tile variant in use, a schedule: every tile assigned to one work-group
+ * of that variant's persistent kernel, largest tiles first, each to the
+ * least-loaded work-group.  It records the launches (one per variant in
+ * use, costliest first) into a HIP graph on a private stream.  Results
+ * are bitwise reproducible: every tile of C is written by one work-group,
+ * no atomics.
  */
 int mgemm_grouped_plan_create(const mgemm_problem *problems, int64_t count,
-                              int precision, const int *bucket_configs,
+                              int precision, const char *tune_cache,
                               void *stream, mgemm_plan **out_plan,
-                              int64_t *bad_index, int *bad_status);
+                              int64_t *bad_index);
+
+/*
+ * The same with the variants given explicitly: `bucket_configs` holds 4
+ * entries (0 .. mgemm_grouped_variant_count()-1, e.g. from
+ * mgemm_grouped_tune; NULL = the library defaults), and on a bad problem
+ * *bad_status (may be NULL) also receives its BLAS-style code (or
+ * MGEMM_ERR_ALIAS / MGEMM_ERR_UNSUPPORTED).  `stream` is unused and may be
+ * NULL.
+ */
+int mgemm_grouped_plan_create_ex(const mgemm_problem *problems, int64_t count,
+                                 int precision, const int *bucket_configs,
+                                 void *stream, mgemm_plan **out_plan,
+                                 int64_t *bad_index, int *bad_status);
 
 /* Replay the plan's graph on `stream` (hipGraphLaunch). */
 int mgemm_grouped_plan_launch(mgemm_plan *plan, void *stream);

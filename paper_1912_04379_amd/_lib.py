@@ -55,9 +55,13 @@ _SIGS = {
     "mgemm_record_choice": (_i32, [_i32, _ch, _ch, _i64, _i64, _i64, _i32]),
     "mgemm_clear_choices": (_i32, []),
     "mgemm_trim_workspace": (_i32, []),
-    "mgemm_grouped_plan_create": (_i32, [ctypes.POINTER(Problem), _i64, _i32,
-                                         ctypes.POINTER(_i32), _vp, ctypes.POINTER(_vp),
-                                         ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
+    "mgemm_save_choices": (_i32, [ctypes.c_char_p]),
+    "mgemm_load_choices": (_i32, [ctypes.c_char_p, ctypes.POINTER(_i64)]),
+    "mgemm_grouped_plan_create": (_i32, [ctypes.POINTER(Problem), _i64, _i32, ctypes.c_char_p,
+                                         _vp, ctypes.POINTER(_vp), ctypes.POINTER(_i64)]),
+    "mgemm_grouped_plan_create_ex": (_i32, [ctypes.POINTER(Problem), _i64, _i32,
+                                            ctypes.POINTER(_i32), _vp, ctypes.POINTER(_vp),
+                                            ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
     "mgemm_grouped_plan_launch": (_i32, [_vp, _vp]),
     "mgemm_grouped_plan_run": (_i32, [_vp, _vp]),
     "mgemm_grouped_plan_info": (_i32, [_vp, ctypes.POINTER(_i64), ctypes.POINTER(_i64)]),

@@ -403,7 +403,8 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
     }
     if (starts.empty()) starts.push_back(0);
 
-    if (!live.empty())
+    if (fault_injected()) e = hipErrorOutOfMemory;
+    if (e == hipSuccess && !live.empty())
         e = hipMalloc((void**)&p->d_probs, live.size() * sizeof(GroupedProblem));
     if (e == hipSuccess && !sched.empty())
         e = hipMalloc((void**)&p->d_tiles, sched.size() * sizeof(TileRef));
@@ -465,9 +466,9 @@ int mgemm_grouped_variant_info(int precision, int variant, int* bm, int* bn, int
     return MGEMM_OK;
 }
 
-int mgemm_grouped_plan_create(const mgemm_problem* problems, int64_t count, int precision,
-                              const int* bucket_configs, void* stream, mgemm_plan** out_plan,
-                              int64_t* bad_index, int* bad_status) {
+int mgemm_grouped_plan_create_ex(const mgemm_problem* problems, int64_t count, int precision,
+                                 const int* bucket_configs, void* stream, mgemm_plan** out_plan,
+                                 int64_t* bad_index, int* bad_status) {
     (void)stream;
     mgemm_plan* p = nullptr;
     int st = build_plan(problems, count, precision, bucket_configs, out_plan ? &p : nullptr,
@@ -490,6 +491,101 @@ int mgemm_grouped_plan_create(const mgemm_problem* problems, int64_t count, int 
     plan_register(p);
     *out_plan = p;
     return MGEMM_OK;
+}
+
+}  // extern "C"
+
+namespace mgemm {
+
+// Runs the tuner on the batch with every C saved before and put back after
+// (the tuner runs the problems), on `s`; waits for `s`.
+static int tune_keeping_c(const mgemm_problem* problems, int64_t count, int precision,
+                          hipStream_t s, int* configs) {
+    std::vector<std::pair<int64_t, int64_t>> spans;   // (problem, bytes)
+    int64_t total = 0;
+    for (int64_t i = 0; i < count; ++i) {
+        const mgemm_problem& q = problems[i];
+        if (q.M <= 0 || q.N <= 0) continue;
+        const int64_t bytes = ((q.N - 1) * q.ldc + q.M) * (int64_t)sizeof(float);
+        spans.emplace_back(i, bytes);
+        total += (bytes + 255) / 256 * 256;
+    }
+    char* save = nullptr;
+    hipError_t e = hipSuccess;
+    if (total > 0) e = fault_injected() ? hipErrorOutOfMemory : hipMalloc((void**)&save, total);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(MGEMM_ERR_ALLOC, "device memory to keep C while tuning");
+    }
+    auto copy_all = [&](bool to_save) {
+        int64_t off = 0;
+        for (const auto& sp : spans) {
+            char* c = reinterpret_cast<char*>(problems[sp.first].C);
+            if (e == hipSuccess)
+                e = to_save ? hipMemcpyAsync(save + off, c, sp.second, hipMemcpyDeviceToDevice, s)
+                            : hipMemcpyAsync(c, save + off, sp.second, hipMemcpyDeviceToDevice, s);
+            off += (sp.second + 255) / 256 * 256;
+        }
+    };
+    copy_all(true);
+    int st = e == hipSuccess ? mgemm_grouped_tune(problems, count, precision, s, 3, configs, nullptr)
+                             : hip_err(e, "saving C");
+    copy_all(false);
+    const hipError_t e2 = hipStreamSynchronize(s);
+    if (save) (void)hipFree(save);
+    if (st == MGEMM_OK && (e != hipSuccess || e2 != hipSuccess))
+        st = hip_err(e != hipSuccess ? e : e2, "restoring C after tuning");
+    return st;
+}
+
+}  // namespace mgemm
+
+extern "C" {
+
+int mgemm_grouped_plan_create(const mgemm_problem* problems, int64_t count, int precision,
+                              const char* tune_cache, void* stream, mgemm_plan** out_plan,
+                              int64_t* bad_index) {
+    int bad_status = 0;
+    const char* source = tune_cache ? "cache" : "defaults";
+    int configs[NUM_BUCKETS];
+    const int* use = nullptr;
+    uint64_t key = 0;
+    if (tune_cache) {
+        key = batch_key(problems && count > 0 ? problems : nullptr, problems ? count : 0);
+        if (grouped_cache_lookup(tune_cache, precision, key, configs)) use = configs;
+    }
+    int st = mgemm_grouped_plan_create_ex(problems, count, precision, use, stream, out_plan,
+                                          bad_index, &bad_status);
+    if (st == MGEMM_OK && tune_cache && !use) {
+        // Not in the cache: tune now (keeping every C), store, and rebuild
+        // the plan if the tuned assignment differs from the defaults.
+        source = "tuned";
+        st = tune_keeping_c(problems, count, precision, (hipStream_t)stream, configs);
+        if (st == MGEMM_OK && !grouped_cache_store(tune_cache, precision, key, configs))
+            st = fail(MGEMM_ERR_UNSUPPORTED, std::string("cannot write ") + tune_cache);
+        bool same = true;
+        for (int b = 0; b < NUM_BUCKETS; ++b)
+            same &= configs[b] == (precision == MGEMM_PREC_FP32 ? DEFAULT_F32[b] : DEFAULT_LP[b]);
+        if (st == MGEMM_OK && !same) {
+            mgemm_grouped_plan_destroy(*out_plan);
+            *out_plan = nullptr;
+            st = mgemm_grouped_plan_create_ex(problems, count, precision, configs, stream,
+                                              out_plan, bad_index, &bad_status);
+        } else if (st != MGEMM_OK) {
+            const std::string why = mgemm_last_error();
+            mgemm_grouped_plan_destroy(*out_plan);
+            *out_plan = nullptr;
+            fail(st, why);
+        }
+        use = configs;
+    }
+    if (log_enabled())
+        log_line("grouped_plan_create precision=%d count=%lld tune_cache=%s source=%s "
+                 "configs=%d,%d,%d,%d status=%d%s%s",
+                 precision, (long long)count, tune_cache ? tune_cache : "(none)", source,
+                 use ? use[0] : -1, use ? use[1] : -1, use ? use[2] : -1, use ? use[3] : -1, st,
+                 st ? " " : "", st ? mgemm_last_error() : "");
+    return st;
 }
 
 int mgemm_grouped_plan_launch(mgemm_plan* plan, void* stream) {

@@ -3,7 +3,10 @@
 #pragma once
 #include <stdint.h>
 
+#include <functional>
 #include <string>
+
+#include "mgemm.h"
 
 namespace mgemm {
 
@@ -31,5 +34,43 @@ int config_count(int precision);
 
 // Configuration recorded by the tuner for exactly this product, or -1.
 int recorded_choice(int precision, int ta, int tb, int64_t M, int64_t N, int64_t K);
+
+// Every recorded single-call choice: fn(precision, ta, tb, M, N, K, config).
+void for_each_choice(
+    const std::function<void(int, int, int, int64_t, int64_t, int64_t, int)>& fn);
+
+// Tuning cache file (tune_cache.cpp): the current device's key, a grouped
+// batch's key, and lookup / append of a batch's bucket configurations.
+void device_key(std::string& arch, int& cus);
+uint64_t batch_key(const mgemm_problem* probs, int64_t count);
+bool grouped_cache_lookup(const char* path, int precision, uint64_t key, int* configs);
+bool grouped_cache_store(const char* path, int precision, uint64_t key, const int* configs);
+
+// A device buffer of `cap` bytes that a call uses as its workspace instead
+// of memory from the library's pool.  When `base` is NULL, `resolve` gives
+// it for the current device `dev` (called once the arguments have been
+// checked; returns MGEMM_OK or an error status).
+struct FixedWorkspace {
+    char* base;
+    int64_t cap;
+    int (*resolve)(int dev, char** base);
+};
+
+// The SGEMM entry points' common body: validation, quick returns,
+// configuration choice and launches.  `fixed` == nullptr takes workspace
+// from the pool; otherwise configurations whose workspace exceeds
+// fixed->cap run as they would without one (see mgemm_sgemm_ex_noalloc).
+int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
+               const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+               int64_t ldc, void* stream, int precision, int config,
+               const FixedWorkspace* fixed);
+
+// True when MGEMM_FAULT=alloc asks every workspace, packed-operand or plan
+// allocation to fail (a test hook for the MGEMM_ERR_ALLOC paths).
+bool fault_injected();
+
+// MGEMM_LOG: whether call logging is on, and one printf-style line of it.
+bool log_enabled();
+void log_line(const char* fmt, ...) __attribute__((format(printf, 1, 2)));
 
 }  // namespace mgemm

@@ -196,9 +196,37 @@ static int default_config(int precision, int ta, int tb, int64_t M, int64_t N, i
     }
 }
 
-static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
+// Workspace of one call: `fixed` (a device buffer of fixed->cap bytes that
+// the caller owns) when given, else stream-ordered memory from the pool.
+static hipError_t take_workspace(int dev, const FixedWorkspace* fixed, int64_t bytes,
+                                 hipStream_t s, char** out) {
+    if (fixed) {
+        if (bytes > fixed->cap) return hipErrorOutOfMemory;
+        *out = fixed->base;
+        return hipSuccess;
+    }
+    hipMemPool_t pool = nullptr;
+    hipError_t e = workspace_pool(dev, &pool);
+    if (e == hipSuccess) e = hipMallocFromPoolAsync((void**)out, (size_t)bytes, pool, s);
+    return e;
+}
+
+static hipError_t give_back_workspace(const FixedWorkspace* fixed, char* ws, hipStream_t s) {
+    return fixed || !ws ? hipSuccess : hipFreeAsync(ws, s);
+}
+
+// What one call did, for MGEMM_LOG.
+struct Dispatch {
+    const char* path = "none";   // quick return, or the kernels launched
+    int cfg = -1;
+    int splits = 0;
+    int64_t ws_bytes = 0;
+};
+
+static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
                       const float* A, int64_t lda, const float* B, int64_t ldb, float beta,
-                      float* C, int64_t ldc, void* stream, int precision, int config) {
+                      float* C, int64_t ldc, void* stream, int precision, int config,
+                      const FixedWorkspace* fixed, Dispatch& dp) {
     std::string why;
     const int bad = validate(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, why);
     if (bad) return fail(bad, why);
@@ -216,16 +244,27 @@ static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K,
     int dev = 0;
     int st = check_device(&dev);
     if (st) return st;
+    FixedWorkspace fx{};
+    if (fixed) {
+        fx = *fixed;
+        if (!fx.base && fx.resolve && (st = fx.resolve(dev, &fx.base)) != MGEMM_OK) return st;
+        if (!fx.base) return fail(MGEMM_ERR_UNSUPPORTED, "fixed workspace has no address");
+        fixed = &fx;
+    }
 
     hipStream_t s = (hipStream_t)stream;
     GemmDesc d{A, B, C, M, N, K, lda, ldb, ldc, alpha, beta, nullptr, nullptr};
     hipError_t e;
     if (no_product) {
+        dp.path = "scale_c";
         e = launch_scale_c(d, s);
         return e == hipSuccess ? MGEMM_OK : hip_fail(e, "scale kernel launch");
     }
     int cfg = config >= 0 ? config : default_config(precision, ta, tb, M, N, K);
+    dp.cfg = cfg;
+    dp.path = precision == MGEMM_PREC_FP32 ? "f32" : "in_staging";
     if (precision == MGEMM_PREC_FP32 && cfg == F32_TAIL_CONFIG) {
+        dp.path = buffer_path_ok(d) ? "f32_rounds_and_tail" : "f32_64bit_addresses";
         // The 64-bit address path has no split tail: 128 x 128 tiles.
         e = buffer_path_ok(d) ? launch_f32_tail(ta, tb, d, device_cus(dev), s)
                               : launch_f32(0, ta, tb, d, s);
@@ -237,20 +276,23 @@ static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K,
         const SplitKPlan plan = f32_splitk_plan(M, N, K, device_cus(dev));
         const int64_t bytes = f32_splitk_workspace_bytes(plan, M, N);
         if (plan.splits < 2 || !buffer_path_ok(d) || M > MAX_BUF_LD ||
-            bytes > F32_SPLITK_MAX_WORKSPACE) {
+            bytes > (fixed ? fixed->cap : F32_SPLITK_MAX_WORKSPACE)) {
+            dp.path = "f32_unsplit";
+            dp.cfg = 0;
             e = launch_f32(0, ta, tb, d, s);
             return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
         }
-        hipMemPool_t pool = nullptr;
-        float* ws = nullptr;
-        e = workspace_pool(dev, &pool);
-        if (e == hipSuccess) e = hipMallocFromPoolAsync((void**)&ws, (size_t)bytes, pool, s);
+        dp.path = "f32_split_k";
+        dp.splits = plan.splits;
+        dp.ws_bytes = bytes;
+        char* ws = nullptr;
+        e = fault_injected() ? hipErrorOutOfMemory : take_workspace(dev, fixed, bytes, s, &ws);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return fail(MGEMM_ERR_ALLOC, "stream-ordered split-K workspace");
         }
-        e = launch_f32_splitk(ta, tb, d, plan, ws, s);
-        const hipError_t e2 = hipFreeAsync(ws, s);
+        e = launch_f32_splitk(ta, tb, d, plan, reinterpret_cast<float*>(ws), s);
+        const hipError_t e2 = give_back_workspace(fixed, ws, s);
         if (e == hipSuccess) e = e2;
         return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
     }
@@ -272,14 +314,27 @@ static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K,
     const int64_t part_bytes = bf ? 0 : (f16_partial_floats(M, N, K) * 4 + 255) / 256 * 256;
     const int64_t exp_bytes =
         bf ? 0 : ((pa + pb) * (int64_t)sizeof(int) + 255) / 256 * 256 + part_bytes;
-    const int64_t pack_bytes =
+    int64_t pack_bytes =
         packed ? packed_workspace_bytes(bf, cfg - LOWP_INSTAGE_CONFIGS, M, N, K) : 0;
+    if (fixed && packed && exp_bytes + pack_bytes > fixed->cap) {
+        // The packed operands do not fit the fixed workspace: split (or
+        // scale) while staging instead, which needs no packed copy.
+        packed = false;
+        cfg = 0;
+        pack_bytes = 0;
+    }
+    if (fixed && exp_bytes > fixed->cap)
+        return fail(MGEMM_ERR_UNSUPPORTED,
+                    "the FP16 panel exponents need " + std::to_string(exp_bytes) +
+                        " bytes of workspace, more than the fixed " +
+                        std::to_string(fixed->cap));
+    dp.cfg = cfg;
+    dp.path = packed ? "packed" : "in_staging";
+    dp.ws_bytes = exp_bytes + pack_bytes;
     char* ws = nullptr;
     if (exp_bytes + pack_bytes > 0) {
-        hipMemPool_t pool = nullptr;
-        e = workspace_pool(dev, &pool);
-        if (e == hipSuccess)
-            e = hipMallocFromPoolAsync((void**)&ws, (size_t)(exp_bytes + pack_bytes), pool, s);
+        e = fault_injected() ? hipErrorOutOfMemory
+                             : take_workspace(dev, fixed, exp_bytes + pack_bytes, s, &ws);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return fail(MGEMM_ERR_ALLOC, "stream-ordered workspace");
@@ -300,10 +355,35 @@ static int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K,
             e = bf ? launch_bf16x3(cfg, ta, tb, d, s) : launch_f16s(cfg, ta, tb, d, s);
     }
     if (ws) {
-        hipError_t e2 = hipFreeAsync(ws, s);
+        hipError_t e2 = give_back_workspace(fixed, ws, s);
         if (e == hipSuccess) e = e2;
     }
     return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
+}
+
+static const char* prec_name(int precision) {
+    return precision == MGEMM_PREC_FP32           ? "fp32"
+           : precision == MGEMM_PREC_BF16X3       ? "bf16x3"
+           : precision == MGEMM_PREC_FP16_SCALED ? "fp16s"
+                                                  : "?";
+}
+
+int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
+               const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
+               int64_t ldc, void* stream, int precision, int config,
+               const FixedWorkspace* fixed) {
+    Dispatch dp;
+    const int st = sgemm_body(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                              stream, precision, config, fixed, dp);
+    if (log_enabled())
+        log_line("sgemm%s %s %c%c M=%lld N=%lld K=%lld lda=%lld ldb=%lld ldc=%lld alpha=%g "
+                 "beta=%g config=%d -> %s cfg=%d splits=%d workspace=%lld status=%d%s%s",
+                 fixed ? "_noalloc" : "", prec_name(precision), transA ? transA : '?',
+                 transB ? transB : '?', (long long)M, (long long)N, (long long)K,
+                 (long long)lda, (long long)ldb, (long long)ldc, (double)alpha, (double)beta,
+                 config, dp.path, dp.cfg, dp.splits, (long long)dp.ws_bytes, st,
+                 st ? " " : "", st ? g_last_error.c_str() : "");
+    return st;
 }
 
 }  // namespace mgemm
@@ -318,14 +398,14 @@ int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, float
                 const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
                 int64_t ldc, void* stream) {
     return sgemm_impl(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream,
-                      MGEMM_PREC_FP32, -1);
+                      MGEMM_PREC_FP32, -1, nullptr);
 }
 
 int mgemm_sgemm_ex(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
                    const float* A, int64_t lda, const float* B, int64_t ldb, float beta,
                    float* C, int64_t ldc, void* stream, int precision, int config) {
     return sgemm_impl(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream,
-                      precision, config);
+                      precision, config, nullptr);
 }
 
 int mgemm_config_count(int precision) { return config_count(precision); }
@@ -420,7 +500,8 @@ int mgemm_pack_b(char transB, int64_t K, int64_t N, const float* B, int64_t ldb,
     mgemm_packed_b* h =
         new mgemm_packed_b{precision, dev, K, N, nullptr, nullptr, nullptr, bytes};
     if (N > 0 && bytes > 0) {
-        hipError_t e = hipMalloc((void**)&h->hi, (size_t)bytes);
+        hipError_t e = fault_injected() ? hipErrorOutOfMemory
+                                        : hipMalloc((void**)&h->hi, (size_t)bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             delete h;
@@ -500,10 +581,8 @@ int mgemm_sgemm_packed_b(char transA, int64_t M, float alpha, const float* A, in
     const int cfg = t256 >= 144 ? PACKED_B_BIG : PACKED_B_SMALL;
     const int64_t pack_bytes = round256(packed_operand_bytes(bf, PACKED_B_KW, M, K));
     const int64_t bytes = pack_bytes + (bf ? 0 : f16_exp_bytes(M, K));
-    hipMemPool_t pool = nullptr;
     char* ws = nullptr;
-    e = workspace_pool(dev, &pool);
-    if (e == hipSuccess) e = hipMallocFromPoolAsync((void**)&ws, (size_t)bytes, pool, s);
+    e = fault_injected() ? hipErrorOutOfMemory : take_workspace(dev, nullptr, bytes, s, &ws);
     if (e != hipSuccess) {
         (void)hipGetLastError();
         return fail(MGEMM_ERR_ALLOC, "stream-ordered workspace for packed A");
@@ -521,7 +600,7 @@ int mgemm_sgemm_packed_b(char transA, int64_t M, float alpha, const float* A, in
         e = launch_f16_exponents(ta, false, da, expA, nullptr, partial, s);
     }
     if (e == hipSuccess) e = launch_packed_b_ready(bf, cfg, ta, d, ws, Bp->hi, Bp->lo, s);
-    const hipError_t e2 = hipFreeAsync(ws, s);
+    const hipError_t e2 = give_back_workspace(nullptr, ws, s);
     if (e == hipSuccess) e = e2;
     return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
 }

@@ -3,6 +3,7 @@
 // that fills it by timing every configuration on the caller's buffers.
 #include <hip/hip_runtime.h>
 
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -27,6 +28,16 @@ int recorded_choice(int precision, int ta, int tb, int64_t M, int64_t N, int64_t
 static void record(int precision, int ta, int tb, int64_t M, int64_t N, int64_t K, int cfg) {
     std::lock_guard<std::mutex> lk(g_choice_mu);
     g_choices[ChoiceKey{precision, ta, tb, M, N, K}] = cfg;
+}
+
+void for_each_choice(
+    const std::function<void(int, int, int, int64_t, int64_t, int64_t, int)>& fn) {
+    std::lock_guard<std::mutex> lk(g_choice_mu);
+    for (const auto& kv : g_choices) {
+        const ChoiceKey& k = kv.first;
+        fn(std::get<0>(k), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k),
+           std::get<5>(k), kv.second);
+    }
 }
 
 }  // namespace mgemm

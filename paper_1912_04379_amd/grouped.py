@@ -1,13 +1,10 @@
 """Many independent GEMMs in one persistent launch, replayed from a HIP graph.
 
-``GroupedPlan`` wraps mgemm_grouped_plan_* (argument marshalling only);
-``tune`` wraps the library's tuner (mgemm_grouped_tune) and keeps its
-answers in a JSON cache keyed by device, library version, precision and
-the exact batch shape.
+``GroupedPlan`` wraps mgemm_grouped_plan_* and ``tune`` the library's tuner
+(mgemm_grouped_tune); argument marshalling only.  Tuned choices persist in
+the library's own cache file (``tune_cache``), which it reads and writes.
 """
 import ctypes
-import hashlib
-import json
 import os
 
 from ._lib import PRECISIONS, MgemmError, Problem, check, lib
@@ -50,18 +47,28 @@ class GroupedPlan:
     float32 device tensors or device addresses; the tensors must outlive
     the plan)."""
 
-    def __init__(self, problems, precision="fp32", bucket_configs=None):
+    def __init__(self, problems, precision="fp32", bucket_configs=None, tune_cache=None,
+                 stream=None):
+        """bucket_configs: the four bucket variants (mgemm_grouped_plan_create_ex);
+        otherwise tune_cache (a path, or MGEMM_TUNE_CACHE from the
+        environment) lets the library read, or tune on `stream` and store,
+        them (mgemm_grouped_plan_create); neither: the library defaults."""
         self._problems = list(problems)     # keeps the tensors alive
         arr = _problem_array(self._problems)
-        cfg = None
-        if bucket_configs is not None:
-            cfg = (ctypes.c_int * NUM_BUCKETS)(*bucket_configs)
         plan = ctypes.c_void_p()
         bad = ctypes.c_int64(-1)
         bst = ctypes.c_int(0)
-        st = lib().mgemm_grouped_plan_create(arr, len(self._problems), _prec(precision), cfg,
-                                             None, ctypes.byref(plan), ctypes.byref(bad),
-                                             ctypes.byref(bst))
+        if bucket_configs is not None:
+            cfg = (ctypes.c_int * NUM_BUCKETS)(*bucket_configs)
+            st = lib().mgemm_grouped_plan_create_ex(arr, len(self._problems), _prec(precision),
+                                                    cfg, None, ctypes.byref(plan),
+                                                    ctypes.byref(bad), ctypes.byref(bst))
+        else:
+            cache = tune_cache if tune_cache is not None else os.environ.get("MGEMM_TUNE_CACHE")
+            st = lib().mgemm_grouped_plan_create(arr, len(self._problems), _prec(precision),
+                                                 cache.encode() if cache else None,
+                                                 stream_handle(stream) if cache else None,
+                                                 ctypes.byref(plan), ctypes.byref(bad))
         self.bad_index, self.bad_status = bad.value, bst.value
         check(st)
         self._plan = plan
@@ -103,46 +110,13 @@ class GroupedPlan:
             pass
 
 
-def _cache_key(problems, precision):
-    import torch
-    props = torch.cuda.get_device_properties(torch.cuda.current_device())
-    shape = [(p["transA"], p["transB"], p["M"], p["N"], p["K"]) for p in problems]
-    digest = hashlib.sha1(json.dumps(shape).encode()).hexdigest()[:16]
-    arch = getattr(props, "gcnArchName", "gpu")
-    return "%s|%d|%d|%s|%s" % (arch, props.multi_processor_count, lib().mgemm_version(),
-                               precision, digest)
-
-
-def tune(problems, precision="fp32", reps=3, stream=None, cache=None):
-    """Bucket configurations for this batch: from the cache when present,
-    else measured by the library's tuner (which RUNS the problems and leaves
-    every C with unspecified contents) and stored.  Returns (configs, ms);
-    ms is None on a cache hit."""
-    cache = cache if cache is not None else os.environ.get("MGEMM_TUNE_CACHE")
-    key = _cache_key(problems, precision) if cache else None
-    if cache and os.path.exists(cache):
-        try:
-            entry = json.load(open(cache)).get(key)
-        except (OSError, ValueError):
-            entry = None
-        if entry:
-            return list(entry["bucket_configs"]), None
+def tune(problems, precision="fp32", reps=3, stream=None):
+    """Bucket configurations for this batch, measured by the library's tuner
+    (which RUNS the problems and leaves every C with unspecified contents).
+    Returns (configs, best milliseconds)."""
     arr = _problem_array(problems)
     cfg = (ctypes.c_int * NUM_BUCKETS)()
     ms = ctypes.c_float()
     check(lib().mgemm_grouped_tune(arr, len(problems), _prec(precision), stream_handle(stream),
                                    reps, cfg, ctypes.byref(ms)))
-    configs = list(cfg)
-    if cache:
-        data = {}
-        if os.path.exists(cache):
-            try:
-                data = json.load(open(cache))
-            except (OSError, ValueError):
-                data = {}
-        data[key] = {"bucket_configs": configs, "ms": ms.value}
-        tmp = cache + ".tmp%d" % os.getpid()
-        with open(tmp, "w") as f:
-            json.dump(data, f, indent=1, sort_keys=True)
-        os.replace(tmp, cache)
-    return configs, ms.value
+    return list(cfg), ms.value

@@ -252,3 +252,33 @@ def test_bf16x3_default_rule_slot_share(shape, cfg):
     in-staging 256 x 256 tile (0) or the packed 128 x 128 tile (11) by slot
     share; 8192^3 takes the pipelined packed 256 x 256 tile (10)."""
     assert mg.default_config("bf16x3", "N", "N", *shape) == cfg
+
+
+def test_choices_round_trip_through_a_cache_file(tmp_path):
+    """Recorded single-call choices are saved to a file stamped with the
+    device key ("nodevice" 0 without a GPU) and the library version, and
+    loaded back into an empty table; lines for another device or version,
+    and lines that are not entries, are ignored."""
+    L = mg.lib()
+    path = str(tmp_path / "tune.txt").encode()
+    L.mgemm_clear_choices()
+    assert L.mgemm_record_choice(0, b"N", b"T", 777, 555, 333, 2) == 0
+    assert L.mgemm_record_choice(1, b"T", b"N", 640, 320, 4096, 5) == 0
+    assert L.mgemm_save_choices(path) == 0
+    lines = open(path).read().splitlines()
+    assert len(lines) == 2
+    assert all(l.startswith("mgemm-tune v1 single ") for l in lines)
+    with open(path, "a") as f:
+        f.write("mgemm-tune v1 single otherarch 8 %d 0 NN 777 555 333 4\n" % mg.version())
+        f.write("mgemm-tune v1 single %s 0 99999 0 NN 1 2 3 1\n" % lines[0].split()[3])
+        f.write("# a comment line\nrubbish\n")
+    L.mgemm_clear_choices()
+    assert L.mgemm_default_config(0, b"N", b"T", 777, 555, 333) != 2
+    n = ctypes.c_int64(-1)
+    assert L.mgemm_load_choices(path, ctypes.byref(n)) == 0
+    assert n.value == 2
+    assert L.mgemm_default_config(0, b"N", b"T", 777, 555, 333) == 2
+    assert L.mgemm_default_config(1, b"T", b"N", 640, 320, 4096) == 5
+    L.mgemm_clear_choices()
+    assert L.mgemm_load_choices(str(tmp_path / "missing.txt").encode(), None) == \
+        _lib.ERR_UNSUPPORTED

@@ -8,6 +8,7 @@ import pytest
 import oracle
 import paper_1912_04379_amd as mg
 import synth
+from form_bars import stat_bar
 from paper_1912_04379_amd import _lib
 from paper_1912_04379_amd import grouped as gp
 
@@ -24,9 +25,9 @@ def create(problems, precision=0, configs=None):
     cfg = (ctypes.c_int * 4)(*configs) if configs else None
     plan = ctypes.c_void_p()
     bad, bst = ctypes.c_int64(), ctypes.c_int()
-    st = mg.lib().mgemm_grouped_plan_create(arr, len(problems), precision, cfg, None,
-                                            ctypes.byref(plan), ctypes.byref(bad),
-                                            ctypes.byref(bst))
+    st = mg.lib().mgemm_grouped_plan_create_ex(arr, len(problems), precision, cfg, None,
+                                               ctypes.byref(plan), ctypes.byref(bad),
+                                               ctypes.byref(bst))
     return st, bad.value, bst.value
 
 
@@ -116,6 +117,14 @@ def check_batch(problems, data, out_host, precision, tol):
         if precision == "fp32":
             bound = oracle.gamma(p["K"] + 2, 2.0 ** -23) * oracle.abs_product(*args)
             assert np.all(np.abs(got - ref) <= bound)
+        else:
+            # Against the split form's FP64 emulation: FP32 accumulation
+            # error only, elementwise and (statistically) normwise.
+            emu = oracle.bf16x3(*args)
+            bound = oracle.gamma(3 * p["K"] + 2, 2.0 ** -23) * (1 + 2.0 ** -6) * \
+                oracle.abs_product(*args)
+            assert np.all(np.abs(got - emu) <= bound)
+            assert oracle.normwise_rel_err(got, emu) <= stat_bar(p["K"])
     return worst
 
 
@@ -216,20 +225,53 @@ def test_edge_problems_in_a_batch():
 
 
 @pytest.mark.gpu
-def test_tuner_returns_valid_configs_and_plan_stays_correct(tmp_path):
+def test_tuner_returns_valid_configs_and_plan_stays_correct():
     import torch
     problems, data, arena, host = make_batch(count=64, seed=11)
     init = torch.from_numpy(host).cuda()
-    cache = str(tmp_path / "tune.json")
-    cfg, ms = mg.tune_grouped(problems, "fp32", reps=2, cache=cache)
+    cfg, ms = mg.tune_grouped(problems, "fp32", reps=2)
     assert len(cfg) == 4 and all(0 <= c < 3 for c in cfg) and ms > 0
-    cfg2, ms2 = mg.tune_grouped(problems, "fp32", cache=cache)      # cache hit
-    assert cfg2 == cfg and ms2 is None
     arena.copy_(init)
     with mg.GroupedPlan(problems, "fp32", bucket_configs=cfg) as plan:
         plan.launch()
         torch.cuda.synchronize()
     check_batch(problems, data, arena.cpu().numpy(), "fp32", 1e-5)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_tune_cache_through_the_c_abi(tmp_path, monkeypatch, precision):
+    """A plan made with a tune_cache path: the first call tunes (every C is
+    kept as it was) and appends the choice for this device, version,
+    precision and batch; the second reads it back without tuning; the plan
+    computes the batch correctly."""
+    import torch
+    print("tune cache", precision, flush=True)
+    problems, data, arena, host = make_batch(count=48, seed=12)
+    init = torch.from_numpy(host).cuda()
+    arena.copy_(init)
+    cache = tmp_path / "tune.txt"
+    log = tmp_path / "mgemm.log"
+    monkeypatch.setenv("MGEMM_LOG", str(log))
+    plan = mg.GroupedPlan(problems, precision, tune_cache=str(cache))
+    torch.cuda.synchronize()
+    assert torch.equal(arena, init), "tuning left a C changed"
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    f = lines[0].split()
+    assert f[:3] == ["mgemm-tune", "v1", "grouped"] and f[3].startswith("gfx950")
+    assert int(f[4]) == torch.cuda.get_device_properties(0).multi_processor_count
+    assert int(f[5]) == mg.version() and int(f[6]) == mg.PRECISIONS[precision]
+    configs = [int(v) for v in f[8].split(",")]
+    plan.close()
+    plan = mg.GroupedPlan(problems, precision, tune_cache=str(cache))
+    assert len(cache.read_text().splitlines()) == 1          # read, not tuned again
+    text = log.read_text()
+    assert "source=tuned" in text and "source=cache configs=%d,%d,%d,%d" % tuple(configs) in text
+    plan.launch()
+    torch.cuda.synchronize()
+    plan.close()
+    check_batch(problems, data, arena.cpu().numpy(), precision, 1e-5)
 
 
 @pytest.mark.gpu
