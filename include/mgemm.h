@@ -111,6 +111,38 @@ int mgemm_sgemm_ex(char transA, char transB, int64_t M, int64_t N, int64_t K,
                    int precision, int config);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as mgemm_sgemm_ex, arguments and results alike, whose workspace is
+ * a device array of MGEMM_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every GPU it runs on, from load until the process ends.  The call makes
+ * no hipMalloc, hipFree or pool allocation; its device address is looked
+ * up once per device, on the first call there.
+ *
+ * The array is shared by every call on one GPU and keeps what the last call
+ * left in it (nothing needs it cleared: every call writes what it reads).
+ * Calls that overlap in time on one GPU -- on different streams, or from
+ * different threads -- race on it and give wrong results; serialise them
+ * (one stream, or events).
+ *
+ * Workspace beyond the array: a named `config` whose workspace exceeds it
+ * (FP32 configuration 11 with S*M*N*4 bytes of partial products, a packed
+ * 16-bit configuration with its packed operands) returns
+ * MGEMM_ERR_UNSUPPORTED and launches nothing; with config = -1 the library
+ * takes its usual choice when it fits, else a configuration that needs
+ * less (FP32 unsplit tiles; 16-bit operands split or scaled while staging,
+ * configuration 0).  Scaled FP16 always needs its panel exponents and
+ * partial maxima (about (M+N)/32 * (4 + 4*ceil(K/2048)) bytes); a product
+ * whose exponents exceed the array returns MGEMM_ERR_UNSUPPORTED.
+ */
+#define MGEMM_NOALLOC_SCRATCH_BYTES (64LL << 20)
+int mgemm_sgemm_ex_noalloc(char transA, char transB, int64_t M, int64_t N,
+                           int64_t K, float alpha, const float *A,
+                           int64_t lda, const float *B, int64_t ldb,
+                           float beta, float *C, int64_t ldc, void *stream,
+                           int precision, int config);
+
+/*
  * Return the memory the workspace pools keep (freed workspaces of earlier
  * 16-bit calls) to the device.  Calls still in flight keep theirs.
  */

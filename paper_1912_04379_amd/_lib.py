@@ -24,6 +24,8 @@ ERR_UNSUPPORTED = 106
 ERR_BAD_PLAN = 107
 ERR_BAD_PROBLEM = 108
 
+NOALLOC_SCRATCH_BYTES = 64 << 20   # MGEMM_NOALLOC_SCRATCH_BYTES
+
 # The exported functions and their C signatures (kept in step with
 # include/mgemm.h; the ABI test checks every declared name resolves).
 _i64, _i32, _f32, _vp, _ch = (ctypes.c_int64, ctypes.c_int, ctypes.c_float,
@@ -45,6 +47,8 @@ _SIGS = {
                            _i64, _vp]),
     "mgemm_sgemm_ex": (_i32, [_ch, _ch, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32,
                               _vp, _i64, _vp, _i32, _i32]),
+    "mgemm_sgemm_ex_noalloc": (_i32, [_ch, _ch, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64,
+                                      _f32, _vp, _i64, _vp, _i32, _i32]),
     "mgemm_config_count": (_i32, [_i32]),
     "mgemm_config_info": (_i32, [_i32, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32),
                                  ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),

@@ -215,6 +215,12 @@ static hipError_t give_back_workspace(const FixedWorkspace* fixed, char* ws, hip
     return fixed || !ws ? hipSuccess : hipFreeAsync(ws, s);
 }
 
+// Error text of a call whose workspace exceeds a fixed workspace.
+static std::string too_big(int64_t bytes, int64_t cap, const char* what) {
+    return std::string("the ") + what + " need " + std::to_string(bytes) +
+           " bytes of workspace, more than the fixed " + std::to_string(cap);
+}
+
 // What one call did, for MGEMM_LOG.
 struct Dispatch {
     const char* path = "none";   // quick return, or the kernels launched
@@ -275,8 +281,10 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
         // not apply (short k, 64-bit address path), 128 x 128 tiles.
         const SplitKPlan plan = f32_splitk_plan(M, N, K, device_cus(dev));
         const int64_t bytes = f32_splitk_workspace_bytes(plan, M, N);
-        if (plan.splits < 2 || !buffer_path_ok(d) || M > MAX_BUF_LD ||
-            bytes > (fixed ? fixed->cap : F32_SPLITK_MAX_WORKSPACE)) {
+        const bool applies = plan.splits >= 2 && buffer_path_ok(d) && M <= MAX_BUF_LD;
+        if (fixed && config >= 0 && applies && bytes > fixed->cap)
+            return fail(MGEMM_ERR_UNSUPPORTED, too_big(bytes, fixed->cap, "split-K partial products"));
+        if (!applies || bytes > (fixed ? fixed->cap : F32_SPLITK_MAX_WORKSPACE)) {
             dp.path = "f32_unsplit";
             dp.cfg = 0;
             e = launch_f32(0, ta, tb, d, s);
@@ -317,17 +325,18 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
     int64_t pack_bytes =
         packed ? packed_workspace_bytes(bf, cfg - LOWP_INSTAGE_CONFIGS, M, N, K) : 0;
     if (fixed && packed && exp_bytes + pack_bytes > fixed->cap) {
-        // The packed operands do not fit the fixed workspace: split (or
-        // scale) while staging instead, which needs no packed copy.
+        // The packed operands do not fit the fixed workspace.  A named
+        // configuration is refused; the library's choice splits (or
+        // scales) while staging instead, which needs no packed copy.
+        if (config >= 0)
+            return fail(MGEMM_ERR_UNSUPPORTED,
+                        too_big(exp_bytes + pack_bytes, fixed->cap, "packed operands"));
         packed = false;
         cfg = 0;
         pack_bytes = 0;
     }
     if (fixed && exp_bytes > fixed->cap)
-        return fail(MGEMM_ERR_UNSUPPORTED,
-                    "the FP16 panel exponents need " + std::to_string(exp_bytes) +
-                        " bytes of workspace, more than the fixed " +
-                        std::to_string(fixed->cap));
+        return fail(MGEMM_ERR_UNSUPPORTED, too_big(exp_bytes, fixed->cap, "FP16 panel exponents"));
     dp.cfg = cfg;
     dp.path = packed ? "packed" : "in_staging";
     dp.ws_bytes = exp_bytes + pack_bytes;
