@@ -1,8 +1,9 @@
 // defaults.cpp -- built-in tile-configuration rules for single calls, used
-// when no measured choice is recorded for the product.  Host code only.
+// when no measured choice is recorded for the product, and the split-K
+// plan.  Host code only, free of HIP (rules.hpp).
 #include <stdint.h>
 
-#include "kernels.hpp"
+#include "rules.hpp"
 
 namespace mgemm {
 
@@ -20,6 +21,32 @@ static double slot_share(int64_t M, int64_t N, int bm, int bn, int64_t slots = N
     const int64_t rounds = (tile_count(M, N, bm, bn) + slots - 1) / slots;
     return rounds == 0 ? 0.0
                        : (double)M * (double)N / ((double)rounds * slots * bm * bn);
+}
+
+// Split-K plan: 128 x 128 tiles when there are at least CUs/4 of them,
+// else 64 x 64; S pieces of kc (a multiple of 32).
+SplitKPlan f32_splitk_plan(int64_t M, int64_t N, int64_t K, int cus) {
+    SplitKPlan p{0, 0, 0};
+    if (M < 1 || N < 1 || K < 1 || cus < 1) return p;
+    const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128);
+    const int64_t t64 = ((M + 63) / 64) * ((N + 63) / 64);
+    p.small_tile = t128 * 4 >= cus ? 0 : 1;
+    const int64_t tiles = p.small_tile ? t64 : t128;
+    // About two work-groups per CU, pieces of at least 256 k.
+    int64_t s = (2 * (int64_t)cus + tiles - 1) / tiles;
+    if (s > 32) s = 32;
+    int64_t kc = (K + s - 1) / s;
+    kc = (kc + 31) / 32 * 32;
+    if (kc < 256) kc = 256;
+    s = (K + kc - 1) / kc;
+    if (s < 2 || tiles * s > 0xffffffffLL) return p;
+    p.splits = (int)s;
+    p.kc = kc;
+    return p;
+}
+
+int64_t f32_splitk_workspace_bytes(const SplitKPlan& p, int64_t M, int64_t N) {
+    return (int64_t)p.splits * M * N * 4;
 }
 
 int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {

@@ -21,7 +21,6 @@
 
 #include <algorithm>
 #include <mutex>
-#include <queue>
 #include <utility>
 #include <string>
 #include <tuple>
@@ -30,6 +29,7 @@
 
 #include "host_common.hpp"
 #include "mgemm.h"
+#include "rules.hpp"
 #include "tile_f32.hpp"
 #include "tile_lowp.hpp"
 
@@ -221,16 +221,6 @@ static hipError_t launch_plan_kernel(const mgemm_plan* p, hipStream_t s) {
     return hipGetLastError();
 }
 
-struct Interval {
-    uintptr_t lo, hi;
-    int64_t owner;
-};
-
-static void extent_of(const void* ptr, int64_t rows, int64_t cols, int64_t ld, Interval& iv) {
-    iv.lo = (uintptr_t)ptr;
-    iv.hi = iv.lo + (uintptr_t)(((cols - 1) * ld + rows) * (int64_t)sizeof(float));
-}
-
 // Build (without a graph) the plan for a batch.  Shared by plan_create and
 // the tuner.
 static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
@@ -254,7 +244,7 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
     // Validate every problem (BLAS rules) and collect the live ones.
     std::vector<GroupedProblem> live;
     std::vector<int64_t> live_index;
-    std::vector<Interval> cs, ab;
+    std::vector<Extent> cs, ab;
     for (int64_t i = 0; i < count; ++i) {
         const mgemm_problem& q = probs[i];
         std::string why;
@@ -290,36 +280,22 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
         g.tiles_n = (uint32_t)((q.N + vs.bn - 1) / vs.bn);
         live.push_back(g);
         live_index.push_back(i);
-        Interval iv;
-        extent_of(q.C, q.M, q.N, q.ldc, iv);
-        iv.owner = i;
-        cs.push_back(iv);
+        cs.push_back(extent_of(q.C, q.M, q.N, q.ldc, i));
         if (!no_product) {
-            extent_of(q.A, ta ? q.K : q.M, ta ? q.M : q.K, q.lda, iv);
-            ab.push_back(iv);
-            extent_of(q.B, tb ? q.N : q.K, tb ? q.K : q.N, q.ldb, iv);
-            ab.push_back(iv);
+            ab.push_back(extent_of(q.A, ta ? q.K : q.M, ta ? q.M : q.K, q.lda, i));
+            ab.push_back(extent_of(q.B, tb ? q.N : q.K, tb ? q.K : q.N, q.ldb, i));
         }
     }
     // No C may overlap another C, or any A or B of the batch.
-    std::sort(cs.begin(), cs.end(), [](const Interval& a, const Interval& b) { return a.lo < b.lo; });
-    for (size_t k = 1; k < cs.size(); ++k)
-        if (cs[k].lo < cs[k - 1].hi) {
-            if (bad_index) *bad_index = cs[k].owner;
-            if (bad_status) *bad_status = MGEMM_ERR_ALIAS;
-            return fail(MGEMM_ERR_BAD_PROBLEM, "problem " + std::to_string(cs[k].owner) +
-                                                   ": C overlaps another problem's C");
-        }
-    for (const Interval& x : ab) {
-        auto it = std::lower_bound(cs.begin(), cs.end(), x.hi,
-                                   [](const Interval& c, uintptr_t v) { return c.lo < v; });
-        if (it != cs.begin() && std::prev(it)->hi > x.lo) {
-            if (bad_index) *bad_index = std::prev(it)->owner;
-            if (bad_status) *bad_status = MGEMM_ERR_ALIAS;
-            return fail(MGEMM_ERR_BAD_PROBLEM,
-                        "problem " + std::to_string(std::prev(it)->owner) +
-                            ": C overlaps an operand of the batch");
-        }
+    int kind = 0;
+    const int64_t culprit = batch_alias(cs, ab, &kind);
+    if (culprit >= 0) {
+        if (bad_index) *bad_index = culprit;
+        if (bad_status) *bad_status = MGEMM_ERR_ALIAS;
+        return fail(MGEMM_ERR_BAD_PROBLEM,
+                    "problem " + std::to_string(culprit) +
+                        (kind == 1 ? ": C overlaps another problem's C"
+                                   : ": C overlaps an operand of the batch"));
     }
     // Tile list, longest first (cost ~ K x tile area; ties keep problem order).
     std::vector<TileRef> tl;
@@ -378,17 +354,11 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
         const uint32_t G = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(slots, (int64_t)idx.size()));
         std::stable_sort(idx.begin(), idx.end(),
                          [&](size_t a2, size_t b2) { return cost[a2] > cost[b2]; });
+        std::vector<double> ordered(idx.size());
+        for (size_t q = 0; q < idx.size(); ++q) ordered[q] = cost[idx[q]];
+        const std::vector<uint32_t> owner = lpt_schedule(ordered, G);
         std::vector<std::vector<TileRef>> per_wg(G);
-        using Load = std::pair<double, uint32_t>;
-        std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
-        for (uint32_t w = 0; w < G; ++w) heap.push(Load{0.0, w});
-        for (size_t k2 : idx) {
-            Load l = heap.top();
-            heap.pop();
-            per_wg[l.second].push_back(tl[k2]);
-            l.first += cost[k2];
-            heap.push(l);
-        }
+        for (size_t q = 0; q < idx.size(); ++q) per_wg[owner[q]].push_back(tl[idx[q]]);
         p->launches.push_back(VariantLaunch{v, G, (int64_t)starts.size()});
         for (uint32_t w = 0; w < G; ++w) {
             starts.push_back((uint32_t)sched.size());

@@ -5,6 +5,7 @@
 
 #include <functional>
 #include <string>
+#include <vector>
 
 #include "mgemm.h"
 
@@ -25,6 +26,19 @@ int validate(char transA, char transB, int64_t M, int64_t N, int64_t K, float al
 // True when the referenced part of C overlaps that of A or B.
 bool overlaps(int ta, int tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
               int64_t lda, const float* B, int64_t ldb, const float* C, int64_t ldc);
+
+// Byte range [lo, hi) of the referenced part of a stored array, and the
+// problem it belongs to.
+struct Extent {
+    uintptr_t lo, hi;
+    int64_t owner;
+};
+Extent extent_of(const void* p, int64_t rows, int64_t cols, int64_t ld, int64_t owner);
+
+// A grouped batch's aliasing rule: no C extent (cs) may overlap another, or
+// any operand extent (ab).  Returns the owner of an offending C (with
+// *kind = 1 for C against C, 2 for C against an operand), or -1.
+int64_t batch_alias(std::vector<Extent> cs, const std::vector<Extent>& ab, int* kind);
 
 // MGEMM_OK when the current device is a gfx950; otherwise an error status.
 int check_device(int* out_dev);

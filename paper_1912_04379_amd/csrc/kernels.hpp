@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "rules.hpp"
 #include "tile_common.hpp"
 
 namespace mgemm {
@@ -15,31 +16,17 @@ struct TileConfigInfo {
 // FP32 MFMA path.
 int f32_config_count();
 TileConfigInfo f32_config_info(int cfg);
-int f32_default_config(bool transA, bool transB, int64_t M, int64_t N, int64_t K);
 hipError_t launch_f32(int cfg, bool transA, bool transB, const GemmDesc& d,
                       hipStream_t stream);
 // FP32 small-product kernel (16 x 16 tiles, k split over 4 waves); needs
 // buffer_path_ok(d).
 hipError_t launch_small(bool transA, bool transB, const GemmDesc& d, hipStream_t stream);
-// FP32 configuration 10: 256 x 256 x 32 tiles in whole rounds of one per
-// CU (`cus` CUs), 128 x 128 tiles in the tail; needs buffer_path_ok(d).
-constexpr int F32_TAIL_CONFIG = 10;
+// FP32 configuration 10 (F32_TAIL_CONFIG): 256 x 256 x 32 tiles in whole
+// rounds of one per CU (`cus` CUs), 128 x 128 tiles in the tail; needs
+// buffer_path_ok(d).
 hipError_t launch_f32_tail(bool transA, bool transB, const GemmDesc& d, int cus,
                            hipStream_t stream);
-// FP32 configuration 11: split-K.  The k range is cut into S pieces of kc
-// (the last one shorter); piece s of every tile is an ordinary tile product
-// written to workspace + s*M*N (column-major, ld M), and a second kernel
-// adds the S partial products in order s = 0..S-1 and applies alpha, beta.
-constexpr int F32_SPLITK_CONFIG = 11;
-struct SplitKPlan {
-    int small_tile;   // 0: 128 x 128 x 16 tiles, 1: 64 x 64 x 16
-    int splits;       // S >= 2, or 0 when splitting does not apply
-    int64_t kc;       // k per piece, a multiple of 32
-};
-SplitKPlan f32_splitk_plan(int64_t M, int64_t N, int64_t K, int cus);
-// Largest split-K workspace taken (1 GiB); larger products run unsplit.
-constexpr int64_t F32_SPLITK_MAX_WORKSPACE = 1LL << 30;
-int64_t f32_splitk_workspace_bytes(const SplitKPlan& p, int64_t M, int64_t N);
+// FP32 configuration 11 (F32_SPLITK_CONFIG, plan in rules.hpp).
 // Needs buffer_path_ok(d), p.splits >= 2 and f32_splitk_workspace_bytes()
 // of workspace.
 hipError_t launch_f32_splitk(bool transA, bool transB, const GemmDesc& d, const SplitKPlan& p,
@@ -48,14 +35,12 @@ hipError_t launch_f32_splitk(bool transA, bool transB, const GemmDesc& d, const 
 // BF16x3 split path.
 int bf16x3_config_count();
 TileConfigInfo bf16x3_config_info(int cfg);
-int bf16x3_default_config(int64_t M, int64_t N, int64_t K);
 hipError_t launch_bf16x3(int cfg, bool transA, bool transB, const GemmDesc& d,
                          hipStream_t stream);
 
 // Scaled FP16 path: exponent pre-pass and main kernel.
 int f16s_config_count();
 TileConfigInfo f16s_config_info(int cfg);
-int f16s_default_config(int64_t M, int64_t N, int64_t K);
 // FP16 exponent pre-pass; `partial` is scratch of f16_partial_floats().
 int64_t f16_partial_floats(int64_t M, int64_t N, int64_t K);
 hipError_t launch_f16_exponents(bool transA, bool transB, const GemmDesc& d,
@@ -68,7 +53,6 @@ hipError_t launch_f16s(int cfg, bool transA, bool transB, const GemmDesc& d,
 // forms (those whose BF16x3 LDS ring exceeds a CU are FP16 only).  The caller provides `workspace` of
 // packed_workspace_bytes(); for the FP16 form d.expA / d.expB must already
 // hold the panel exponents.
-constexpr int LOWP_INSTAGE_CONFIGS = 4;
 int packed_config_count();
 TileConfigInfo packed_config_info(int cfg);
 int64_t packed_workspace_bytes(bool bf16x3, int cfg, int64_t M, int64_t N, int64_t K);

@@ -29,55 +29,6 @@ static int hip_fail(hipError_t e, const char* where) {
     return fail(MGEMM_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
-int trans_code(char t) {
-    if (t == 'N' || t == 'n') return 0;
-    if (t == 'T' || t == 't' || t == 'C' || t == 'c') return 1;
-    return -1;
-}
-
-static int64_t max1(int64_t v) { return v > 1 ? v : 1; }
-
-// Byte ranges [lo, hi) touched by the referenced part of a stored array.
-static void extent(const void* p, int64_t rows, int64_t cols, int64_t ld, uintptr_t& lo,
-                   uintptr_t& hi) {
-    lo = (uintptr_t)p;
-    hi = lo + (uintptr_t)(((cols - 1) * ld + rows) * (int64_t)sizeof(float));
-}
-
-int validate(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
-             const float* A, int64_t lda, const float* B, int64_t ldb, float beta,
-             const float* C, int64_t ldc, std::string& why) {
-    const int ta = trans_code(transA), tb = trans_code(transB);
-    if (ta < 0) { why = "transA must be N, T or C"; return -1; }
-    if (tb < 0) { why = "transB must be N, T or C"; return -2; }
-    if (M < 0) { why = "M < 0"; return -3; }
-    if (N < 0) { why = "N < 0"; return -4; }
-    if (K < 0) { why = "K < 0"; return -5; }
-    const int64_t rows_a = ta ? K : M, rows_b = tb ? N : K;
-    const bool reads_ab = alpha != 0.0f && K > 0 && M > 0 && N > 0;
-    if (reads_ab && A == nullptr) { why = "A is NULL"; return -7; }
-    if (lda < max1(rows_a)) { why = "lda < max(1, stored rows of A)"; return -8; }
-    if (reads_ab && B == nullptr) { why = "B is NULL"; return -9; }
-    if (ldb < max1(rows_b)) { why = "ldb < max(1, stored rows of B)"; return -10; }
-    if (M > 0 && N > 0 && C == nullptr) { why = "C is NULL"; return -12; }
-    if (ldc < max1(M)) { why = "ldc < max(1, M)"; return -13; }
-    (void)beta;
-    return 0;
-}
-
-// C must not overlap the referenced part of A or B (the kernels read A and
-// B while other work-groups write C).
-bool overlaps(int ta, int tb, int64_t M, int64_t N, int64_t K, float alpha, const float* A,
-              int64_t lda, const float* B, int64_t ldb, const float* C, int64_t ldc) {
-    if (alpha == 0.0f || K == 0 || M == 0 || N == 0) return false;
-    uintptr_t clo, chi, lo, hi;
-    extent(C, M, N, ldc, clo, chi);
-    extent(A, ta ? K : M, ta ? M : K, lda, lo, hi);
-    if (lo < chi && clo < hi) return true;
-    extent(B, tb ? N : K, tb ? K : N, ldb, lo, hi);
-    return lo < chi && clo < hi;
-}
-
 // Per-device check that the current device is a gfx950: 0 unknown,
 // 1 ok, 2 wrong architecture.
 static std::atomic<int> g_dev_state[64];
@@ -569,10 +520,9 @@ int mgemm_sgemm_packed_b(char transA, int64_t M, float alpha, const float* A, in
     const bool no_product = alpha == 0.0f || K == 0;
     if (no_product && beta == 1.0f) return MGEMM_OK;
     if (!no_product) {
-        const uintptr_t alo = (uintptr_t)A,
-                        ahi = alo + (uintptr_t)((((ta ? M : K) - 1) * lda + (ta ? K : M)) * 4);
-        const uintptr_t clo = (uintptr_t)C, chi = clo + (uintptr_t)(((N - 1) * ldc + M) * 4);
-        if (alo < chi && clo < ahi) return fail(MGEMM_ERR_ALIAS, "C overlaps A");
+        const Extent a = extent_of(A, ta ? K : M, ta ? M : K, lda, 0);
+        const Extent c = extent_of(C, M, N, ldc, 0);
+        if (a.lo < c.hi && c.lo < a.hi) return fail(MGEMM_ERR_ALIAS, "C overlaps A");
     }
     int dev = 0;
     int st = check_device(&dev);

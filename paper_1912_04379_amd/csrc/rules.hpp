@@ -1,0 +1,45 @@
+// rules.hpp -- the library's host-side decision rules, free of any HIP
+// type: tile-configuration defaults, the split-K plan, and the list
+// schedule of grouped plans.  Internal; built into the library and, on its
+// own, into the host-only sanitizer check.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+namespace mgemm {
+
+// FP32 configuration 10: 256 x 256 x 32 tiles in whole rounds of one per
+// CU, 128 x 128 tiles in the tail.
+constexpr int F32_TAIL_CONFIG = 10;
+// FP32 configuration 11: split-K.  The k range is cut into S pieces of kc
+// (the last one shorter); piece s of every tile is an ordinary tile product
+// written to workspace + s*M*N (column-major, ld M), and a second kernel
+// adds the S partial products in order s = 0..S-1 and applies alpha, beta.
+constexpr int F32_SPLITK_CONFIG = 11;
+struct SplitKPlan {
+    int small_tile;   // 0: 128 x 128 x 16 tiles, 1: 64 x 64 x 16
+    int splits;       // S >= 2, or 0 when splitting does not apply
+    int64_t kc;       // k per piece, a multiple of 32
+};
+SplitKPlan f32_splitk_plan(int64_t M, int64_t N, int64_t K, int cus);
+// Largest split-K workspace taken (1 GiB); larger products run unsplit.
+constexpr int64_t F32_SPLITK_MAX_WORKSPACE = 1LL << 30;
+int64_t f32_splitk_workspace_bytes(const SplitKPlan& p, int64_t M, int64_t N);
+
+// Configurations 0..3 of the 16-bit forms split or scale while staging;
+// configuration LOWP_INSTAGE_CONFIGS + c is packed configuration c.
+constexpr int LOWP_INSTAGE_CONFIGS = 4;
+
+// Built-in configuration of a single call (no recorded choice).
+int f32_default_config(bool transA, bool transB, int64_t M, int64_t N, int64_t K);
+int bf16x3_default_config(int64_t M, int64_t N, int64_t K);
+int f16s_default_config(int64_t M, int64_t N, int64_t K);
+
+// Longest-processing-time-first list schedule: items taken in the order
+// given (the caller sorts them by decreasing cost), each to the work-group
+// with the least assigned cost so far, ties to the lowest number.  Returns
+// the work-group of every item; G >= 1.
+std::vector<uint32_t> lpt_schedule(const std::vector<double>& cost_in_order, uint32_t G);
+
+}  // namespace mgemm

@@ -176,30 +176,6 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restr
     }
 }
 
-SplitKPlan f32_splitk_plan(int64_t M, int64_t N, int64_t K, int cus) {
-    SplitKPlan p{0, 0, 0};
-    if (M < 1 || N < 1 || K < 1 || cus < 1) return p;
-    const int64_t t128 = ((M + 127) / 128) * ((N + 127) / 128);
-    const int64_t t64 = ((M + 63) / 64) * ((N + 63) / 64);
-    p.small_tile = t128 * 4 >= cus ? 0 : 1;
-    const int64_t tiles = p.small_tile ? t64 : t128;
-    // About two work-groups per CU, pieces of at least 256 k.
-    int64_t s = (2 * (int64_t)cus + tiles - 1) / tiles;
-    if (s > 32) s = 32;
-    int64_t kc = (K + s - 1) / s;
-    kc = (kc + 31) / 32 * 32;
-    if (kc < 256) kc = 256;
-    s = (K + kc - 1) / kc;
-    if (s < 2 || tiles * s > 0xffffffffLL) return p;
-    p.splits = (int)s;
-    p.kc = kc;
-    return p;
-}
-
-int64_t f32_splitk_workspace_bytes(const SplitKPlan& p, int64_t M, int64_t N) {
-    return (int64_t)p.splits * M * N * 4;
-}
-
 template <class Cfg>
 static void launch_splitk_pieces(bool ta, bool tb, const GemmDesc& d, const SplitKPlan& p,
                                  float* ws, hipStream_t s) {
