@@ -628,7 +628,8 @@ def bench_splitk(args, mg, torch):
     """Products with few tiles and a long k range (NN, ld = rows + 16, alpha
     1.5, beta -0.5, uniform inputs): the library's choice (split-K) against
     the same product unsplit on 64 x 64 tiles (configuration 1) and, at
-    256^2, the small-product kernel (configuration 9)."""
+    256^2, the small-product kernel (configuration 9); the same for the two
+    16-bit forms."""
     import synth
     stream = torch.cuda.current_stream()
     out = {}
@@ -642,10 +643,25 @@ def bench_splitk(args, mg, torch):
                                         c["ldc"], config=cfg), max(10, args.steps), 3, stream)
             res[name] = {"ms": round(ms, 4), "tflops": round(2.0 * M * N * K / ms / 1e9, 3)}
         res["speedup"] = round(res["unsplit_config_%d" % other]["ms"] / res["default"]["ms"], 3)
+        # The 16-bit forms: the library's choice (split-K) against the
+        # fastest unsplit configuration the library had chosen before
+        # split-K existed (BF16x3 in-staging 64 x 64, FP16 packed 128 x 128).
+        for prec, unsplit in (("bf16x3", 3), ("fp16s", 11)):
+            r = {"default_config": mg.default_config(prec, "N", "N", M, N, K)}
+            for name, cfg in (("default", -1), ("unsplit_config_%d" % unsplit, unsplit)):
+                ms = timed(lambda: mg.sgemm("N", "N", M, N, K, 1.5, A, c["lda"], B, c["ldb"], -0.5,
+                                            C, c["ldc"], precision=prec, config=cfg),
+                           max(10, args.steps), 3, stream)
+                r[name] = {"ms": round(ms, 4), "tflops": round(2.0 * M * N * K / ms / 1e9, 3)}
+            r["speedup"] = round(r["unsplit_config_%d" % unsplit]["ms"] / r["default"]["ms"], 3)
+            res[prec] = r
         out["%dx%dx%d" % (M, N, K)] = res
-        log("split-K %dx%dx%d: %.1f TFLOP/s (config %d), unsplit %.1f" %
+        log("split-K %dx%dx%d: %.1f TFLOP/s (config %d), unsplit %.1f; bf16x3 %.1f (%.2fx), "
+            "fp16s %.1f (%.2fx)" %
             (M, N, K, res["default"]["tflops"], res["default_config"],
-             res["unsplit_config_%d" % other]["tflops"]))
+             res["unsplit_config_%d" % other]["tflops"], res["bf16x3"]["default"]["tflops"],
+             res["bf16x3"]["speedup"], res["fp16s"]["default"]["tflops"],
+             res["fp16s"]["speedup"]))
         del A, B, C
     return out
 

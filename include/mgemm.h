@@ -99,7 +99,14 @@ int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  * per CU and K of about 2048 and up, takes S*M*N*4 bytes from the same
  * pool (at most 1 GiB; larger products, and leading dimensions beyond the
  * 32-bit buffer path, run configuration 0 instead).  The other FP32
- * configurations take no workspace.
+ * configurations take no workspace.  The last configuration of either
+ * 16-bit form (13) is split-K in the same way: the pieces are in-staging
+ * tiles (128 x 128, or 64 x 64 for few tiles), their S*M*N*4 bytes of
+ * partial products come from the pool too (the FP16 unscale is applied per
+ * piece, exactly), and where splitting does not apply configuration 1 runs.
+ * The library's choice takes it for BF16x3 products with at most 128 tiles
+ * of 128 x 128 and K >= 2048, or at most 256 and K >= 8192, and for FP16
+ * products with at most 64 such tiles and K >= 2048.
  * An allocation failure returns MGEMM_ERR_ALLOC before anything runs.  A
  * packed configuration that the product cannot use (K too long for 32-bit
  * block offsets, or an LDS ring larger than a CU) runs configuration 0.
@@ -126,12 +133,11 @@ int mgemm_sgemm_ex(char transA, char transB, int64_t M, int64_t N, int64_t K,
  * (one stream, or events).
  *
  * Workspace beyond the array: a named `config` whose workspace exceeds it
- * (FP32 configuration 11 with S*M*N*4 bytes of partial products, a packed
- * 16-bit configuration with its packed operands) returns
+ * (the split-K configurations with S*M*N*4 bytes of partial products, a
+ * packed 16-bit configuration with its packed operands) returns
  * MGEMM_ERR_UNSUPPORTED and launches nothing; with config = -1 the library
  * takes its usual choice when it fits, else a configuration that needs
- * less (FP32 unsplit tiles; 16-bit operands split or scaled while staging,
- * configuration 0).  Scaled FP16 always needs its panel exponents and
+ * less (unsplit tiles; 16-bit operands split or scaled while staging).  Scaled FP16 always needs its panel exponents and
  * partial maxima (about (M+N)/32 * (4 + 4*ceil(K/2048)) bytes); a product
  * whose exponents exceed the array returns MGEMM_ERR_UNSUPPORTED.
  */

@@ -126,6 +126,13 @@ int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
     return best;
 }
 
+// The split-K plan applies (at least two pieces) and its partial products
+// fit the workspace limit.
+static bool lowp_split_fits(int64_t M, int64_t N, int64_t K) {
+    const SplitKPlan p = f32_splitk_plan(M, N, K, (int)NUM_CUS);
+    return p.splits >= 2 && f32_splitk_workspace_bytes(p, M, N) <= F32_SPLITK_MAX_WORKSPACE;
+}
+
 // In-staging tiles, for products too shallow to repay pre-packing: 256x256
 // once the chip gets at least two rounds of work-groups, otherwise the tile
 // that still gives every CU several work-groups.
@@ -148,6 +155,14 @@ int bf16x3_default_config(int64_t M, int64_t N, int64_t K) {
     // for deep products, in-staging 128x128 for shallow ones, in-staging
     // 64x64 below one round of 128x128 tiles.
     const int64_t t256 = tile_count(M, N, 256, 256), t128 = tile_count(M, N, 128, 128);
+    // Few tiles and a long k range: split-K.  Measured NN, TFLOP/s, split
+    // against the best unsplit configuration: 512^2 x 16384 139 against 27;
+    // 1024^2 x 8192 223 against 106; 256^2 x 65536 128 against 7; 1024^2 x
+    // 2048 114 against 99; 2048 x 1024 x 3072 205 against 168; 1024 x 4096 x
+    // 8192 262 against 252; it loses at 2048^2 x 4096 (254 against 265).
+    if (((t128 <= NUM_CUS / 2 && K >= 2048) || (t128 <= NUM_CUS && K >= 8192)) &&
+        lowp_split_fits(M, N, K))
+        return LOWP_SPLITK_CONFIG;
     if (t256 >= NUM_CUS && (M < N ? M : N) >= 4608 && K >= 512)
         return K >= 2048 && slot_share(M, N, 256, 256) >= 0.85 ? LOWP_INSTAGE_CONFIGS + 6
                                                                : LOWP_INSTAGE_CONFIGS + 7;
@@ -177,6 +192,13 @@ int f16s_default_config(int64_t M, int64_t N, int64_t K) {
     // TFLOP/s at 8192^3) and the pipelined packed 128x128 tile (about 850),
     // the slot-share model picks; the larger tile's longer prologue needs K
     // of 3072 or more.
+    // Few tiles and a long k range: split-K.  Measured NN, TFLOP/s, split
+    // against the best unsplit configuration: 512^2 x 16384 95 against 44;
+    // 1024^2 x 8192 181 against 140; 256^2 x 65536 80 against 13; 1000^2 x
+    // 4000 120 against 105; 1024^2 x 2048 83 against 79.  With more tiles the
+    // packed 128 x 128 tile wins (2048 x 1024 x 3072: 186 against 163).
+    if (tile_count(M, N, 128, 128) <= NUM_CUS / 4 && K >= 2048 && lowp_split_fits(M, N, K))
+        return LOWP_SPLITK_CONFIG;
     if (K < 512) return lowp_default(M, N);
     const double big = 906.0 * slot_share(M, N, 256, 256);
     const double mid = 850.0 * slot_share(M, N, 128, 128);

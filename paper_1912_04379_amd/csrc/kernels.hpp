@@ -31,6 +31,10 @@ hipError_t launch_f32_tail(bool transA, bool transB, const GemmDesc& d, int cus,
 // of workspace.
 hipError_t launch_f32_splitk(bool transA, bool transB, const GemmDesc& d, const SplitKPlan& p,
                              float* workspace, hipStream_t stream);
+// The second kernel of every split-K path: C <- alpha * sum of the `splits`
+// M x N slices of `ws` (ld M), added in order s = 0..splits-1, + beta * C.
+hipError_t launch_splitk_reduce(const float* ws, int splits, const GemmDesc& d,
+                                hipStream_t stream);
 
 // BF16x3 split path.
 int bf16x3_config_count();
@@ -47,6 +51,13 @@ hipError_t launch_f16_exponents(bool transA, bool transB, const GemmDesc& d,
                                 int* expA, int* expB, float* partial, hipStream_t stream);
 hipError_t launch_f16s(int cfg, bool transA, bool transB, const GemmDesc& d,
                        hipStream_t stream);
+// Split-K of either 16-bit form (the LOWP_SPLITK_CONFIG configuration): the
+// pieces of plan p run as in-staging tiles (64 x 64 when p.small_tile, else
+// 128 x 128) into `workspace` (S*M*N floats), then launch_splitk_reduce.
+// For the FP16 form d.expA / d.expB already hold the panel exponents of the
+// whole K.  Needs buffer_path_ok(d), d.M <= MAX_BUF_LD and p.splits >= 2.
+hipError_t launch_lowp_splitk(bool bf16x3, bool transA, bool transB, const GemmDesc& d,
+                              const SplitKPlan& p, float* workspace, hipStream_t stream);
 
 // Pre-packed 16-bit path (direct-to-LDS engine).  Configuration c of this
 // family is configuration LOWP_INSTAGE_CONFIGS + c of the BF16x3 and FP16

@@ -260,7 +260,25 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
         return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
     }
     const bool bf = precision == MGEMM_PREC_BF16X3;
-    bool packed = cfg >= LOWP_INSTAGE_CONFIGS;
+    // Split-K (configuration LOWP_SPLITK_CONFIG): where it does not apply
+    // (short k, 64-bit address path, a workspace beyond the limit), the
+    // 128 x 128 in-staging tile.
+    SplitKPlan split{0, 0, 0};
+    int64_t split_bytes = 0;
+    if (cfg == LOWP_SPLITK_CONFIG) {
+        split = f32_splitk_plan(M, N, K, device_cus(dev));
+        split_bytes = f32_splitk_workspace_bytes(split, M, N);
+        const bool applies = split.splits >= 2 && buffer_path_ok(d) && M <= MAX_BUF_LD;
+        if (fixed && config >= 0 && applies && split_bytes > fixed->cap)
+            return fail(MGEMM_ERR_UNSUPPORTED,
+                        too_big(split_bytes, fixed->cap, "split-K partial products"));
+        if (!applies || split_bytes > (fixed ? fixed->cap : F32_SPLITK_MAX_WORKSPACE)) {
+            split = SplitKPlan{0, 0, 0};
+            split_bytes = 0;
+            cfg = 1;
+        }
+    }
+    bool packed = cfg >= LOWP_INSTAGE_CONFIGS && cfg < LOWP_SPLITK_CONFIG;
     if (packed && !packed_supported(bf, cfg - LOWP_INSTAGE_CONFIGS, M, N, K)) {
         // Not available for this form, or lane offsets would not fit in 31
         // bits: split while staging, with the 256 x 256 in-staging tile.
@@ -288,13 +306,24 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
     }
     if (fixed && exp_bytes > fixed->cap)
         return fail(MGEMM_ERR_UNSUPPORTED, too_big(exp_bytes, fixed->cap, "FP16 panel exponents"));
+    if (fixed && split.splits && exp_bytes + split_bytes > fixed->cap) {
+        // Exponents and partial products together exceed the fixed
+        // workspace: a named configuration is refused, the library's choice
+        // runs unsplit.
+        if (config >= 0)
+            return fail(MGEMM_ERR_UNSUPPORTED,
+                        too_big(exp_bytes + split_bytes, fixed->cap, "split-K partial products"));
+        split = SplitKPlan{0, 0, 0};
+        split_bytes = 0;
+        cfg = 1;
+    }
     dp.cfg = cfg;
-    dp.path = packed ? "packed" : "in_staging";
-    dp.ws_bytes = exp_bytes + pack_bytes;
+    dp.path = packed ? "packed" : split.splits ? "lowp_split_k" : "in_staging";
+    dp.splits = split.splits;
+    dp.ws_bytes = exp_bytes + pack_bytes + split_bytes;
     char* ws = nullptr;
-    if (exp_bytes + pack_bytes > 0) {
-        e = fault_injected() ? hipErrorOutOfMemory
-                             : take_workspace(dev, fixed, exp_bytes + pack_bytes, s, &ws);
+    if (dp.ws_bytes > 0) {
+        e = fault_injected() ? hipErrorOutOfMemory : take_workspace(dev, fixed, dp.ws_bytes, s, &ws);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return fail(MGEMM_ERR_ALLOC, "stream-ordered workspace");
@@ -311,6 +340,9 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
     if (e == hipSuccess) {
         if (packed)
             e = launch_packed(bf, cfg - LOWP_INSTAGE_CONFIGS, ta, tb, d, ws + exp_bytes, s);
+        else if (split.splits)
+            e = launch_lowp_splitk(bf, ta, tb, d, split, reinterpret_cast<float*>(ws + exp_bytes),
+                                   s);
         else
             e = bf ? launch_bf16x3(cfg, ta, tb, d, s) : launch_f16s(cfg, ta, tb, d, s);
     }

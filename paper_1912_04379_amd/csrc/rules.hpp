@@ -30,6 +30,11 @@ int64_t f32_splitk_workspace_bytes(const SplitKPlan& p, int64_t M, int64_t N);
 // Configurations 0..3 of the 16-bit forms split or scale while staging;
 // configuration LOWP_INSTAGE_CONFIGS + c is packed configuration c.
 constexpr int LOWP_INSTAGE_CONFIGS = 4;
+// Packed configurations of the 16-bit forms, and the split-K configuration
+// that follows them (the k range cut as for FP32 configuration 11, the
+// pieces run as in-staging tiles).
+constexpr int LOWP_PACKED_CONFIGS = 9;
+constexpr int LOWP_SPLITK_CONFIG = LOWP_INSTAGE_CONFIGS + LOWP_PACKED_CONFIGS;
 
 // Built-in configuration of a single call (no recorded choice).
 int f32_default_config(bool transA, bool transB, int64_t M, int64_t N, int64_t K);

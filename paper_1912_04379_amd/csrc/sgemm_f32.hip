@@ -209,11 +209,15 @@ hipError_t launch_f32_splitk(bool ta, bool tb, const GemmDesc& d, const SplitKPl
         launch_splitk_pieces<F32Cfg0>(ta, tb, d, p, ws, s);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    return launch_splitk_reduce(ws, p.splits, d, s);
+}
+
+hipError_t launch_splitk_reduce(const float* ws, int splits, const GemmDesc& d, hipStream_t s) {
     const int64_t mn = d.M * d.N;
     int64_t blocks = (mn + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, ws,
-                       p.splits, d.M, d.N, d.C, d.ldc, d.alpha, d.beta);
+                       splits, d.M, d.N, d.C, d.ldc, d.alpha, d.beta);
     return hipGetLastError();
 }
 

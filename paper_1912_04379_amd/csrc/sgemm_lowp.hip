@@ -82,18 +82,90 @@ static hipError_t lowp_launch(int cfg, bool ta, bool tb, const GemmDesc& d, hipS
     }
 }
 
+// ---------------------------------------------------------------------------
+// Split-K.  Piece s of every tile is an ordinary in-staging tile over k in
+// [s kc, min((s+1) kc, K)) with alpha 1 and beta 0, written to slice s of the
+// workspace (column-major, ld M); the FP16 unscale by the whole-K panel
+// exponents is applied per piece, which is exact (a power of two).  The
+// reduction kernel then adds the slices in order and applies alpha, beta.
+// ---------------------------------------------------------------------------
+template <class Cfg, Form F, bool AK, bool BKC>
+__global__ __launch_bounds__(Cfg::NT) void sgemm_lowp_splitk_kernel(GemmDesc d, uint32_t tiles_m,
+                                                                   uint32_t tiles_n, int64_t kc,
+                                                                   float* ws) {
+    extern __shared__ __attribute__((aligned(16))) char lowp_smem[];
+    // Logical id -> (piece, tile): one XCD takes consecutive tiles of one
+    // piece, which share panels of A and B.
+    const uint32_t id = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t tiles = tiles_m * tiles_n;
+    const uint32_t s = id / tiles;
+    uint32_t tm, tn;
+    grouped_tile<8>(id - s * tiles, tiles_m, tiles_n, tm, tn);
+    const int64_t k0 = (int64_t)s * kc;
+    GemmDesc p = d;
+    p.A = d.A + (AK ? k0 : k0 * d.lda);
+    p.B = d.B + (BKC ? k0 : k0 * d.ldb);
+    p.K = d.K - k0 < kc ? d.K - k0 : kc;
+    p.C = ws + (int64_t)s * d.M * d.N;
+    p.ldc = d.M;
+    p.alpha = 1.0f;
+    p.beta = 0.0f;
+    tile_lowp<Cfg, F, AK, BKC, true>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, lowp_smem);
+}
+
+template <class Cfg, Form F>
+static hipError_t launch_splitk_pieces(bool ta, bool tb, const GemmDesc& d, const SplitKPlan& p,
+                                       float* ws, hipStream_t s) {
+    const uint32_t tm = (uint32_t)((d.M + Cfg::BM - 1) / Cfg::BM);
+    const uint32_t tn = (uint32_t)((d.N + Cfg::BN - 1) / Cfg::BN);
+    const dim3 grid(tm * tn * (uint32_t)p.splits), block(Cfg::NT);
+    constexpr int bytes = lowp_smem_bytes<Cfg, F>();
+    static_assert(bytes <= 65536, "split-K tiles use at most 64 KB of LDS");
+    if (!ta && !tb)
+        hipLaunchKernelGGL((sgemm_lowp_splitk_kernel<Cfg, F, false, true>), grid, block, bytes, s,
+                           d, tm, tn, p.kc, ws);
+    else if (!ta && tb)
+        hipLaunchKernelGGL((sgemm_lowp_splitk_kernel<Cfg, F, false, false>), grid, block, bytes,
+                           s, d, tm, tn, p.kc, ws);
+    else if (ta && !tb)
+        hipLaunchKernelGGL((sgemm_lowp_splitk_kernel<Cfg, F, true, true>), grid, block, bytes, s,
+                           d, tm, tn, p.kc, ws);
+    else
+        hipLaunchKernelGGL((sgemm_lowp_splitk_kernel<Cfg, F, true, false>), grid, block, bytes, s,
+                           d, tm, tn, p.kc, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowp_splitk(bool bf16x3, bool ta, bool tb, const GemmDesc& d,
+                              const SplitKPlan& p, float* ws, hipStream_t s) {
+    if (!buffer_path_ok(d) || p.splits < 2 || p.kc < 32 || p.kc % 32 || d.M > MAX_BUF_LD || !ws)
+        return hipErrorInvalidValue;
+    if ((int64_t)(p.splits - 1) * p.kc >= d.K) return hipErrorInvalidValue;   // empty piece
+    if (!bf16x3 && (!d.expA || !d.expB)) return hipErrorInvalidValue;
+    hipError_t e;
+    if (bf16x3)
+        e = p.small_tile ? launch_splitk_pieces<LPCfg3, Form::BF16X3>(ta, tb, d, p, ws, s)
+                         : launch_splitk_pieces<LPCfg1, Form::BF16X3>(ta, tb, d, p, ws, s);
+    else
+        e = p.small_tile ? launch_splitk_pieces<LPCfg3, Form::F16S>(ta, tb, d, p, ws, s)
+                         : launch_splitk_pieces<LPCfg1, Form::F16S>(ta, tb, d, p, ws, s);
+    if (e != hipSuccess) return e;
+    return launch_splitk_reduce(ws, p.splits, d, s);
+}
+
 static TileConfigInfo lowp_any_info(int cfg) {
+    if (cfg == LOWP_SPLITK_CONFIG) return lowp_info(1);   // 128 x 128 pieces (64 x 64 for few tiles)
     return cfg < LOWP_INSTAGE_CONFIGS ? lowp_info(cfg)
                                       : packed_config_info(cfg - LOWP_INSTAGE_CONFIGS);
 }
 
-int bf16x3_config_count() { return LOWP_INSTAGE_CONFIGS + packed_config_count(); }
+int bf16x3_config_count() { return LOWP_INSTAGE_CONFIGS + packed_config_count() + 1; }
 TileConfigInfo bf16x3_config_info(int cfg) { return lowp_any_info(cfg); }
 hipError_t launch_bf16x3(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
     return lowp_launch<Form::BF16X3>(cfg, ta, tb, d, s);
 }
 
-int f16s_config_count() { return LOWP_INSTAGE_CONFIGS + packed_config_count(); }
+int f16s_config_count() { return LOWP_INSTAGE_CONFIGS + packed_config_count() + 1; }
 TileConfigInfo f16s_config_info(int cfg) { return lowp_any_info(cfg); }
 hipError_t launch_f16s(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t s) {
     return lowp_launch<Form::F16S>(cfg, ta, tb, d, s);

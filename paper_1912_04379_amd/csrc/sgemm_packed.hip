@@ -175,7 +175,7 @@ using PKCfg6 = CfgPK<256, 256, 2, 4, 4, 16, 2, true>;
 using PKCfg7 = CfgPK<128, 128, 2, 2, 4, 16, 2, true>;
 // FP16 only: as 6 in 4 x 32-k stages (128 KB), half the barriers per MFMA.
 using PKCfg8 = CfgPK<256, 256, 2, 4, 4, 32, 2, true>;
-constexpr int PACKED_CONFIGS = 9;
+constexpr int PACKED_CONFIGS = LOWP_PACKED_CONFIGS;
 
 // Calls f(Cfg{}) for configuration `cfg` (0 <= cfg < PACKED_CONFIGS).
 template <class Fn>

@@ -87,7 +87,7 @@ def test_unsupported_precision_and_config():
     assert call(config=99) == _lib.ERR_UNSUPPORTED
     assert mg.config_count("fp32") == 12
     # test_precision enumerates the 16-bit configurations by this count
-    assert mg.config_count("bf16x3") == 13 and mg.config_count("fp16s") == 13
+    assert mg.config_count("bf16x3") == 14 and mg.config_count("fp16s") == 14
     for prec in ("fp32", "bf16x3", "fp16s"):
         for cfg in range(mg.config_count(prec)):
             info = mg.config_info(prec, cfg)
@@ -252,6 +252,22 @@ def test_bf16x3_default_rule_slot_share(shape, cfg):
     in-staging 256 x 256 tile (0) or the packed 128 x 128 tile (11) by slot
     share; 8192^3 takes the pipelined packed 256 x 256 tile (10)."""
     assert mg.default_config("bf16x3", "N", "N", *shape) == cfg
+
+
+@pytest.mark.parametrize("prec,shape,split", [
+    ("bf16x3", (512, 512, 16384), True), ("bf16x3", (1024, 1024, 8192), True),
+    ("bf16x3", (256, 256, 65536), True), ("bf16x3", (2048, 1024, 3072), True),
+    ("bf16x3", (1024, 4096, 8192), True), ("bf16x3", (1024, 1024, 1024), False),
+    ("bf16x3", (2048, 2048, 4096), False), ("bf16x3", (8192, 8192, 8192), False),
+    ("fp16s", (512, 512, 16384), True), ("fp16s", (1024, 1024, 8192), True),
+    ("fp16s", (1000, 1000, 4000), True), ("fp16s", (2048, 1024, 3072), False),
+    ("fp16s", (1024, 4096, 8192), False), ("fp16s", (2048, 2048, 4096), False)])
+def test_lowp_default_rule_split_k(prec, shape, split):
+    """The 16-bit split-K rule as documented: BF16x3 for at most half a round
+    of 128 x 128 tiles with K >= 2048 or a full round with K >= 8192; FP16
+    for at most a quarter round with K >= 2048."""
+    got = mg.default_config(prec, "N", "N", *shape)
+    assert (got == mg.config_count(prec) - 1) == split
 
 
 def test_choices_round_trip_through_a_cache_file(tmp_path):

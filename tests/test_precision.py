@@ -22,8 +22,9 @@ from gpu_util import log, logical_c, padding_untouched, run, sampled_check, wide
 
 # Tile configurations of the 16-bit forms: 0..3 split while staging, the
 # rest stream pre-packed operands (test_abi checks the count).
-N_CONFIGS = 13
-PACKED_CONFIGS = list(range(4, N_CONFIGS))
+N_CONFIGS = 14
+PACKED_CONFIGS = list(range(4, N_CONFIGS - 1))
+SPLITK_CONFIG = N_CONFIGS - 1
 
 pytestmark = pytest.mark.gpu
 
@@ -97,6 +98,37 @@ def test_forms_every_config(prec, cfg):
     c = synth.sgemm_case(32, "T", "N", 520, 390, 200, alpha=1.5, beta=-0.5, dist="loguni")
     log("%s cfg %d" % (prec, cfg))
     check_form(c, prec, run(c, precision=prec, config=cfg))
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+@pytest.mark.parametrize("ta,tb", TRANS)
+@pytest.mark.parametrize("shape", [(200, 136, 5000), (300, 260, 3001)])
+def test_forms_split_k(prec, ta, tb, shape, tmp_path, monkeypatch):
+    """Split-K of the 16-bit forms: pieces of the k range as in-staging
+    tiles, added in a fixed order.  Against the exact product and the form's
+    emulation, bitwise the same on a second run, and taken (not a
+    fallback)."""
+    M, N, K = shape
+    logf = tmp_path / "mgemm.log"
+    monkeypatch.setenv("MGEMM_LOG", str(logf))
+    c = synth.sgemm_case(33, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=3, dist="loguni")
+    log("%s split-K %s %s%s" % (prec, shape, ta, tb))
+    got = run(c, precision=prec, config=SPLITK_CONFIG)
+    check_form(c, prec, got)
+    again = run(c, precision=prec, config=SPLITK_CONFIG)
+    assert np.array_equal(got.view(np.uint32), again.view(np.uint32))
+    assert "-> lowp_split_k cfg=%d splits=" % SPLITK_CONFIG in logf.read_text()
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+def test_forms_split_k_integer_inputs_bitwise(prec):
+    """|v| <= 16, K = 8192: every partial sum is an integer below 2**24, so
+    the split sums are exact and equal the oracle bitwise."""
+    c = synth.sgemm_case(34, "N", "T", 130, 70, 8192, alpha=1.0, beta=1.0, dist="int16",
+                         dist_c="int16")
+    log("%s split-K integers" % prec)
+    got = logical_c(run(c, precision=prec, config=SPLITK_CONFIG), c)
+    assert np.array_equal(got, oracle.sgemm(*args_of(c)))
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
