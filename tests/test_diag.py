@@ -65,11 +65,12 @@ def test_fault_alloc_fails_before_launching(monkeypatch):
     def call(prec, cfg):
         return _ex("N", "N", 300, 200, 4096, 1.5, A.data_ptr(), c["lda"], B.data_ptr(), c["ldb"],
                    -0.5, C.data_ptr(), c["ldc"], precision=prec, config=cfg, stream=s)
-    # This product's BF16x3 default splits while staging (no workspace), so
-    # the BF16x3 cases name a packed configuration.
-    assert mg.lib().mgemm_default_config(1, b"N", b"N", 300, 200, 4096) < 4
+    # Workspace-taking cases: FP32 and 16-bit split-K (this product's
+    # default for both 16-bit forms), packed BF16x3 configurations, and the
+    # FP16 exponents of every FP16 configuration.
+    assert mg.lib().mgemm_default_config(1, b"N", b"N", 300, 200, 4096) == 13
     monkeypatch.setenv("MGEMM_FAULT", "alloc")
-    for prec, cfg in ((0, 11), (1, 4), (1, 11), (2, 0), (2, -1)):
+    for prec, cfg in ((0, 11), (1, -1), (1, 4), (1, 11), (1, 13), (2, 0), (2, -1)):
         assert call(prec, cfg) == _lib.ERR_ALLOC, (prec, cfg)
         assert b"workspace" in mg.lib().mgemm_last_error()
     torch.cuda.synchronize()
@@ -87,6 +88,7 @@ def test_fault_alloc_fails_before_launching(monkeypatch):
                                             ctypes.byref(plan), ctypes.byref(bad))
     assert st == _lib.ERR_ALLOC and not plan.value
     assert call(0, 0) == 0          # FP32 configuration 0 takes no workspace
+    assert call(1, 3) == 0          # nor does BF16x3 split while staging
     monkeypatch.delenv("MGEMM_FAULT")
     for prec, cfg in ((0, 11), (1, -1), (1, 4), (2, -1)):
         assert call(prec, cfg) == 0
