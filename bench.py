@@ -57,11 +57,28 @@ def measured_traffic(key, prec):
     return rec.get("bytes_per_launch")
 
 
-def timed(fn, steps, warmup, stream):
+def timed(fn, steps, warmup, stream, min_ms=0.0):
+    """Mean time per call of `steps` back-to-back calls after `warmup` calls.
+    With min_ms > 0 (the sections other than the headline FP32 step), both
+    the warm-up and the timed run are extended to at least min_ms of work
+    each, so that short calls are timed at a steady engine clock."""
     import torch
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if min_ms > 0:
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        per = max(e0.elapsed_time(e1), 1e-3)
+        reps = int(min_ms / per) + 1
+        for _ in range(reps):
+            fn()
+        steps = max(steps, reps)
+        torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -86,6 +103,23 @@ def per_call_ms(fn, reps, stream):
         ts.append(e0.elapsed_time(e1))
     ts.sort()
     return ts[len(ts) // 2]
+
+
+def prewarm(torch, seconds):
+    """Back-to-back 4096^3 FP32 products through torch for about `seconds`,
+    so that the engine clock has ramped up before the first library launch
+    (the first few launches after an idle period otherwise run slower)."""
+    if seconds <= 0:
+        return
+    x = torch.rand(4096, 4096, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    while time.time() - t0 < seconds:
+        for _ in range(10):
+            torch.mm(x, x, out=y)
+        torch.cuda.synchronize()
+    del x, y
 
 
 def under_profiler():
@@ -177,6 +211,12 @@ def main():
                     help="do not sample the engine clock with amd-smi")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the size sweep (all trans pairs) and the 2048^3 forms")
+    ap.add_argument("--no-single-calls", action="store_true",
+                    help="skip the median of synchronised single FP32 calls (profiling runs: "
+                         "the idle gaps between them let the engine clock dip)")
+    ap.add_argument("--prewarm-s", type=float, default=1.0,
+                    help="seconds of back-to-back torch FP32 products before anything is "
+                         "timed, so that no library launch runs while the clock ramps up")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -230,15 +270,20 @@ def main():
         got = C.view(n, ld)[torch.from_numpy(cols).to(dev), torch.from_numpy(rows).to(dev)]
         return oracle.normwise_rel_err(got.double().cpu().numpy(), ref)
 
+    prewarm(torch, args.prewarm_s)
     results = {}
     forms = ["fp32"] if args.no_forms else ["fp32", "bf16x3", "fp16s"]
     flush = torch.empty(512 * 2 ** 20 // 4, dtype=torch.float32, device=dev)
     for prec in forms:
         if mg.config_count(prec) == 0:
             continue
-        err = error_of(prec)
-        log("%s: sampled normwise error %.3e; timing ..." % (prec, err))
+        # Timed first, right after the pre-warm or the previous form's
+        # timing: the host work of the error check leaves the GPU idle long
+        # enough for its clock to drop.
+        log("%s: timing ..." % prec)
         ms = timed(call(prec, C), args.steps, args.warmup, stream)
+        err = error_of(prec)
+        log("%s: sampled normwise error %.3e" % (prec, err))
         cold = cold_time(call(prec, C), args.cold_reps, stream, flush) if args.cold_reps else None
         results[prec] = dict(ms=ms, cold_ms=cold, tflops=flops / ms / 1e9, err=err,
                              cfg=mg.default_config(prec, "N", "N", n, n, n))
@@ -254,8 +299,9 @@ def main():
 
     f32 = results["fp32"]
     f32_call = call("fp32", C)
-    f32["median_ms"] = per_call_ms(f32_call, max(20, args.steps), stream)
-    log("fp32: median of single calls %.3f ms; sampling the clock ..." % f32["median_ms"])
+    f32["median_ms"] = None if args.no_single_calls else \
+        per_call_ms(f32_call, max(20, args.steps), stream)
+    log("fp32: median of single calls %s ms; sampling the clock ..." % f32["median_ms"])
     f32["clock"] = None if (args.no_clock or under_profiler()) else clock_under_load(f32_call)
     line = {
         "metric": METRIC,
@@ -276,8 +322,11 @@ def main():
                    "tile_config": f32["cfg"]},
         "pct_of_fp32_mfma_peak": round(100.0 * f32["tflops"] / PEAK["fp32"], 2),
         "fp32_normwise_err": f32["err"],
+        "value_timing": "warm: K back-to-back launches between HIP events on the launch stream; "
+                        "the cache-flushed median (L2 and MALL overwritten before each launch, "
+                        "the paper's method) is fp32_cold_ms and roofline.cold",
         "fp32_cold_ms": f32["cold_ms"],
-        "fp32_median_ms": round(f32["median_ms"], 4),
+        "fp32_median_ms": None if f32["median_ms"] is None else round(f32["median_ms"], 4),
         "gpu_clock": f32["clock"],
     }
     key = "sgemm_f32_nn_%d" % n
@@ -421,7 +470,7 @@ def bench_small(args, mg, torch):
     A, B, C = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
     fn = lambda: mg.sgemm("N", "N", n, n, n, 1.0, A, n, B, n, 0.0, C, n)
     stream = torch.cuda.current_stream()
-    ms = timed(fn, 200, 20, stream)
+    ms = timed(fn, 200, 20, stream, min_ms=50)
     med = per_call_ms(fn, 50, stream)
     # The same calls replayed from a HIP graph: the device-side rate, without
     # the Python binding's per-call cost.
@@ -479,7 +528,7 @@ def bench_wide_range(args, mg, torch, oracle, synth, n):
         torch.cuda.synchronize()
         got = C.view(n, ld)[torch.from_numpy(cols).to(dev), torch.from_numpy(rows).to(dev)]
         err = oracle.normwise_rel_err(got.double().cpu().numpy(), ref)
-        ms = timed(fn, args.steps, args.warmup, stream)
+        ms = timed(fn, args.steps, args.warmup, stream, min_ms=50)
         out[prec] = {"ms": round(ms, 4), "tflops": round(2.0 * n ** 3 / ms / 1e9, 3),
                      "normwise_err": err}
         log("wide-range inputs %s: %.3f ms, sampled normwise error %.3e" % (prec, ms, err))
@@ -504,7 +553,7 @@ def bench_vendor(args, torch, n, alpha, beta):
         C = torch.rand(size, size, device="cuda", generator=g) * 2 - 1
         D = torch.empty_like(C)
         fn = lambda: torch.addmm(C, A, B, beta=beta, alpha=alpha, out=D)
-        ms = timed(fn, steps, warmup, stream)
+        ms = timed(fn, steps, warmup, stream, min_ms=50)
         out["n%d" % size] = {"ms": round(ms, 4), "tflops": round(2.0 * size ** 3 / ms / 1e9, 3)}
         del A, B, C, D
     log("vendor fp32: %s" % out)
@@ -548,7 +597,7 @@ def bench_grouped(args, mg, torch):
         cfg = None if args.grouped_defaults else mg.tune_grouped(probs, prec, reps=3)[0]
         arena.copy_(init)
         plan = mg.GroupedPlan(probs, prec, bucket_configs=cfg)
-        ms_graph = timed(lambda: plan.launch(stream), args.steps, args.warmup, stream)
+        ms_graph = timed(lambda: plan.launch(stream), args.steps, args.warmup, stream, min_ms=50)
         pcode = mg.PRECISIONS[prec]
         calls = [(p["transA"].encode(), p["transB"].encode(), p["M"], p["N"], p["K"],
                   ctypes.c_float(p["alpha"]), p["A"], p["lda"], p["B"], p["ldb"],
@@ -590,7 +639,7 @@ def bench_dense(args, mg, torch):
             Xd.grad = None
             Wd.grad = None
             mg.linear(Xd, Wd, precision=prec).backward(Gd)
-        ms = timed(step, max(5, args.steps // 2), 2, stream)
+        ms = timed(step, max(5, args.steps // 2), 2, stream, min_ms=50)
         out[prec] = {"ms": round(ms, 4), "tflops": round(flops / ms / 1e9, 3)}
         log("dense layer %s: %.3f ms per fwd+bwd (%.1f TFLOP/s)" % (prec, ms, flops / ms / 1e9))
     return out
@@ -614,7 +663,7 @@ def bench_mlp(args, mg, torch):
     for prec in ("fp32", "bf16x3"):
         net = mg.MLP([torch.from_numpy(W).cuda() for W in Ws], precision=prec)
         first = float(net.step(Xd, Td, lr))
-        ms = timed(lambda: net.step(Xd, Td, lr), max(5, args.steps // 2), 2, stream)
+        ms = timed(lambda: net.step(Xd, Td, lr), max(5, args.steps // 2), 2, stream, min_ms=50)
         last = float(net.step(Xd, Td, lr))
         out[prec] = {"ms_per_step": round(ms, 4), "tflops": round(flops / ms / 1e9, 3),
                      "loss_first": round(first, 6), "loss_last": round(last, 6)}
@@ -640,7 +689,8 @@ def bench_splitk(args, mg, torch):
         res = {"default_config": mg.default_config("fp32", "N", "N", M, N, K)}
         for name, cfg in (("default", -1), ("unsplit_config_%d" % other, other)):
             ms = timed(lambda: mg.sgemm("N", "N", M, N, K, 1.5, A, c["lda"], B, c["ldb"], -0.5, C,
-                                        c["ldc"], config=cfg), max(10, args.steps), 3, stream)
+                                        c["ldc"], config=cfg), max(10, args.steps), 3, stream,
+                       min_ms=50)
             res[name] = {"ms": round(ms, 4), "tflops": round(2.0 * M * N * K / ms / 1e9, 3)}
         res["speedup"] = round(res["unsplit_config_%d" % other]["ms"] / res["default"]["ms"], 3)
         # The 16-bit forms: the library's choice (split-K) against the
@@ -651,7 +701,7 @@ def bench_splitk(args, mg, torch):
             for name, cfg in (("default", -1), ("unsplit_config_%d" % unsplit, unsplit)):
                 ms = timed(lambda: mg.sgemm("N", "N", M, N, K, 1.5, A, c["lda"], B, c["ldb"], -0.5,
                                             C, c["ldc"], precision=prec, config=cfg),
-                           max(10, args.steps), 3, stream)
+                           max(10, args.steps), 3, stream, min_ms=50)
                 r[name] = {"ms": round(ms, 4), "tflops": round(2.0 * M * N * K / ms / 1e9, 3)}
             r["speedup"] = round(r["unsplit_config_%d" % unsplit]["ms"] / r["default"]["ms"], 3)
             res[prec] = r
@@ -695,7 +745,7 @@ def bench_sweep(args, mg, torch, oracle, synth):
             ref = oracle.sgemm_entries(ta, tb, n, n, n, 1.5, c["A"], ld, c["B"], ld, -0.5, c["C"],
                                        ld, rows, cols)
             err = oracle.normwise_rel_err(got.double().cpu().numpy(), ref)
-            ms = timed(fn, steps, warmup, stream)
+            ms = timed(fn, steps, warmup, stream, min_ms=50)
             res[ta + tb] = {"ms": round(ms, 4), "tflops": round(2.0 * n ** 3 / ms / 1e9, 3),
                             "normwise_err": float("%.3e" % err),
                             "tile_config": mg.default_config("fp32", ta, tb, n, n, n)}
@@ -727,7 +777,7 @@ def bench_forms_2048(args, mg, torch, oracle, synth):
         torch.cuda.synchronize()
         got = C.view(n, ld)[torch.from_numpy(cols).cuda(), torch.from_numpy(rows).cuda()]
         err = oracle.normwise_rel_err(got.double().cpu().numpy(), ref)
-        ms = timed(fn, max(10, args.steps), args.warmup, stream)
+        ms = timed(fn, max(10, args.steps), args.warmup, stream, min_ms=50)
         out[prec] = {"ms": round(ms, 4), "tflops": round(2.0 * n ** 3 / ms / 1e9, 3),
                      "normwise_err": float("%.3e" % err)}
     for prec in ("bf16x3", "fp16s"):
@@ -747,7 +797,8 @@ def bench_prepacked(args, mg, torch, n):
     stream = torch.cuda.current_stream()
     ld = c["lda"]
     ms_call = timed(lambda: mg.sgemm("N", "N", n, n, n, 1.5, A, ld, B, ld, -0.5, C, ld,
-                                     precision="bf16x3"), args.steps, args.warmup, stream)
+                                     precision="bf16x3"), args.steps, args.warmup, stream,
+                    min_ms=50)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     pb = mg.PackedB("N", n, n, B, ld)
@@ -755,7 +806,7 @@ def bench_prepacked(args, mg, torch, n):
     torch.cuda.synchronize()
     ms_pack = e0.elapsed_time(e1)
     ms_packed = timed(lambda: pb.sgemm("N", n, 1.5, A, ld, -0.5, C, ld), args.steps,
-                      args.warmup, stream)
+                      args.warmup, stream, min_ms=50)
     pb.close()
     flops = 2.0 * n ** 3
     out = {"workload": "bf16x3 NN %d^3, op(B) packed once" % n,
@@ -766,10 +817,11 @@ def bench_prepacked(args, mg, torch, n):
         % (n, ms_packed, ms_call, ms_pack))
     # Scaled FP16: the handle also keeps op(B)'s panel exponents.
     ms_f16 = timed(lambda: mg.sgemm("N", "N", n, n, n, 1.5, A, ld, B, ld, -0.5, C, ld,
-                                    precision="fp16s"), args.steps, args.warmup, stream)
+                                    precision="fp16s"), args.steps, args.warmup, stream,
+                   min_ms=50)
     with mg.PackedB("N", n, n, B, ld, precision="fp16s") as pf:
         ms_f16p = timed(lambda: pf.sgemm("N", n, 1.5, A, ld, -0.5, C, ld), args.steps,
-                        args.warmup, stream)
+                        args.warmup, stream, min_ms=50)
     out["fp16s"] = {"ordinary_ms": round(ms_f16, 4), "packed_b_ms": round(ms_f16p, 4),
                     "packed_b_tflops": round(flops / ms_f16p / 1e9, 3),
                     "speedup": round(ms_f16 / ms_f16p, 3)}
