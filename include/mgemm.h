@@ -118,6 +118,37 @@ int mgemm_sgemm_ex(char transA, char transB, int64_t M, int64_t N, int64_t K,
                    int precision, int config);
 
 /*
+ * Activations that mgemm_sgemm_act applies to v = alpha op(A) op(B) + beta C
+ * before C is written (the paper's application, Section 4, trains a neural
+ * network whose layers are these products):
+ *   MGEMM_ACT_TANH       C <- tanh(v)                (a tanh layer's output)
+ *   MGEMM_ACT_TANH_GRAD  C <- v * (1 - aux^2)        (the gradient through a
+ *                        tanh layer whose output is aux)
+ */
+#define MGEMM_ACT_NONE      0
+#define MGEMM_ACT_TANH      1
+#define MGEMM_ACT_TANH_GRAD 2
+
+/*
+ * mgemm_sgemm_ex with an activation fused into the epilogue, so that the
+ * product is stored once, already activated.  `aux` (device, caller-owned)
+ * is read only by MGEMM_ACT_TANH_GRAD: an M x N column-major array with C's
+ * leading dimension ldc, which must not overlap C (MGEMM_ERR_ALIAS); it may
+ * be NULL otherwise.  An unknown activation, or a NULL aux that would be
+ * read, returns MGEMM_ERR_UNSUPPORTED before anything runs.  Everything
+ * else is as for mgemm_sgemm_ex, except that with an activation the quick
+ * return for (alpha == 0 or K == 0) and beta == 1 does not apply: C <-
+ * act(C) is still computed.  Split-K configurations apply the activation
+ * once, in their reduction.  tanh is the device library's tanhf.
+ */
+int mgemm_sgemm_act(char transA, char transB, int64_t M, int64_t N, int64_t K,
+                    float alpha, const float *A, int64_t lda,
+                    const float *B, int64_t ldb,
+                    float beta, float *C, int64_t ldc, void *stream,
+                    int precision, int config, int activation,
+                    const float *aux);
+
+/*
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * call as mgemm_sgemm_ex, arguments and results alike, whose workspace is

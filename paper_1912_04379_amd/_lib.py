@@ -14,6 +14,11 @@ PREC_BF16X3 = 1
 PREC_FP16_SCALED = 2
 PRECISIONS = {"fp32": PREC_FP32, "bf16x3": PREC_BF16X3, "fp16s": PREC_FP16_SCALED}
 
+ACT_NONE = 0
+ACT_TANH = 1
+ACT_TANH_GRAD = 2
+ACTIVATIONS = {None: ACT_NONE, "none": ACT_NONE, "tanh": ACT_TANH, "tanh_grad": ACT_TANH_GRAD}
+
 OK = 0
 ERR_HIP = 100
 ERR_NO_DEVICE = 101
@@ -47,6 +52,8 @@ _SIGS = {
                            _i64, _vp]),
     "mgemm_sgemm_ex": (_i32, [_ch, _ch, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32,
                               _vp, _i64, _vp, _i32, _i32]),
+    "mgemm_sgemm_act": (_i32, [_ch, _ch, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64, _f32,
+                               _vp, _i64, _vp, _i32, _i32, _i32, _vp]),
     "mgemm_sgemm_ex_noalloc": (_i32, [_ch, _ch, _i64, _i64, _i64, _f32, _vp, _i64, _vp, _i64,
                                       _f32, _vp, _i64, _vp, _i32, _i32]),
     "mgemm_config_count": (_i32, [_i32]),

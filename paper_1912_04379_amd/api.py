@@ -1,7 +1,7 @@
 """BLAS-style and torch-style entry points (argument marshalling only)."""
 import ctypes
 
-from ._lib import PRECISIONS, check, lib
+from ._lib import ACTIVATIONS, PRECISIONS, check, lib
 
 
 def stream_handle(stream=None):
@@ -71,19 +71,27 @@ def check_operands(transA, transB, M, N, K, alpha, A, lda, B, ldb, C, ldc):
 
 
 def sgemm(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, *,
-          precision="fp32", config=-1, stream=None):
-    """C <- alpha op(A) op(B) + beta C on column-major device buffers.
+          precision="fp32", config=-1, stream=None, activation=None, aux=None):
+    """C <- act(alpha op(A) op(B) + beta C) on column-major device buffers.
 
     A, B, C are float32 device tensors (read as flat column-major arrays
     from data_ptr(); the part the call references must lie in the tensor's
-    storage, else ValueError) or raw device addresses.  Raises MgemmError on
-    any non-zero status.
+    storage, else ValueError) or raw device addresses.  activation: None,
+    "tanh" or "tanh_grad" (C <- v * (1 - aux^2), aux M x N at ldc).  Raises
+    MgemmError on any non-zero status.
     """
     check_operands(transA, transB, M, N, K, alpha, A, lda, B, ldb, C, ldc)
     p = _prec(precision)
     s = stream_handle(stream)
     L = lib()
-    if p == 0 and config == -1:
+    act = ACTIVATIONS[activation] if not isinstance(activation, int) else activation
+    if act != 0:
+        if aux is not None:
+            _check_tensor(aux, "aux")
+            _check_extent(aux, "aux", M, N, ldc)
+        st = L.mgemm_sgemm_act(transA.encode(), transB.encode(), M, N, K, alpha, _ptr(A), lda,
+                               _ptr(B), ldb, beta, _ptr(C), ldc, s, p, config, act, _ptr(aux))
+    elif p == 0 and config == -1:
         st = L.mgemm_sgemm(transA.encode(), transB.encode(), M, N, K, alpha, _ptr(A), lda,
                            _ptr(B), ldb, beta, _ptr(C), ldc, s)
     else:
@@ -129,10 +137,13 @@ def colmajor_view(T):
     return _view(tuple(T.shape), tuple(T.stride()))
 
 
-def matmul(X, W, *, alpha=1.0, beta=0.0, precision="fp32", config=-1, out=None, stream=None):
-    """Y = alpha X @ W + beta Y for 2-D float32 device tensors; Y is a new
-    (or the given contiguous) row-major (b x o) tensor.  beta != 0 needs
-    ``out``, whose values it scales.  One library call."""
+def matmul(X, W, *, alpha=1.0, beta=0.0, precision="fp32", config=-1, out=None, stream=None,
+           activation=None, aux=None):
+    """Y = act(alpha X @ W + beta Y) for 2-D float32 device tensors; Y is a
+    new (or the given contiguous) row-major (b x o) tensor.  beta != 0 needs
+    ``out``, whose values it scales.  activation: None, "tanh", or
+    "tanh_grad" with ``aux`` a contiguous (b x o) tensor (Y = v * (1 -
+    aux^2)).  One library call."""
     import torch
     ta, tb, M, N, K, lda, ldb, ldc = matmul_args(tuple(X.shape), tuple(X.stride()),
                                                  tuple(W.shape), tuple(W.stride()))
@@ -143,8 +154,11 @@ def matmul(X, W, *, alpha=1.0, beta=0.0, precision="fp32", config=-1, out=None, 
         out = torch.empty((b, o), dtype=torch.float32, device=X.device)
     elif tuple(out.shape) != (b, o) or (b > 1 and o > 0 and out.stride() != (o, 1)):
         raise ValueError("out must be a contiguous (b x o) tensor")
+    if aux is not None and (tuple(aux.shape) != (b, o) or (b > 1 and o > 0 and
+                                                          aux.stride() != (o, 1))):
+        raise ValueError("aux must be a contiguous (b x o) tensor")
     sgemm(ta, tb, M, N, K, alpha, W, lda, X, ldb, beta, out, ldc,
-          precision=precision, config=config, stream=stream)
+          precision=precision, config=config, stream=stream, activation=activation, aux=aux)
     return out
 
 

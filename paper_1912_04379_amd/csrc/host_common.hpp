@@ -74,10 +74,12 @@ struct FixedWorkspace {
 // configuration choice and launches.  `fixed` == nullptr takes workspace
 // from the pool; otherwise configurations whose workspace exceeds
 // fixed->cap run as they would without one (see mgemm_sgemm_ex_noalloc).
+// `act` / `aux`: the fused activation (MGEMM_ACT_*) and its second operand.
 int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
                const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
                int64_t ldc, void* stream, int precision, int config,
-               const FixedWorkspace* fixed);
+               const FixedWorkspace* fixed, int act = MGEMM_ACT_NONE,
+               const float* aux = nullptr);
 
 // True when MGEMM_FAULT=alloc asks every workspace, packed-operand or plan
 // allocation to fail (a test hook for the MGEMM_ERR_ALLOC paths).

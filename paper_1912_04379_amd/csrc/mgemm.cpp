@@ -183,7 +183,7 @@ struct Dispatch {
 static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
                       const float* A, int64_t lda, const float* B, int64_t ldb, float beta,
                       float* C, int64_t ldc, void* stream, int precision, int config,
-                      const FixedWorkspace* fixed, Dispatch& dp) {
+                      const FixedWorkspace* fixed, int act, const float* aux, Dispatch& dp) {
     std::string why;
     const int bad = validate(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, why);
     if (bad) return fail(bad, why);
@@ -191,13 +191,22 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
         return fail(MGEMM_ERR_UNSUPPORTED, "unknown precision");
     if (config < -1 || config >= config_count(precision))
         return fail(MGEMM_ERR_UNSUPPORTED, "unknown tile configuration");
+    if (act < MGEMM_ACT_NONE || act > MGEMM_ACT_TANH_GRAD)
+        return fail(MGEMM_ERR_UNSUPPORTED, "unknown activation");
+    if (act == MGEMM_ACT_TANH_GRAD && M > 0 && N > 0 && aux == nullptr)
+        return fail(MGEMM_ERR_UNSUPPORTED, "aux is NULL");
     const int ta = trans_code(transA), tb = trans_code(transB);
-    // Quick returns (reference BLAS).
+    // Quick returns (reference BLAS); an activation still has to be applied
+    // when C itself is left as it is.
     if (M == 0 || N == 0) return MGEMM_OK;
     const bool no_product = alpha == 0.0f || K == 0;
-    if (no_product && beta == 1.0f) return MGEMM_OK;
+    if (no_product && beta == 1.0f && act == MGEMM_ACT_NONE) return MGEMM_OK;
     if (overlaps(ta, tb, M, N, K, alpha, A, lda, B, ldb, C, ldc))
         return fail(MGEMM_ERR_ALIAS, "C overlaps A or B");
+    if (act == MGEMM_ACT_TANH_GRAD) {
+        const Extent c = extent_of(C, M, N, ldc, 0), x = extent_of(aux, M, N, ldc, 0);
+        if (c.lo < x.hi && x.lo < c.hi) return fail(MGEMM_ERR_ALIAS, "C overlaps aux");
+    }
     int dev = 0;
     int st = check_device(&dev);
     if (st) return st;
@@ -210,7 +219,8 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
     }
 
     hipStream_t s = (hipStream_t)stream;
-    GemmDesc d{A, B, C, M, N, K, lda, ldb, ldc, alpha, beta, nullptr, nullptr};
+    GemmDesc d{A, B, C, M, N, K, lda, ldb, ldc, alpha, beta, nullptr, nullptr, act,
+               act == MGEMM_ACT_TANH_GRAD ? aux : nullptr};
     hipError_t e;
     if (no_product) {
         dp.path = "scale_c";
@@ -363,17 +373,19 @@ static const char* prec_name(int precision) {
 int sgemm_impl(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
                const float* A, int64_t lda, const float* B, int64_t ldb, float beta, float* C,
                int64_t ldc, void* stream, int precision, int config,
-               const FixedWorkspace* fixed) {
+               const FixedWorkspace* fixed, int act, const float* aux) {
     Dispatch dp;
     const int st = sgemm_body(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                              stream, precision, config, fixed, dp);
+                              stream, precision, config, fixed, act, aux, dp);
     if (log_enabled())
         log_line("sgemm%s %s %c%c M=%lld N=%lld K=%lld lda=%lld ldb=%lld ldc=%lld alpha=%g "
-                 "beta=%g config=%d -> %s cfg=%d splits=%d workspace=%lld status=%d%s%s",
+                 "beta=%g config=%d%s -> %s cfg=%d splits=%d workspace=%lld status=%d%s%s",
                  fixed ? "_noalloc" : "", prec_name(precision), transA ? transA : '?',
                  transB ? transB : '?', (long long)M, (long long)N, (long long)K,
                  (long long)lda, (long long)ldb, (long long)ldc, (double)alpha, (double)beta,
-                 config, dp.path, dp.cfg, dp.splits, (long long)dp.ws_bytes, st,
+                 config,
+                 act == MGEMM_ACT_TANH ? " act=tanh" : act == MGEMM_ACT_TANH_GRAD ? " act=tanh_grad" : "",
+                 dp.path, dp.cfg, dp.splits, (long long)dp.ws_bytes, st,
                  st ? " " : "", st ? g_last_error.c_str() : "");
     return st;
 }
@@ -398,6 +410,14 @@ int mgemm_sgemm_ex(char transA, char transB, int64_t M, int64_t N, int64_t K, fl
                    float* C, int64_t ldc, void* stream, int precision, int config) {
     return sgemm_impl(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream,
                       precision, config, nullptr);
+}
+
+int mgemm_sgemm_act(char transA, char transB, int64_t M, int64_t N, int64_t K, float alpha,
+                    const float* A, int64_t lda, const float* B, int64_t ldb, float beta,
+                    float* C, int64_t ldc, void* stream, int precision, int config,
+                    int activation, const float* aux) {
+    return sgemm_impl(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, stream,
+                      precision, config, nullptr, activation, aux);
 }
 
 int mgemm_config_count(int precision) { return config_count(precision); }

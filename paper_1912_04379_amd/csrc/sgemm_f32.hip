@@ -156,15 +156,17 @@ __global__ __launch_bounds__(Cfg::NT, Cfg::WPE) void sgemm_f32_splitk_kernel(
     p.ldc = d.M;
     p.alpha = 1.0f;
     p.beta = 0.0f;
+    p.act = ACT_NONE;   // applied once, by the reduction
     tile_f32<Cfg, AK, BKC, true>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
 }
 
-// C <- alpha * sum_s ws[s] + beta * C, s in increasing order; beta == 0
-// never reads C.  Grid-stride over the M*N outputs, m fastest.
+// C <- act(alpha * sum_s ws[s] + beta * C), s in increasing order; beta ==
+// 0 never reads C.  Grid-stride over the M*N outputs, m fastest.
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restrict__ ws,
                                                             int splits, int64_t M, int64_t N,
                                                             float* C, int64_t ldc, float alpha,
-                                                            float beta) {
+                                                            float beta, int act,
+                                                            const float* __restrict__ aux) {
     const int64_t mn = M * N;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < mn;
          i += (int64_t)gridDim.x * 256) {
@@ -172,7 +174,8 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float* __restr
         for (int s = 1; s < splits; ++s) sum += ws[(int64_t)s * mn + i];
         const int64_t n = i / M, m = i - n * M;
         float* c = C + m + n * ldc;
-        *c = beta == 0.0f ? alpha * sum : fmaf(beta, *c, alpha * sum);
+        const float v = beta == 0.0f ? alpha * sum : fmaf(beta, *c, alpha * sum);
+        *c = activate(act, v, act == ACT_TANH_GRAD ? aux[m + n * ldc] : 0.0f);
     }
 }
 
@@ -217,7 +220,7 @@ hipError_t launch_splitk_reduce(const float* ws, int splits, const GemmDesc& d, 
     int64_t blocks = (mn + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, ws,
-                       splits, d.M, d.N, d.C, d.ldc, d.alpha, d.beta);
+                       splits, d.M, d.N, d.C, d.ldc, d.alpha, d.beta, d.act, d.aux);
     return hipGetLastError();
 }
 
@@ -274,12 +277,14 @@ hipError_t launch_f32(int cfg, bool ta, bool tb, const GemmDesc& d, hipStream_t 
 // reads C.  Grid-stride over rows (x) and columns (y) of C.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void scale_c_kernel(float* C, int64_t M, int64_t N,
-                                                      int64_t ldc, float beta) {
+                                                      int64_t ldc, float beta, int act,
+                                                      const float* __restrict__ aux) {
     for (int64_t n = blockIdx.y; n < N; n += gridDim.y)
         for (int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x; m < M;
              m += (int64_t)gridDim.x * 256) {
             float* c = C + m + n * ldc;
-            *c = beta == 0.0f ? 0.0f : beta * *c;
+            const float v = beta == 0.0f ? 0.0f : beta * *c;
+            *c = activate(act, v, act == ACT_TANH_GRAD ? aux[m + n * ldc] : 0.0f);
         }
 }
 
@@ -287,7 +292,7 @@ hipError_t launch_scale_c(const GemmDesc& d, hipStream_t s) {
     const int64_t gx = (d.M + 255) / 256 < 64 ? (d.M + 255) / 256 : 64;
     const int64_t gy = d.N < 4096 ? d.N : 4096;
     hipLaunchKernelGGL(scale_c_kernel, dim3((uint32_t)gx, (uint32_t)gy), dim3(256), 0, s,
-                       d.C, d.M, d.N, d.ldc, d.beta);
+                       d.C, d.M, d.N, d.ldc, d.beta, d.act, d.aux);
     return hipGetLastError();
 }
 

@@ -110,6 +110,7 @@ __global__ __launch_bounds__(Cfg::NT) void sgemm_lowp_splitk_kernel(GemmDesc d, 
     p.ldc = d.M;
     p.alpha = 1.0f;
     p.beta = 0.0f;
+    p.act = ACT_NONE;   // applied once, by the reduction
     tile_lowp<Cfg, F, AK, BKC, true>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, lowp_smem);
 }
 

@@ -136,6 +136,15 @@ __global__ __launch_bounds__(256) void sgemm_small_kernel(GemmDesc d, uint32_t t
 #pragma unroll
         for (int r = 0; r < 4; ++r) v[r] = d.alpha * acc[r];
     }
+    if (d.act != ACT_NONE) {
+        const BufRsrc ra = make_rsrc(d.act == ACT_TANH_GRAD ? d.aux + first : d.C + first,
+                                     d.act == ACT_TANH_GRAD
+                                         ? 4 * (stored_extent(d.M, d.N, d.ldc) - first)
+                                         : 0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            v[r] = activate(d.act, v[r], d.act == ACT_TANH_GRAD ? buf_load_f32(ra, off[r]) : 0.0f);
+    }
 #pragma unroll
     for (int r = 0; r < 4; ++r) buf_store_f32(rc, off[r], v[r]);
 }

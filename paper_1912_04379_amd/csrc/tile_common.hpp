@@ -35,7 +35,22 @@ struct GemmDesc {
     // exponents of op(B) (NULL otherwise).
     const int* expA;
     const int* expB;
+    // Activation applied to v = alpha acc + beta C before it is stored
+    // (ACT_NONE, ACT_TANH or ACT_TANH_GRAD); aux: ACT_TANH_GRAD's second
+    // operand, M x N with C's leading dimension.
+    int act;
+    const float* aux;
 };
+
+// Fused activations of the epilogue.  ACT_TANH: tanh(v).  ACT_TANH_GRAD:
+// v (1 - y^2), the derivative of tanh at the point whose tanh is y, times v.
+constexpr int ACT_NONE = 0, ACT_TANH = 1, ACT_TANH_GRAD = 2;
+
+__device__ inline float activate(int act, float v, float y) {
+    if (act == ACT_TANH) return tanhf(v);
+    if (act == ACT_TANH_GRAD) return v * (1.0f - y * y);
+    return v;
+}
 
 // ---------------------------------------------------------------------------
 // Rasterisation.  The hardware hands work-group w to XCD (w mod 8); each XCD
@@ -257,12 +272,17 @@ __device__ inline int mfma32_row(int r, int lane) {
 }
 
 struct EpilogueB {
-    BufRsrc r;
+    BufRsrc r, raux;
     int64_t mrem, nrem, ldc;
     float alpha, beta;
+    int act;
     __device__ inline EpilogueB(const GemmDesc& d, int64_t m0, int64_t n0) {
         const int64_t first = m0 + n0 * d.ldc;
-        r = make_rsrc(d.C + first, 4 * (stored_extent(d.M, d.N, d.ldc) - first));
+        const int64_t bytes = 4 * (stored_extent(d.M, d.N, d.ldc) - first);
+        r = make_rsrc(d.C + first, bytes);
+        act = d.act;
+        raux = make_rsrc(act == ACT_TANH_GRAD ? d.aux + first : d.C + first,
+                         act == ACT_TANH_GRAD ? bytes : 0);
         mrem = d.M - m0;
         nrem = d.N - n0;
         ldc = d.ldc;
@@ -292,6 +312,17 @@ struct EpilogueB {
 #pragma unroll
             for (int e = 0; e < 16; ++e) v[e] = alpha * acc[e];
         }
+        if (act == ACT_TANH_GRAD) {
+            // aux is read through its own descriptor at the offsets of C.
+            float y[16];
+#pragma unroll
+            for (int e = 0; e < 16; ++e) y[e] = buf_load_f32(raux, off[e]);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = activate(act, v[e], y[e]);
+        } else if (act != ACT_NONE) {
+#pragma unroll
+            for (int e = 0; e < 16; ++e) v[e] = activate(act, v[e], 0.0f);
+        }
 #pragma unroll
         for (int e = 0; e < 16; ++e) buf_store_f32(r, off[e], v[e]);
     }
@@ -299,10 +330,14 @@ struct EpilogueB {
 
 struct EpilogueG {
     float* C;
+    const float* aux;
     int64_t mrem, nrem, ldc;
     float alpha, beta;
+    int act;
     __device__ inline EpilogueG(const GemmDesc& d, int64_t m0, int64_t n0) {
         C = d.C + m0 + n0 * d.ldc;
+        act = d.act;
+        aux = act == ACT_TANH_GRAD ? d.aux + m0 + n0 * d.ldc : nullptr;
         mrem = d.M - m0;
         nrem = d.N - n0;
         ldc = d.ldc;
@@ -329,6 +364,15 @@ struct EpilogueG {
             } else {
 #pragma unroll
                 for (int e = 0; e < 4; ++e) v[e] = alpha * acc[4 * g + e];
+            }
+            if (act != ACT_NONE) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float y = act == ACT_TANH_GRAD && ok[e]
+                                        ? aux[m + (int64_t)(n0b + mfma32_row(4 * g + e, lane)) * ldc]
+                                        : 0.0f;
+                    v[e] = activate(act, v[e], y);
+                }
             }
 #pragma unroll
             for (int e = 0; e < 4; ++e)

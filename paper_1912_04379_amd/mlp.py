@@ -15,13 +15,18 @@ backpropagation:
     dL/dW_l = H_{l-1}^T G_l
     G_{l-1} = (G_l W_l^T) o (1 - H_{l-1}^2)        (l > 1)
 
-Every product is one library call on row-major tensors.  The update is
-fused into the weight-gradient product: C = W_l, alpha = -lr, beta = 1
-computes W_l - lr H_{l-1}^T G_l in the kernel's epilogue, so the gradient
-is never stored and the weights are read and written once.  G_{l-1} is
-formed from W_l before that update.  The activation, its derivative and the
-output error are torch elementwise operations: they are not products and
-take a few percent of the step's time.
+Every product is one library call on row-major tensors, and the
+elementwise work around the products is fused into their epilogues:
+* the hidden layers' tanh into the forward products (the library's tanh
+  activation), so each H_l is stored once, already activated;
+* the tanh derivative into the input-gradient products (the tanh_grad
+  activation with aux = H_{l-1}): G_{l-1} = (G_l W_l^T) o (1 - H_{l-1}^2) in
+  one pass;
+* the update into the weight-gradient product: C = W_l, alpha = -lr, beta =
+  1 computes W_l - lr H_{l-1}^T G_l, so the gradient is never stored and the
+  weights are read and written once.  G_{l-1} is formed from W_l before that
+  update.
+Only the output error (H_L - T) / B and the loss are torch operations.
 """
 import torch
 
@@ -61,10 +66,8 @@ class MLP:
         H = [X]
         last = len(self.weights) - 1
         for l, W in enumerate(self.weights):
-            Z = matmul(H[-1], W, precision=self.precision)
-            if l < last:
-                torch.tanh_(Z)
-            H.append(Z)
+            H.append(matmul(H[-1], W, precision=self.precision,
+                            activation="tanh" if l < last else None))
         return H
 
     def _output_gradient(self, H, T):
@@ -87,10 +90,10 @@ class MLP:
         return loss, dWs
 
     def _backward_input(self, G, l, H):
-        # (G W_l^T) o (1 - H_{l-1}^2): the product in the library, the tanh
-        # derivative in one elementwise pass (torch's fused tanh backward).
-        Gp = matmul(G, self.weights[l].t(), precision=self.precision)
-        return torch.ops.aten.tanh_backward(Gp, H[l])
+        # (G W_l^T) o (1 - H_{l-1}^2) in one library call: the product with
+        # the tanh derivative in its epilogue (H[l] is H_{l-1}).
+        return matmul(G, self.weights[l].t(), precision=self.precision,
+                      activation="tanh_grad", aux=H[l])
 
     def step(self, X, T, lr):
         """One gradient-descent step on the batch (X, T); returns the loss
