@@ -268,7 +268,7 @@ typedef struct mgemm_plan mgemm_plan;
  * Problems are sorted into four size buckets (mgemm_grouped_bucket); each
  * bucket uses one tile variant.  `tune_cache` chooses them:
  *   - NULL: the library defaults (one variant for every bucket: FP32
- *     64x64x16, BF16x3 128x128);
+ *     64x64x32, BF16x3 128x128);
  *   - a file path: the variants recorded in that file for this device
  *     (architecture and CU count), library version, precision and batch
  *     (the problems' trans flags and sizes, in order).  When the file has
@@ -285,12 +285,17 @@ typedef struct mgemm_plan mgemm_plan;
  * (Section 3); the cache keeps such experiments across processes.
  *
  * The plan uploads to device memory it owns a descriptor table and, per
- * tile variant in use, a schedule: every tile assigned to one work-group
- * of that variant's persistent kernel, largest tiles first, each to the
- * least-loaded work-group.  It records the launches (one per variant in
- * use, costliest first) into a HIP graph on a private stream.  Results
- * are bitwise reproducible: every tile of C is written by one work-group,
- * no atomics.
+ * tile variant in use, up to eight work queues of tiles (one per XCD:
+ * whole problems to the least-loaded queue, each queue costliest tile
+ * first) with one counter each.  The variant's persistent work-groups take
+ * tiles from their XCD's queue with an atomic counter and then help the
+ * other queues; the last work-group to finish zeroes the counters.  It
+ * records the launches (one per variant in use, costliest first) into a
+ * HIP graph on a private stream.  Results are bitwise reproducible: a
+ * tile's result does not depend on which work-group computes it, and
+ * every tile of C is written by one work-group.  Launches of one plan must
+ * not overlap in time (they share the counters, as well as C): launch it
+ * on one stream, or order the streams.
  */
 int mgemm_grouped_plan_create(const mgemm_problem *problems, int64_t count,
                               int precision, const char *tune_cache,

@@ -2,17 +2,22 @@
 //
 // A plan holds, in device memory, one descriptor per problem (operands,
 // sizes, trans flags, the tile variant chosen for its size bucket, its tile
-// grid) and a schedule: the (problem, tile) references of every work-group
-// of the persistent kernel, made on the host by longest-processing-time-
-// first list scheduling (tiles by decreasing cost ~ (K + 32) x tile area,
-// each to the least-loaded work-group; the first G tiles, the largest, go
-// to work-groups 0..G-1 in order).  The kernel starts (CUs x work-groups
-// per CU) work-groups; after an XCD-aware renumbering (neighbouring
-// work-group numbers run on one XCD, so the neighbouring tiles of one
-// problem they start with share its operands in that XCD's L2), work-group
-// w computes its own list.  Every tile is written by exactly one work-group
-// with no atomics, so results are bitwise reproducible run to run and
-// between the graph replay and a direct launch.
+// grid) and, per launch (one per tile variant in use), up to eight work
+// queues of (problem, tile) references, one per XCD.  The host fills the
+// queues: whole problems (a large one cut into runs of tiles) go to the
+// queue with the least work so far, and each queue holds its tiles
+// costliest first (cost ~ k slabs + a fixed per-tile share).  The kernel
+// starts (CUs x work-groups per CU) work-groups; work-group w serves the
+// queue of its XCD (w mod 8) by taking the next tile with an atomic
+// counter, then helps the other queues in turn once its own is empty.  A
+// tile's result does not depend on which work-group computes it or when,
+// and every tile is written by exactly one work-group, so results are
+// bitwise reproducible run to run and between the graph replay and a
+// direct launch.  Taking tiles as work-groups free up balances the load
+// against the tiles' real durations, which a static schedule could only
+// estimate; keeping a problem on one XCD keeps its operands in that XCD's
+// L2.  The last work-group to finish puts the counters back to zero, so
+// every launch finds them zeroed.
 //
 // The plan records its launch into a HIP graph once; mgemm_grouped_plan_launch
 // replays it.  mgemm_grouped_tune picks the variant of each size bucket by
@@ -69,10 +74,20 @@ constexpr int lp_lds() { return 2 * 2 * (Cfg::BM + Cfg::BN) * Cfg::ROW_BYTES; }
 
 // Default variant per size bucket (bucket = by max(M, N)): one variant for
 // every bucket, so an untuned batch is one launch (measured fastest on a
-// batch of 512 problems with M, N, K uniform on 16..512: FP32 64x64, with
-// 16- and 32-deep slabs within 1% of each other; BF16x3 128x128).
-static const int DEFAULT_F32[NUM_BUCKETS] = {0, 0, 0, 0};
+// batch of 512 problems with M, N, K uniform on 16..512: FP32 64x64x32, 2%
+// ahead of 64x64x16; BF16x3 128x128, level with 128x64).
+static const int DEFAULT_F32[NUM_BUCKETS] = {2, 2, 2, 2};
 static const int DEFAULT_LP[NUM_BUCKETS] = {1, 1, 1, 1};
+
+// A tile's fixed cost (prologue, epilogue, the hand-over to the next tile)
+// in units of one k slab of its own variant: least-squares fits of measured
+// tile durations against their slab counts on the 512-problem batch (M, N,
+// K uniform on 16..512).
+static double tile_overhead_slabs(int precision, int v) {
+    static const double f32[NUM_VARIANTS] = {0.5, 0.5, 0.5};
+    static const double lp[NUM_VARIANTS] = {2.0, 4.0, 3.0};
+    return precision == MGEMM_PREC_FP32 ? f32[v] : lp[v];
+}
 
 static int bucket_of(int64_t M, int64_t N) {
     const int64_t s = M > N ? M : N;
@@ -101,41 +116,82 @@ constexpr int variant_lds() {
     else return lp_lds<VariantLP<V>>();
 }
 
-// One persistent kernel per (precision, tile variant): work-group w (after
-// the XCD renumbering) computes its scheduled tiles starts[w] ..
-// starts[w+1]-1.  The table pointers are kernel arguments, so every field
-// of a problem is a wave-uniform scalar load, and the four operand layouts
-// are inlined tile code, as in the single-call kernels.
+// One persistent kernel per (precision, tile variant).  The queues of the
+// launch are qstarts[q] .. qstarts[q+1]-1 of `tiles` (q < nq); counter q
+// (counters[q * CTR_STRIDE]) is queue q's next ticket and counter nq counts
+// finished work-groups.  Each counter has a 256-byte line of its own:
+// atomics on one line are served one at a time, so counters sharing a line
+// would serialise every work-group's draw.
+// Thread 0 draws the ticket for the next tile when a tile starts, so the
+// atomic's round trip overlaps the tile; the ticket is resolved, and handed
+// to the work-group through LDS, when the tile is done.  The table pointers
+// are kernel arguments, so every field of a problem is a wave-uniform
+// scalar load, and the four operand layouts are inlined tile code, as in
+// the single-call kernels.
+constexpr uint32_t NO_TILE = 0xffffffffu;
+constexpr uint32_t CTR_STRIDE = 64;
+
 template <int PREC, int V>
 __global__ __launch_bounds__(256, 2) void grouped_kernel(const GroupedProblem* __restrict__ probs,
                                                       const TileRef* __restrict__ tiles,
-                                                      const uint32_t* __restrict__ starts) {
+                                                      const uint32_t* __restrict__ qstarts,
+                                                      uint32_t* __restrict__ counters, uint32_t nq) {
     extern __shared__ __attribute__((aligned(16))) char grouped_smem[];
-    const uint32_t w = xcd_remap(blockIdx.x, gridDim.x);
-    const uint32_t end = starts[w + 1];
-    for (uint32_t t = starts[w]; t < end; ++t) {
+    __shared__ uint32_t next_tile;
+    // Thread 0's cursor: the queue it draws from and how many queues it has
+    // not yet found empty.  Each queue is found empty at most once, so a
+    // work-group draws at most (its tiles + nq) tickets.
+    uint32_t q = blockIdx.x % nq, left = nq;
+    auto resolve = [&](uint32_t ticket) -> uint32_t {
+        for (;;) {
+            if (ticket < qstarts[q + 1] - qstarts[q]) return qstarts[q] + ticket;
+            q = q + 1 == nq ? 0 : q + 1;
+            if (--left == 0) return NO_TILE;
+            ticket = atomicAdd(&counters[q * CTR_STRIDE], 1u);
+        }
+    };
+    if (threadIdx.x == 0) next_tile = resolve(atomicAdd(&counters[q * CTR_STRIDE], 1u));
+    __syncthreads();
+    uint32_t t = next_tile;
+    while (t != NO_TILE) {
+        uint32_t ticket = 0;
+        if (threadIdx.x == 0) ticket = atomicAdd(&counters[q * CTR_STRIDE], 1u);
         const TileRef tr = tiles[t];
         const GroupedProblem& gp = probs[tr.problem];
         const GemmDesc d = gp.d;
         const uint32_t tm = tr.tile % gp.tiles_m, tn = tr.tile / gp.tiles_m;
+        // The work-item index, opaque to the compiler in every iteration:
+        // otherwise it hoists the tile code's per-lane addresses out of this
+        // loop and keeps them all live across it (about 45 more VGPRs for
+        // the 64 x 64 tile, and lower occupancy).
+        int tid = threadIdx.x;
+        asm volatile("" : "+v"(tid));
         // op(A) is K-contiguous for A 'T'; op(B) is K-contiguous for B 'N'.
         if constexpr (PREC == MGEMM_PREC_FP32) {
             using Cfg = VariantF32<V>;
             const int64_t m0 = (int64_t)tm * Cfg::BM, n0 = (int64_t)tn * Cfg::BN;
             float* sm = reinterpret_cast<float*>(grouped_smem);
-            if (!gp.ta && !gp.tb) tile_f32<Cfg, false, true, true>(d, m0, n0, sm);
-            else if (!gp.ta)      tile_f32<Cfg, false, false, true>(d, m0, n0, sm);
-            else if (!gp.tb)      tile_f32<Cfg, true, true, true>(d, m0, n0, sm);
-            else                  tile_f32<Cfg, true, false, true>(d, m0, n0, sm);
+            if (!gp.ta && !gp.tb) tile_f32<Cfg, false, true, true>(d, m0, n0, sm, tid);
+            else if (!gp.ta)      tile_f32<Cfg, false, false, true>(d, m0, n0, sm, tid);
+            else if (!gp.tb)      tile_f32<Cfg, true, true, true>(d, m0, n0, sm, tid);
+            else                  tile_f32<Cfg, true, false, true>(d, m0, n0, sm, tid);
         } else {
             using Cfg = VariantLP<V>;
             const int64_t m0 = (int64_t)tm * Cfg::BM, n0 = (int64_t)tn * Cfg::BN;
-            if (!gp.ta && !gp.tb) tile_lowp<Cfg, Form::BF16X3, false, true, true>(d, m0, n0, grouped_smem);
-            else if (!gp.ta)      tile_lowp<Cfg, Form::BF16X3, false, false, true>(d, m0, n0, grouped_smem);
-            else if (!gp.tb)      tile_lowp<Cfg, Form::BF16X3, true, true, true>(d, m0, n0, grouped_smem);
-            else                  tile_lowp<Cfg, Form::BF16X3, true, false, true>(d, m0, n0, grouped_smem);
+            if (!gp.ta && !gp.tb) tile_lowp<Cfg, Form::BF16X3, false, true, true>(d, m0, n0, grouped_smem, tid);
+            else if (!gp.ta)      tile_lowp<Cfg, Form::BF16X3, false, false, true>(d, m0, n0, grouped_smem, tid);
+            else if (!gp.tb)      tile_lowp<Cfg, Form::BF16X3, true, true, true>(d, m0, n0, grouped_smem, tid);
+            else                  tile_lowp<Cfg, Form::BF16X3, true, false, true>(d, m0, n0, grouped_smem, tid);
         }
-        __syncthreads();  // LDS is reused by the next tile
+        __syncthreads();  // LDS is reused by the next tile; next_tile was read
+        if (threadIdx.x == 0) next_tile = resolve(ticket);
+        __syncthreads();
+        t = next_tile;
+    }
+    // Every ticket this work-group drew has returned; the last work-group
+    // out zeroes the counters for the next launch.
+    if (threadIdx.x == 0 && atomicAdd(&counters[nq * CTR_STRIDE], 1u) == gridDim.x - 1) {
+        for (uint32_t i = 0; i <= nq; ++i) atomicExch(&counters[i * CTR_STRIDE], 0u);
     }
 }
 
@@ -158,11 +214,13 @@ static int lds_of(int precision, int v) {
                   : v == 1 ? variant_lds<MGEMM_PREC_BF16X3, 1>() : variant_lds<MGEMM_PREC_BF16X3, 2>();
 }
 
-// One launch of a plan: the kernel of one variant over its own schedule.
+// One launch of a plan: the kernel of one variant over its own queues.
 struct VariantLaunch {
     int variant;
     uint32_t grid;
-    int64_t starts_off;   // first of its grid + 1 offsets in the plan's starts table
+    uint32_t nq;          // queues (at most one per XCD, at most grid)
+    int64_t starts_off;   // first of its nq + 1 offsets in the plan's starts table
+    int64_t counters_off; // first of its (nq + 1) x CTR_STRIDE counter words
 };
 
 }  // namespace mgemm
@@ -176,7 +234,9 @@ struct mgemm_plan {
     std::vector<mgemm::VariantLaunch> launches;   // in launch order
     mgemm::GroupedProblem* d_probs = nullptr;
     mgemm::TileRef* d_tiles = nullptr;
-    uint32_t* d_starts = nullptr;   // grid + 1 offsets into d_tiles
+    uint32_t* d_starts = nullptr;   // per launch, nq + 1 queue offsets into d_tiles
+    uint32_t* d_counters = nullptr; // per launch, nq tickets + 1 finished count, one line each
+                                    // (zero between launches)
     hipStream_t capture = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -199,6 +259,7 @@ static void plan_free(mgemm_plan* p) {
     if (p->d_probs) (void)hipFree(p->d_probs);
     if (p->d_tiles) (void)hipFree(p->d_tiles);
     if (p->d_starts) (void)hipFree(p->d_starts);
+    if (p->d_counters) (void)hipFree(p->d_counters);
     delete p;
 }
 
@@ -213,7 +274,9 @@ static hipError_t launch_plan_kernel(const mgemm_plan* p, hipStream_t s) {
         const GroupedProblem* probs = p->d_probs;
         const TileRef* tiles = p->d_tiles;
         const uint32_t* starts = p->d_starts + l.starts_off;
-        void* args[] = {&probs, &tiles, &starts};
+        uint32_t* counters = p->d_counters + l.counters_off;
+        uint32_t nq = l.nq;
+        void* args[] = {&probs, &tiles, &starts, &counters, &nq};
         hipError_t e = hipLaunchKernel(k, dim3(l.grid), dim3(256), args,
                                        (size_t)lds_of(p->precision, l.variant), s);
         if (e != hipSuccess) return e;
@@ -297,53 +360,53 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
                         (kind == 1 ? ": C overlaps another problem's C"
                                    : ": C overlaps an operand of the batch"));
     }
-    // Tile list, longest first (cost ~ K x tile area; ties keep problem order).
-    std::vector<TileRef> tl;
-    std::vector<double> cost;
+    // Tiles per problem, and the cost of one: its k slabs plus a fixed share
+    // for its prologue and epilogue, times the tile's MFMA area (edge tiles
+    // run the whole tile's MFMAs).
+    std::vector<uint32_t> ntile(live.size());
+    std::vector<double> tcost(live.size());
+    uint64_t total_tiles = 0;
     for (size_t i = 0; i < live.size(); ++i) {
         const VariantShape vs = variant_shape(precision, live[i].variant);
-        const double c = (double)(live[i].d.K + 32) * vs.bm * vs.bn;
         const uint64_t n = (uint64_t)live[i].tiles_m * live[i].tiles_n;
         if (n > 0xffffffffULL) return fail(MGEMM_ERR_UNSUPPORTED, "too many tiles");
-        for (uint32_t t = 0; t < (uint32_t)n; ++t) {
-            tl.push_back(TileRef{(uint32_t)i, t});
-            cost.push_back(c);
-        }
+        ntile[i] = (uint32_t)n;
+        total_tiles += n;
+        const double slabs = (double)((live[i].d.K + vs.bk - 1) / vs.bk) +
+                             tile_overhead_slabs(precision, live[i].variant);
+        tcost[i] = slabs * vs.bk * vs.bm * vs.bn;
     }
-    if (tl.size() > 0xffffffffULL) return fail(MGEMM_ERR_UNSUPPORTED, "too many tiles");
+    if (total_tiles > 0xffffffffULL) return fail(MGEMM_ERR_UNSUPPORTED, "too many tiles");
     int st = check_device(nullptr);
     if (st) return st;
     mgemm_plan* p = new mgemm_plan();
     hipError_t e = hipGetDevice(&p->device);
     p->precision = precision;
     p->nprob = (int64_t)live.size();
-    p->ntiles = (int64_t)tl.size();
+    p->ntiles = (int64_t)total_tiles;
     int cus = 0;
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                                                    p->device);
 
-    // One launch per variant in use, the costliest first.  Each variant's
-    // tiles are list-scheduled longest-processing-time-first over its
-    // work-groups: each tile, largest first, to the least-loaded work-group
-    // (ties to the lowest number, so the largest G tiles go to work-groups
-    // 0..G-1).  All schedules share one tile table and one offsets table.
+    // One launch per variant in use, the costliest first, each with
+    // min(8, work-groups) queues.  All launches share one tile table, one
+    // offsets table and one counters table.
     double vcost[NUM_VARIANTS] = {0.0, 0.0, 0.0};
-    std::vector<size_t> by_variant[NUM_VARIANTS];
-    for (size_t k2 = 0; k2 < tl.size(); ++k2) {
-        const int v = live[tl[k2].problem].variant;
-        vcost[v] += cost[k2];
-        by_variant[v].push_back(k2);
+    uint64_t vtiles[NUM_VARIANTS] = {0, 0, 0};
+    for (size_t i = 0; i < live.size(); ++i) {
+        vcost[live[i].variant] += ntile[i] * tcost[i];
+        vtiles[live[i].variant] += ntile[i];
     }
     int vorder[NUM_VARIANTS] = {0, 1, 2};
     std::stable_sort(vorder, vorder + NUM_VARIANTS,
                      [&](int a2, int b2) { return vcost[a2] > vcost[b2]; });
     std::vector<TileRef> sched;
     std::vector<uint32_t> starts;
-    sched.reserve(tl.size());
+    int64_t ncounters = 0;
+    sched.reserve(total_tiles);
     for (int vi = 0; vi < NUM_VARIANTS && e == hipSuccess; ++vi) {
         const int v = vorder[vi];
-        std::vector<size_t>& idx = by_variant[v];
-        if (idx.empty()) continue;
+        if (vtiles[v] == 0) continue;
         const void* k = kernel_of(precision, v);
         const int lds = lds_of(precision, v);
         int per_cu = 0;
@@ -351,20 +414,24 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
         if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k, 256, lds);
         if (e != hipSuccess) break;
         const int64_t slots = (int64_t)(per_cu > 0 ? per_cu : 1) * (cus > 0 ? cus : 1);
-        const uint32_t G = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(slots, (int64_t)idx.size()));
-        std::stable_sort(idx.begin(), idx.end(),
-                         [&](size_t a2, size_t b2) { return cost[a2] > cost[b2]; });
-        std::vector<double> ordered(idx.size());
-        for (size_t q = 0; q < idx.size(); ++q) ordered[q] = cost[idx[q]];
-        const std::vector<uint32_t> owner = lpt_schedule(ordered, G);
-        std::vector<std::vector<TileRef>> per_wg(G);
-        for (size_t q = 0; q < idx.size(); ++q) per_wg[owner[q]].push_back(tl[idx[q]]);
-        p->launches.push_back(VariantLaunch{v, G, (int64_t)starts.size()});
-        for (uint32_t w = 0; w < G; ++w) {
+        const uint32_t G = (uint32_t)std::max<int64_t>(1, std::min<int64_t>(slots, (int64_t)vtiles[v]));
+        const uint32_t nq = std::min<uint32_t>(NUM_XCD, G);
+        std::vector<uint32_t> pid, nt;
+        std::vector<double> pc;
+        for (size_t i = 0; i < live.size(); ++i) {
+            if (live[i].variant != v || ntile[i] == 0) continue;
+            pid.push_back((uint32_t)i);
+            nt.push_back(ntile[i]);
+            pc.push_back(tcost[i]);
+        }
+        const auto queues = queue_partition(nt, pc, nq);
+        p->launches.push_back(VariantLaunch{v, G, nq, (int64_t)starts.size(), ncounters});
+        for (uint32_t q = 0; q < nq; ++q) {
             starts.push_back((uint32_t)sched.size());
-            sched.insert(sched.end(), per_wg[w].begin(), per_wg[w].end());
+            for (const auto& pt : queues[q]) sched.push_back(TileRef{pid[pt.first], pt.second});
         }
         starts.push_back((uint32_t)sched.size());
+        ncounters += (int64_t)(nq + 1) * CTR_STRIDE;
         p->grid = std::max(p->grid, G);
     }
     if (e != hipSuccess) {
@@ -372,6 +439,7 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
         return hip_err(e, "grouped plan set-up");
     }
     if (starts.empty()) starts.push_back(0);
+    const std::vector<uint32_t> zeros((size_t)std::max<int64_t>(1, ncounters), 0u);
 
     if (fault_injected()) e = hipErrorOutOfMemory;
     if (e == hipSuccess && !live.empty())
@@ -379,6 +447,7 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
     if (e == hipSuccess && !sched.empty())
         e = hipMalloc((void**)&p->d_tiles, sched.size() * sizeof(TileRef));
     if (e == hipSuccess) e = hipMalloc((void**)&p->d_starts, starts.size() * sizeof(uint32_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_counters, zeros.size() * sizeof(uint32_t));
     if (e != hipSuccess) {
         plan_free(p);
         (void)hipGetLastError();
@@ -393,6 +462,12 @@ static int build_plan(const mgemm_problem* probs, int64_t count, int precision,
     if (e == hipSuccess)
         e = hipMemcpy(p->d_starts, starts.data(), starts.size() * sizeof(uint32_t),
                       hipMemcpyHostToDevice);
+    // The counters start at zero (an upload, not a memset: the plan's
+    // launches may run on streams that do not wait for the null stream).
+    if (e == hipSuccess)
+        e = hipMemcpy(p->d_counters, zeros.data(), zeros.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     if (e != hipSuccess) {
         plan_free(p);
         return hip_err(e, "grouped plan upload");

@@ -5,6 +5,7 @@
 #pragma once
 #include <stdint.h>
 
+#include <utility>
 #include <vector>
 
 namespace mgemm {
@@ -46,5 +47,13 @@ int f16s_default_config(int64_t M, int64_t N, int64_t K);
 // with the least assigned cost so far, ties to the lowest number.  Returns
 // the work-group of every item; G >= 1.
 std::vector<uint32_t> lpt_schedule(const std::vector<double>& cost_in_order, uint32_t G);
+
+// The work queues of one grouped launch: problem i has ntiles[i] tiles of
+// cost tile_cost[i] each.  Problems (cut into contiguous runs of tiles when
+// one costs more than a queue's share) go to the nq queues by the list
+// schedule above; each queue holds its (problem, tile) pairs costliest
+// first.  Every tile appears in exactly one queue.
+std::vector<std::vector<std::pair<uint32_t, uint32_t>>> queue_partition(
+    const std::vector<uint32_t>& ntiles, const std::vector<double>& tile_cost, uint32_t nq);
 
 }  // namespace mgemm

@@ -12,7 +12,7 @@ __global__ __launch_bounds__(Cfg::NT, Cfg::WPE) void sgemm_f32_kernel(GemmDesc d
     __shared__ __attribute__((aligned(16))) float smem[Cfg::SMEM_FLOATS];
     uint32_t tm, tn;
     grouped_tile<8>(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
-    tile_f32<Cfg, AK, BKC, BUF>(d, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
+    tile_f32<Cfg, AK, BKC, BUF>(d, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem, threadIdx.x);
 }
 
 template <class Cfg, bool BUF>
@@ -83,7 +83,7 @@ __global__ __launch_bounds__(Cfg::NT, Cfg::WPE) void sgemm_f32_tail_kernel(GemmD
     const int64_t m0 = (int64_t)tm * BigCfg::BM + (int64_t)(q % R) * Cfg::BM;
     const int64_t n0 = (int64_t)tn * BigCfg::BN + (int64_t)(q / R) * Cfg::BN;
     if (m0 >= d.M || n0 >= d.N) return;   // a quarter past the edge of C
-    tile_f32<Cfg, AK, BKC, true>(d, m0, n0, smem);
+    tile_f32<Cfg, AK, BKC, true>(d, m0, n0, smem, threadIdx.x);
 }
 
 hipError_t launch_f32_tail(bool ta, bool tb, const GemmDesc& d, int cus, hipStream_t s) {
@@ -157,7 +157,7 @@ __global__ __launch_bounds__(Cfg::NT, Cfg::WPE) void sgemm_f32_splitk_kernel(
     p.alpha = 1.0f;
     p.beta = 0.0f;
     p.act = ACT_NONE;   // applied once, by the reduction
-    tile_f32<Cfg, AK, BKC, true>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem);
+    tile_f32<Cfg, AK, BKC, true>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, smem, threadIdx.x);
 }
 
 // C <- act(alpha * sum_s ws[s] + beta * C), s in increasing order; beta ==

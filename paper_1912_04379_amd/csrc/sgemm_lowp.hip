@@ -12,7 +12,7 @@ __global__ __launch_bounds__(Cfg::NT) void sgemm_lowp_kernel(GemmDesc d, uint32_
     extern __shared__ __attribute__((aligned(16))) char lowp_smem[];
     uint32_t tm, tn;
     grouped_tile<8>(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
-    tile_lowp<Cfg, F, AK, BKC, BUF>(d, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, lowp_smem);
+    tile_lowp<Cfg, F, AK, BKC, BUF>(d, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, lowp_smem, threadIdx.x);
 }
 
 template <class Cfg, Form F>
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(Cfg::NT) void sgemm_lowp_splitk_kernel(GemmDesc d, 
     p.alpha = 1.0f;
     p.beta = 0.0f;
     p.act = ACT_NONE;   // applied once, by the reduction
-    tile_lowp<Cfg, F, AK, BKC, true>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, lowp_smem);
+    tile_lowp<Cfg, F, AK, BKC, true>(p, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN, lowp_smem, threadIdx.x);
 }
 
 template <class Cfg, Form F>

@@ -109,7 +109,7 @@ enum class Step { STAGE_LOAD_FULL, STAGE_LOAD_PART, STAGE, LAST };
 // partial slab, no load, last slab) so that no step joins two load
 // sequences: a join makes the compiler wait for every load in flight.
 template <class Cfg, bool AK, bool BKC, bool BUF>
-__device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float* smem) {
+__device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float* smem, int tid) {
     constexpr int BM = Cfg::BM, BK = Cfg::BK, NT = Cfg::NT, S = Cfg::S;
     constexpr int FM = Cfg::FM, FN = Cfg::FN, NC = BK / 8;
     static_assert(NC >= 2, "the pipeline needs two k-chunks per slab");
@@ -118,7 +118,7 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
     using LB = typename std::conditional<BUF, SlabLoaderB<Cfg::BN, BK, NT, BKC>,
                                          SlabLoaderG<Cfg::BN, BK, NT, BKC>>::type;
     using Epi = typename std::conditional<BUF, EpilogueB, EpilogueG>::type;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, h = lane >> 5;
     const int wm = (wave % Cfg::WGM) * Cfg::WM;
     const int wn = (wave / Cfg::WGM) * Cfg::WN;

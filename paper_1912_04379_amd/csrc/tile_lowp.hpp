@@ -100,12 +100,12 @@ __device__ inline void stage_lowp(const Loader& ld, char* hi, char* lo,
 }
 
 template <class Cfg, Form F, bool AK, bool BKC, bool BUF>
-__device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char* smem) {
+__device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char* smem, int tid) {
     constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, NT = Cfg::NT;
     constexpr int FM = Cfg::FM, FN = Cfg::FN;
     constexpr int ARR = (BM + BN) * Cfg::ROW_BYTES;                 // one array, one stage
     constexpr int STAGE = (F == Form::BF16X3 ? 2 : 1) * ARR;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
     const int l32 = lane & 31, h = lane >> 5;
     const int wm = (wave % Cfg::WGM) * Cfg::WM;
     const int wn = (wave / Cfg::WGM) * Cfg::WN;

@@ -73,6 +73,20 @@ int main() {
             const std::vector<uint32_t> owner = lpt_schedule(cost, G);
             for (size_t i = 0; i < owner.size(); ++i) std::printf(i ? " %u" : "%u", owner[i]);
             std::printf("\n");
+        } else if (op == 'Q') {
+            unsigned nq;
+            size_t n;
+            in >> nq >> n;
+            std::vector<uint32_t> ntiles(n);
+            std::vector<double> cost(n);
+            for (uint32_t& t : ntiles) in >> t;
+            for (double& c : cost) in >> c;
+            const auto queues = queue_partition(ntiles, cost, nq);
+            for (size_t q = 0; q < queues.size(); ++q) {
+                std::printf(q ? " ; %zu" : "%zu", queues[q].size());
+                for (const auto& pt : queues[q]) std::printf(" %u %u", pt.first, pt.second);
+            }
+            std::printf("\n");
         } else if (op == 'B') {
             size_t nc, na;
             in >> nc >> na;

@@ -168,6 +168,63 @@ def test_graph_replay_equals_direct_launch_bitwise(precision):
 
 
 @pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_back_to_back_launches_find_the_queues_reset(precision):
+    """Work-groups take tiles from counters that the last work-group of a
+    launch puts back to zero.  Launches queued back to back on one stream
+    (graph replays and direct runs, C restored between them on the same
+    stream, no host synchronisation) must each compute every tile: a tile
+    left out would keep C's initial value."""
+    import torch
+    problems, data, arena, host = make_batch(count=64, seed=9)
+    init = torch.from_numpy(host).cuda()
+    with mg.GroupedPlan(problems, precision) as plan:
+        plan.run()
+        torch.cuda.synchronize()
+        direct = arena.clone()
+        outs = []
+        for r in range(12):
+            arena.copy_(init)
+            plan.launch() if r % 3 else plan.run()
+            outs.append(arena.clone())
+        torch.cuda.synchronize()
+    for r, o in enumerate(outs):
+        assert torch.equal(o, direct), "launch %d differs" % r
+    check_batch(problems, data, direct.cpu().numpy(), precision, 1e-5)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("shapes", [[(20, 30, 40)], [(64, 64, 16)], [(130, 70, 50), (5, 5, 5)]])
+def test_batches_with_fewer_tiles_than_queues(shapes):
+    """One queue per XCD, but never more queues than work-groups: one tile,
+    or a handful, still runs to completion."""
+    import torch
+    rng = np.random.default_rng(21)
+    probs, keep, hosts = [], [], []
+    for (M, N, K) in shapes:
+        A, B, C = (synth.matrix(rng, r, c, r) for r, c in ((M, K), (K, N), (M, N)))
+        t = [torch.from_numpy(x.copy()).cuda() for x in (A, B, C)]
+        keep.append(t)
+        hosts.append((A, B, C))
+        probs.append(dict(transA="N", transB="N", M=M, N=N, K=K, alpha=1.25, beta=-0.5, A=t[0],
+                          lda=M, B=t[1], ldb=K, C=t[2], ldc=M))
+    for precision in ("fp32", "bf16x3"):
+        for t, (A, B, C) in zip(keep, hosts):
+            t[2].copy_(torch.from_numpy(C))
+        with mg.GroupedPlan(probs, precision) as plan:
+            for _ in range(3):
+                for t, (A, B, C) in zip(keep, hosts):
+                    t[2].copy_(torch.from_numpy(C))
+                plan.launch()
+            torch.cuda.synchronize()
+        for p, (A, B, C), t in zip(probs, hosts, keep):
+            ref = oracle.sgemm("N", "N", p["M"], p["N"], p["K"], p["alpha"], A, p["lda"], B,
+                               p["ldb"], p["beta"], C, p["ldc"])
+            got = t[2].cpu().numpy().reshape(p["N"], p["ldc"])[:, :p["M"]].T.astype(np.float64)
+            assert oracle.normwise_rel_err(got, ref) <= 1e-5, (precision, p["M"], p["N"], p["K"])
+
+
+@pytest.mark.gpu
 def test_grouped_equals_single_calls_with_same_tile():
     """Variant 1 (128x128x16) is the single-call configuration 0: the same
     tile code, so the results are bitwise equal."""

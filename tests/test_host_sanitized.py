@@ -226,6 +226,46 @@ def test_list_schedule_is_longest_first_to_least_loaded(bins):
             assert max(load) <= cost.sum() / G + cost.max() + 1e-9
 
 
+def test_queue_partition_covers_every_tile_once(bins):
+    """The grouped plan's work queues: every tile of every problem in exactly
+    one queue, each queue costliest first, the queues balanced within one
+    chunk, and a problem costing more than a queue's share spread over
+    several queues."""
+    rng = np.random.default_rng(5)
+    cases = []
+    for _ in range(150):
+        n = int(rng.integers(0, 60))
+        nq = int(rng.integers(1, 9))
+        nt = rng.integers(0, 70, n)
+        cost = rng.integers(1, 40, n).astype(float) * 16.0
+        cases.append((nq, nt, cost))
+    cases.append((8, np.array([1000]), np.array([5.0])))          # one large problem
+    cases.append((8, np.array([3, 1]), np.array([7.0, 100.0])))   # fewer chunks than queues
+    lines = ["Q %d %d %s %s" % (nq, len(nt), " ".join(str(int(x)) for x in nt),
+                                " ".join("%.17g" % x for x in cost)) for nq, nt, cost in cases]
+    out = _host(bins, lines)
+    for (nq, nt, cost), line in zip(cases, out):
+        queues = []
+        for part in line.split(";"):
+            f = [int(x) for x in part.split()]
+            assert f[0] * 2 == len(f) - 1
+            queues.append(list(zip(f[1::2], f[2::2])))
+        assert len(queues) == nq
+        seen = sorted(pt for q in queues for pt in q)
+        assert seen == sorted((p, t) for p in range(len(nt)) for t in range(int(nt[p])))
+        total = float(sum(nt[p] * cost[p] for p in range(len(nt))))
+        loads = []
+        for q in queues:
+            c = [cost[p] for p, _ in q]
+            assert all(c[i] >= c[i + 1] for i in range(len(c) - 1))
+            loads.append(sum(c))
+        if total > 0:
+            # a chunk costs at most a queue's share plus one tile
+            assert max(loads) <= 2 * total / nq + cost.max() + 1e-9
+    line = out[-2]
+    assert all(int(part.split()[0]) == 125 for part in line.split(";"))
+
+
 def test_batch_aliasing_against_brute_force(bins):
     rng = np.random.default_rng(4)
     cases, lines = [], []
