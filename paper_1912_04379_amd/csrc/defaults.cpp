@@ -81,11 +81,15 @@ int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
     // (TFLOP/s, large square products): 256x256 with 32-deep slabs (only
     // for K >= 4096: its longer prologue and epilogue cost more on shorter
     // products), 256x128 at 2 waves per SIMD (128x256 for TT, whose operand
-    // layouts favour it), 128x128, 64x64.  Each is scored by the slot-share
-    // model, less 10% while it has fewer tiles than it needs resident per CU
-    // to hide its load latency.  Against measured sweeps (1024^3 to 8192^3,
-    // odd and rectangular shapes, all four transposes) the pick is the
-    // fastest configuration or within 6% of it.
+    // layouts favour it), 128x128, and 64x64 with 32-deep slabs.  Each is
+    // scored by the slot-share model, less 10% while it has fewer tiles than
+    // it needs resident per CU to hide its load latency.  Against measured
+    // sweeps (512^3 to 8192^3, odd and rectangular shapes, all four
+    // transposes) the pick is the fastest configuration or within 6% of it.
+    // The 64x64x32 tile replaced 64x64x16 (rate 125, 6 resident) here: 3-11%
+    // faster at every size from 512^3 to 8192^3, it also wins at 2048^3
+    // (127 against 123 for 128x128) and 5120^3 (133 against 127 for the
+    // rounds with a 128x128 tail).
     struct Cand {
         int cfg, bm, bn;
         double rate;
@@ -95,9 +99,9 @@ int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
         Cand{8, 256, 256, 148.5, 1, 4096},
         ta && tb ? Cand{6, 128, 256, 147.0, 2, 0} : Cand{5, 256, 128, 147.0, 2, 0},
         Cand{0, 128, 128, 142.0, 3, 0},
-        Cand{1, 64, 64, 125.0, 6, 0},
+        Cand{F32_DEEP64_CONFIG, 64, 64, 131.0, 4, 0},
     };
-    int best = 1;
+    int best = F32_DEEP64_CONFIG;
     double best_score = -1.0;
     for (const Cand& c : cands) {
         if (K < c.min_k) continue;

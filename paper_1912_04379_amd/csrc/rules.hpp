@@ -18,6 +18,10 @@ constexpr int F32_TAIL_CONFIG = 10;
 // written to workspace + s*M*N (column-major, ld M), and a second kernel
 // adds the S partial products in order s = 0..S-1 and applies alpha, beta.
 constexpr int F32_SPLITK_CONFIG = 11;
+// FP32 configuration 12: 64 x 64 tiles with 32-deep slabs (4 waves of
+// 32 x 32), the default for products of about one to a few 64 x 64 tiles
+// per CU.
+constexpr int F32_DEEP64_CONFIG = 12;
 struct SplitKPlan {
     int small_tile;   // 0: 128 x 128 x 16 tiles, 1: 64 x 64 x 16
     int splits;       // S >= 2, or 0 when splitting does not apply

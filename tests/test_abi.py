@@ -85,7 +85,7 @@ def test_lowercase_and_conjugate_flags():
 def test_unsupported_precision_and_config():
     assert call(precision=7) == _lib.ERR_UNSUPPORTED
     assert call(config=99) == _lib.ERR_UNSUPPORTED
-    assert mg.config_count("fp32") == 12
+    assert mg.config_count("fp32") == 13
     # test_precision enumerates the 16-bit configurations by this count
     assert mg.config_count("bf16x3") == 14 and mg.config_count("fp16s") == 14
     for prec in ("fp32", "bf16x3", "fp16s"):

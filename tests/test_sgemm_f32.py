@@ -48,7 +48,7 @@ def test_ragged_shapes(ta, tb, shape):
     full_check(c, run(c))
 
 
-@pytest.mark.parametrize("cfg", range(12))
+@pytest.mark.parametrize("cfg", range(13))
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_every_config(cfg, ta, tb):
     c = synth.sgemm_case(3, ta, tb, 300, 270, 77, alpha=1.5, beta=-0.5, pad=3)
@@ -56,7 +56,7 @@ def test_every_config(cfg, ta, tb):
     full_check(c, run(c, config=cfg))
 
 
-@pytest.mark.parametrize("cfg", range(12))
+@pytest.mark.parametrize("cfg", range(13))
 @pytest.mark.parametrize("ta,tb", TRANS)
 def test_every_config_sizes_multiple_of_4(cfg, ta, tb):
     """M and N multiples of 4 but of no tile edge, odd leading dimensions
@@ -67,7 +67,7 @@ def test_every_config_sizes_multiple_of_4(cfg, ta, tb):
     full_check(c, run(c, config=cfg))
 
 
-@pytest.mark.parametrize("cfg", range(12))
+@pytest.mark.parametrize("cfg", range(13))
 @pytest.mark.parametrize("K", [1, 17, 33])
 @pytest.mark.parametrize("ta,tb", [("N", "N"), ("T", "T")])
 def test_short_k_every_config(cfg, K, ta, tb):
