@@ -23,7 +23,7 @@ constexpr int F32_SPLITK_CONFIG = 11;
 // per CU.
 constexpr int F32_DEEP64_CONFIG = 12;
 struct SplitKPlan {
-    int small_tile;   // 0: 128 x 128 x 16 tiles, 1: 64 x 64 x 16
+    int small_tile;   // 0: 128 x 128 x 16 tiles, 1: 64 x 64 x 32
     int splits;       // S >= 2, or 0 when splitting does not apply
     int64_t kc;       // k per piece, a multiple of 32
 };
