@@ -676,13 +676,13 @@ def bench_mlp(args, mg, torch):
 def bench_splitk(args, mg, torch):
     """Products with few tiles and a long k range (NN, ld = rows + 16, alpha
     1.5, beta -0.5, uniform inputs): the library's choice (split-K) against
-    the same product unsplit on 64 x 64 tiles (configuration 1) and, at
-    256^2, the small-product kernel (configuration 9); the same for the two
-    16-bit forms."""
+    the same product unsplit on 64 x 64 x 32 tiles (configuration 12, the
+    rule's pick without split-K) and, at 256^2, the small-product kernel
+    (configuration 9); the same for the two 16-bit forms."""
     import synth
     stream = torch.cuda.current_stream()
     out = {}
-    for (M, N, K), other in (((1024, 1024, 8192), 1), ((512, 512, 16384), 1),
+    for (M, N, K), other in (((1024, 1024, 8192), 12), ((512, 512, 16384), 12),
                              ((256, 256, 65536), 9)):
         c = synth.sgemm_case(0, "N", "N", M, N, K, alpha=1.5, beta=-0.5)
         A, B, C = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
