@@ -99,7 +99,10 @@ int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  * per CU and K of about 2048 and up, takes S*M*N*4 bytes from the same
  * pool (at most 1 GiB; larger products, and leading dimensions beyond the
  * 32-bit buffer path, run configuration 0 instead).  The other FP32
- * configurations take no workspace.  The last configuration of either
+ * configurations take no workspace; mgemm_config_info describes each
+ * (configuration 12, 64 x 64 tiles with 32-deep slabs, is the library's
+ * choice for products of one to a few such tiles per CU).  The last
+ * configuration of either
  * 16-bit form (13) is split-K in the same way: the pieces are in-staging
  * tiles (128 x 128, or 64 x 64 for few tiles), their S*M*N*4 bytes of
  * partial products come from the pool too (the FP16 unscale is applied per
