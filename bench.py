@@ -790,7 +790,8 @@ def bench_forms_2048(args, mg, torch, oracle, synth):
 def bench_prepacked(args, mg, torch, n):
     """BF16x3 at n^3 NN with op(B) packed once (mgemm_pack_b) against the
     ordinary call, which packs both operands every time; same inputs as the
-    headline product (alpha 1.5, beta -0.5)."""
+    headline product (alpha 1.5, beta -0.5).  Then scaled FP16 the same way,
+    and FP32 TT with op(B) transposed once."""
     import synth
     c = synth.sgemm_case(0, "N", "N", n, n, n, alpha=1.5, beta=-0.5)
     A, B, C = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
@@ -826,6 +827,18 @@ def bench_prepacked(args, mg, torch, n):
                     "packed_b_tflops": round(flops / ms_f16p / 1e9, 3),
                     "speedup": round(ms_f16 / ms_f16p, 3)}
     log("pre-packed B fp16s %d^3: %.3f ms per call against %.3f" % (n, ms_f16p, ms_f16))
+    # FP32: op(B) stored transposed ('T', the same buffer read as N x K),
+    # transposed once into the k-contiguous layout; A 'T' too, so the
+    # ordinary call is the TT product and the packed one runs as TN.
+    ms_tt = timed(lambda: mg.sgemm("T", "T", n, n, n, 1.5, A, ld, B, ld, -0.5, C, ld),
+                  args.steps, args.warmup, stream, min_ms=50)
+    with mg.PackedB("T", n, n, B, ld, precision="fp32") as p32:
+        ms_ttp = timed(lambda: p32.sgemm("T", n, 1.5, A, ld, -0.5, C, ld), args.steps,
+                       args.warmup, stream, min_ms=50)
+    out["fp32_tt"] = {"ordinary_ms": round(ms_tt, 4), "packed_b_ms": round(ms_ttp, 4),
+                      "packed_b_tflops": round(flops / ms_ttp / 1e9, 3),
+                      "speedup": round(ms_tt / ms_ttp, 3)}
+    log("pre-packed B fp32 TT %d^3: %.3f ms per call against %.3f" % (n, ms_ttp, ms_tt))
     del A, B, C
     return out
 

@@ -373,11 +373,16 @@ int mgemm_grouped_tune(const mgemm_problem *problems, int64_t count,
  * Built for MGEMM_PREC_BF16X3 (the hi and lo bf16 halves of every
  * element, 4 bytes per element of op(B), K rounded up to 16 and N to 32)
  * and MGEMM_PREC_FP16_SCALED (2 bytes per element, scaled by the panel
- * exponents of op(B), which the handle keeps); MGEMM_PREC_FP32 returns
- * MGEMM_ERR_UNSUPPORTED.  Products run on the pipelined packed 256 x 256
- * tile when there are at least 144 such tiles, else on the pipelined
- * 128 x 128 tile (16-bit configurations 10 and 11): their results equal
- * mgemm_sgemm_ex with the same precision and configuration bitwise.
+ * exponents of op(B), which the handle keeps).  Their products run on the
+ * pipelined packed 256 x 256 tile when there are at least 144 such tiles,
+ * else on the pipelined 128 x 128 tile (16-bit configurations 10 and 11):
+ * their results equal mgemm_sgemm_ex with the same precision and
+ * configuration bitwise.  MGEMM_PREC_FP32 keeps op(B) transposed once into
+ * the layout the FP32 kernels load with 16-byte loads (a column-major K x N
+ * array, k contiguous, leading dimension K rounded up to 4; 4 bytes per
+ * element); its products are the ordinary FP32 call with that array as a
+ * 'N' operand (library's choice of configuration for op(A) and 'N'), and
+ * equal that call bitwise.
  *
  * Argument errors are reported with the SGEMM number of the same argument
  * (transB -2, N -4, K -5, B -9, ldb -10; transA -1, M -3, A -7, lda -8,

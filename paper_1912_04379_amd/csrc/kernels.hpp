@@ -75,6 +75,12 @@ hipError_t launch_packed(bool bf16x3, int cfg, bool transA, bool transB, const G
 // contiguous along k), the block depth of a packed configuration (0 for an
 // unknown one), and the main kernel with op(B) already packed.
 int64_t packed_operand_bytes(bool bf16x3, int kw, int64_t P, int64_t K);
+// FP32 pre-packed B: op(B) (K x N; B stored K x N for !tb, N x K for tb,
+// leading dimension ldb) into a column-major K x N array at `out` with
+// leading dimension ldp >= K (k contiguous, the FP32 kernels' 16-byte-load
+// layout).  Rows k >= K of `out` are not written.
+hipError_t launch_f32_pack_b(bool tb, const float* B, int64_t ldb, int64_t K, int64_t N,
+                             float* out, int64_t ldp, hipStream_t s);
 hipError_t launch_pack_operand(bool bf16x3, int kw, bool kcontig, const float* X, int64_t ld,
                                int64_t P, int64_t K, char* hi, char* lo, const int* expo,
                                hipStream_t stream);

@@ -5,6 +5,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <cstdint>
 #include <cstdio>
@@ -454,9 +455,10 @@ struct mgemm_packed_b {
     int device;
     int64_t K, N;
     char* hi;     // the allocation: packed values, then (FP16) exponents
-    char* lo;     // BF16x3 lo halves (NULL for FP16)
-    int* expB;    // FP16: panel exponents of op(B) (NULL for BF16x3)
+    char* lo;     // BF16x3 lo halves (NULL for FP16 and FP32)
+    int* expB;    // FP16: panel exponents of op(B) (NULL otherwise)
     int64_t bytes;
+    int64_t ld;   // FP32: leading dimension of the k-contiguous K x N array
 };
 
 namespace mgemm {
@@ -485,6 +487,45 @@ static bool packed_b_live(const mgemm_packed_b* p) {
 
 }  // namespace mgemm
 
+namespace mgemm {
+
+// FP32 pre-packed B: op(B) as a column-major K x N array, k contiguous, with
+// its leading dimension rounded up to a multiple of 4 floats.
+static int pack_b_f32(int tb, int64_t K, int64_t N, const float* B, int64_t ldb, void* stream,
+                      mgemm_packed_b** out) {
+    int dev = 0;
+    const int st = check_device(&dev);
+    if (st) return st;
+    const int64_t ld = (std::max<int64_t>(K, 1) + 3) / 4 * 4;
+    const int64_t bytes = K > 0 && N > 0 ? ld * N * (int64_t)sizeof(float) : 0;
+    mgemm_packed_b* h =
+        new mgemm_packed_b{MGEMM_PREC_FP32, dev, K, N, nullptr, nullptr, nullptr, bytes, ld};
+    if (bytes > 0) {
+        hipError_t e = fault_injected() ? hipErrorOutOfMemory
+                                        : hipMalloc((void**)&h->hi, (size_t)bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            delete h;
+            return fail(MGEMM_ERR_ALLOC, "packed B buffer");
+        }
+        e = launch_f32_pack_b(tb != 0, B, ldb, K, N, reinterpret_cast<float*>(h->hi), ld,
+                              (hipStream_t)stream);
+        if (e != hipSuccess) {
+            (void)hipFree(h->hi);
+            delete h;
+            return hip_fail(e, "pack kernel launch");
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_packed_mu);
+        g_packed.insert(h);
+    }
+    *out = h;
+    return MGEMM_OK;
+}
+
+}  // namespace mgemm
+
 extern "C" {
 
 int mgemm_pack_b(char transB, int64_t K, int64_t N, const float* B, int64_t ldb, int precision,
@@ -498,8 +539,9 @@ int mgemm_pack_b(char transB, int64_t K, int64_t N, const float* B, int64_t ldb,
     if (K > 0 && N > 0 && B == nullptr) return fail(-9, "B is NULL");
     const int64_t rows_b = tb ? N : K;
     if (ldb < (rows_b > 1 ? rows_b : 1)) return fail(-10, "ldb < max(1, stored rows of B)");
+    if (precision == MGEMM_PREC_FP32) return pack_b_f32(tb, K, N, B, ldb, stream, out);
     if (precision != MGEMM_PREC_BF16X3 && precision != MGEMM_PREC_FP16_SCALED)
-        return fail(MGEMM_ERR_UNSUPPORTED, "pre-packed B is built for the BF16x3 and FP16 forms");
+        return fail(MGEMM_ERR_UNSUPPORTED, "unknown precision");
     const bool bf = precision == MGEMM_PREC_BF16X3;
     if (!packed_supported(bf, PACKED_B_BIG, 1, N, K) ||
         !packed_supported(bf, PACKED_B_SMALL, 1, N, K))
@@ -510,7 +552,7 @@ int mgemm_pack_b(char transB, int64_t K, int64_t N, const float* B, int64_t ldb,
     const int64_t pack_bytes = packed_operand_bytes(bf, PACKED_B_KW, N, K);
     const int64_t bytes = round256(pack_bytes) + (bf ? 0 : f16_exp_bytes(N, K));
     mgemm_packed_b* h =
-        new mgemm_packed_b{precision, dev, K, N, nullptr, nullptr, nullptr, bytes};
+        new mgemm_packed_b{precision, dev, K, N, nullptr, nullptr, nullptr, bytes, 0};
     if (N > 0 && bytes > 0) {
         hipError_t e = fault_injected() ? hipErrorOutOfMemory
                                         : hipMalloc((void**)&h->hi, (size_t)bytes);
@@ -586,6 +628,12 @@ int mgemm_sgemm_packed_b(char transA, int64_t M, float alpha, const float* A, in
     if (no_product) {
         e = launch_scale_c(d, s);
         return e == hipSuccess ? MGEMM_OK : hip_fail(e, "scale kernel launch");
+    }
+    if (Bp->precision == MGEMM_PREC_FP32) {
+        // An ordinary FP32 product with op(B) as the packed 'N' operand.
+        return sgemm_impl(transA, 'N', M, N, K, alpha, A, lda,
+                          reinterpret_cast<const float*>(Bp->hi), Bp->ld, beta, C, ldc, stream,
+                          MGEMM_PREC_FP32, -1, nullptr);
     }
     const bool bf = Bp->precision == MGEMM_PREC_BF16X3;
     const int64_t t256 = ((M + 255) / 256) * ((N + 255) / 256);

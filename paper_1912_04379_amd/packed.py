@@ -1,7 +1,8 @@
 """Pre-packed op(B): packed once by the library, reused by many products.
 
 Argument marshalling only: the packing and the products run in libmgemm
-(``mgemm_pack_b``, ``mgemm_sgemm_packed_b``; BF16x3 and scaled-FP16 forms).
+(``mgemm_pack_b``, ``mgemm_sgemm_packed_b``; BF16x3, scaled FP16, and FP32 with
+op(B) transposed once into the k-contiguous layout).
 """
 import ctypes
 

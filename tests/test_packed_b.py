@@ -2,7 +2,10 @@
 equal the ordinary call of the same form on the same packed configuration
 bitwise (the same packed values and exponents reach the same kernel), and
 the FP64 oracle within the form's bar (1e-5 BF16x3, 1e-3 FP16); one handle
-serves several products."""
+serves several products.  FP32: op(B) transposed once into a k-contiguous
+K x N array; products equal the ordinary call with op(B) given as a stored
+K x N 'N' operand bitwise, and the oracle within the FP32 elementwise
+bound."""
 import numpy as np
 import pytest
 
@@ -111,3 +114,65 @@ def test_wide_ldc(prec):
     ref_buf, got_buf = both(c, prec)
     assert np.array_equal(ref_buf, got_buf, equal_nan=True)
     full_check(c, got_buf, bound_fn=None, normwise=BAR[prec])
+
+
+# ---- FP32: op(B) transposed once ----------------------------------------------
+
+def _op_b_as_n(c):
+    """op(B) of the case as a stored K x N column-major array at ld K."""
+    K, N, ldb = c["K"], c["N"], c["ldb"]
+    if c["transB"] == "N":
+        nk = c["B"].reshape(N, ldb)[:, :K]          # [n][k]
+    else:
+        nk = c["B"].reshape(K, ldb)[:, :N].T        # stored N x K: [k][n] -> [n][k]
+    return np.ascontiguousarray(nk).reshape(-1).astype(np.float32)
+
+
+@pytest.mark.parametrize("ta,tb", TRANS)
+@pytest.mark.parametrize("shape", [(300, 270, 77), (513, 257, 1000), (33, 65, 7), (1, 1, 1),
+                                   (130, 70, 0), (1024, 768, 513)])
+def test_fp32_packed_b_equals_n_operand_call_and_oracle(ta, tb, shape):
+    import torch
+    from gpu_util import fp32_bound
+    M, N, K = shape
+    c = synth.sgemm_case(54, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=3)
+    log("packed B fp32 %s %s%s" % (shape, ta, tb))
+    A, B = to_dev(c["A"]), to_dev(c["B"])
+    C1, C2 = to_dev(c["C"]), to_dev(c["C"])
+    Bn = to_dev(_op_b_as_n(c)) if K > 0 else to_dev(np.zeros(1, np.float32))
+    mg.sgemm(ta, "N", M, N, K, 1.5, A, c["lda"], Bn, max(1, K), -0.5, C1, c["ldc"])
+    with mg.PackedB(tb, K, N, B, c["ldb"], precision="fp32") as pb:
+        info = pb.info()
+        assert info["precision"] == mg.PRECISIONS["fp32"]
+        assert info["bytes"] == (((max(K, 1) + 3) // 4) * 4 * N * 4 if K > 0 and N > 0 else 0)
+        pb.sgemm(ta, M, 1.5, A, c["lda"], -0.5, C2, c["ldc"])
+    torch.cuda.synchronize()
+    ref_buf, got_buf = C1.cpu().numpy(), C2.cpu().numpy()
+    assert np.array_equal(ref_buf, got_buf, equal_nan=True)
+    got = logical_c(got_buf, c)
+    ref = oracle.sgemm(*oracle_args(c))
+    assert np.all(np.abs(got - ref) <= fp32_bound(c) + 1e-30)
+
+
+def test_fp32_one_handle_many_products_and_streams():
+    """One FP32 packed B (stored 'T'), three products with different A on
+    the current stream and on a side stream that waits for the pack."""
+    import torch
+    K, N = 600, 333
+    cb = synth.sgemm_case(55, "N", "T", 8, N, K, pad=4)
+    B = to_dev(cb["B"])
+    side = torch.cuda.Stream()
+    with mg.PackedB("T", K, N, B, cb["ldb"], precision="fp32") as pb:
+        for i, (M, st) in enumerate(((400, None), (65, side), (1, None))):
+            ca = synth.sgemm_case(70 + i, "T", "T", M, N, K, alpha=0.5, beta=0.25, pad=2)
+            ca["B"], ca["ldb"] = cb["B"], cb["ldb"]
+            A, C1, C2 = to_dev(ca["A"]), to_dev(ca["C"]), to_dev(ca["C"])
+            mg.sgemm("T", "T", M, N, K, 0.5, A, ca["lda"], B, cb["ldb"], 0.25, C1, ca["ldc"])
+            if st is not None:
+                st.wait_stream(torch.cuda.current_stream())   # A and C2 are copied in
+            pb.sgemm("T", M, 0.5, A, ca["lda"], 0.25, C2, ca["ldc"], stream=st)
+            torch.cuda.synchronize()
+            ref = oracle.sgemm(*oracle_args(ca))
+            err = oracle.normwise_rel_err(logical_c(C2.cpu().numpy(), ca), ref)
+            assert err <= 1e-6, (M, err)
+
