@@ -324,7 +324,8 @@ def main():
         "fp32_normwise_err": f32["err"],
         "value_timing": "warm: K back-to-back launches between HIP events on the launch stream; "
                         "the cache-flushed median (L2 and MALL overwritten before each launch, "
-                        "the paper's method) is fp32_cold_ms and roofline.cold",
+                        "the paper's method) is fp32_cold_ms and roofline.cold; the 16-bit forms' "
+                        "speedups likewise (speedup_vs_fp32 warm, speedup_vs_fp32_cold flushed)",
         "fp32_cold_ms": f32["cold_ms"],
         "fp32_median_ms": None if f32["median_ms"] is None else round(f32["median_ms"], 4),
         "gpu_clock": f32["clock"],
@@ -349,6 +350,8 @@ def main():
         line["bf16x3"] = {"tflops": round(b["tflops"], 3), "ms": round(b["ms"], 4),
                           "cold_ms": b["cold_ms"],
                           "speedup_vs_fp32": round(f32["ms"] / b["ms"], 3),
+                          "speedup_vs_fp32_cold": (round(f32["cold_ms"] / b["cold_ms"], 3)
+                                                   if f32["cold_ms"] and b["cold_ms"] else None),
                           "normwise_err": b["err"],
                           "both_within_1e-5": bool(b["err"] <= 1e-5 and f32["err"] <= 1e-5),
                           "mfma_frac": round(3 * b["tflops"] / PEAK["bf16"], 4)}
@@ -357,6 +360,8 @@ def main():
         line["fp16s"] = {"tflops": round(h["tflops"], 3), "ms": round(h["ms"], 4),
                          "cold_ms": h["cold_ms"],
                          "speedup_vs_fp32": round(f32["ms"] / h["ms"], 3),
+                         "speedup_vs_fp32_cold": (round(f32["cold_ms"] / h["cold_ms"], 3)
+                                                  if f32["cold_ms"] and h["cold_ms"] else None),
                          "normwise_err": h["err"],
                          "mfma_frac": round(h["tflops"] / PEAK["fp16"], 4)}
 
