@@ -345,12 +345,15 @@ int mgemm_grouped_variant_info(int precision, int variant, int *bm, int *bn,
 
 /*
  * Autotuner: choose the variant of every size bucket present in the batch
- * by timing the whole grouped launch on `stream` (best of `reps` timed
- * runs after one warm-up, HIP events): the defaults and each assignment of
- * one variant to every bucket are timed, then, from the fastest, each
- * bucket in turn tries every variant (two passes).  A change is kept only
- * when it is more than 2% faster than the assignment it replaces, so near
- * ties keep the earlier choice.  Writes 4 entries to
+ * by timing the whole grouped launch on `stream` (HIP events; the best of
+ * `reps` rounds, each the mean of 8 back-to-back launches, after two
+ * warm-up launches): the defaults and each assignment of one variant to
+ * every bucket are timed, then, from the fastest, each bucket in turn
+ * tries every variant (two passes).  A change is kept only when it is more
+ * than 2% faster than the assignment it replaces, so near ties keep the
+ * earlier choice; a result other than the defaults must also beat them by
+ * 2% in a final head-to-head, the two timed alternately three times.
+ * Writes 4 entries to
  * bucket_configs and the best time in
  * milliseconds to *best_ms (may be NULL).  The problems are RUN: every C
  * is overwritten with unspecified values, so tune on scratch outputs or

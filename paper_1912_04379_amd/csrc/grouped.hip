@@ -675,21 +675,26 @@ int mgemm_grouped_tune(const mgemm_problem* problems, int64_t count, int precisi
         if (e0) (void)hipEventDestroy(e0);
         return hip_err(hipGetLastError(), "hipEventCreate");
     }
-    // Time the whole batch with the given bucket assignment (best of reps).
+    // Time the whole batch with the given bucket assignment: the best of
+    // `reps` rounds, each the mean of LAUNCHES back-to-back launches, after
+    // two warm-up launches (one launch of a few hundred microseconds is too
+    // short to time against the clock's drift).
+    constexpr int LAUNCHES = 8;
     auto time_of = [&](const int* cfg, float& ms) -> int {
         mgemm_plan* p = nullptr;
         int st = build_plan(problems, count, precision, cfg, &p, nullptr, nullptr);
         if (st) return st;
         hipError_t e = launch_plan_kernel(p, s);   // warm-up
+        if (e == hipSuccess) e = launch_plan_kernel(p, s);
         float best = 1e30f;
         for (int r = 0; r < reps && e == hipSuccess; ++r) {
             e = hipEventRecord(e0, s);
-            if (e == hipSuccess) e = launch_plan_kernel(p, s);
+            for (int l = 0; l < LAUNCHES && e == hipSuccess; ++l) e = launch_plan_kernel(p, s);
             if (e == hipSuccess) e = hipEventRecord(e1, s);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float t = 0.0f;
             if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-            if (e == hipSuccess && t < best) best = t;
+            if (e == hipSuccess && t / LAUNCHES < best) best = t / LAUNCHES;
         }
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         plan_free(p);
@@ -705,8 +710,11 @@ int mgemm_grouped_tune(const mgemm_problem* problems, int64_t count, int precisi
     // of two assignments within timing noise of each other, the earlier one
     // stays.
     constexpr float TUNE_MARGIN = 0.98f;
+    int defaults[NUM_BUCKETS];
+    for (int b = 0; b < NUM_BUCKETS; ++b) defaults[b] = bucket_configs[b];
     float cur = 0.0f;
-    int st = time_of(bucket_configs, cur);
+    int st = time_of(bucket_configs, cur);   // brings the clock up; timed again below
+    if (st == MGEMM_OK) st = time_of(bucket_configs, cur);
     for (int v = 0; v < NUM_VARIANTS && st == MGEMM_OK; ++v) {
         int uni[NUM_BUCKETS];
         for (int b = 0; b < NUM_BUCKETS; ++b) uni[b] = v;
@@ -733,6 +741,29 @@ int mgemm_grouped_tune(const mgemm_problem* problems, int64_t count, int precisi
                 }
             }
             bucket_configs[b] = best_v;
+        }
+    }
+    // The descent compares assignments timed at different moments.  The
+    // winner replaces the defaults only if it also wins a head-to-head
+    // against them, timed alternately, by the same margin.
+    bool moved = false;
+    for (int b = 0; b < NUM_BUCKETS; ++b) moved |= bucket_configs[b] != defaults[b];
+    if (moved && st == MGEMM_OK) {
+        float td = 1e30f, tc = 1e30f;
+        for (int r = 0; r < 3 && st == MGEMM_OK; ++r) {
+            float t = 0.0f;
+            st = time_of(defaults, t);
+            if (st == MGEMM_OK) td = std::min(td, t);
+            if (st == MGEMM_OK) st = time_of(bucket_configs, t);
+            if (st == MGEMM_OK) tc = std::min(tc, t);
+        }
+        if (st == MGEMM_OK) {
+            if (tc < td * TUNE_MARGIN) {
+                cur = tc;
+            } else {
+                for (int b = 0; b < NUM_BUCKETS; ++b) bucket_configs[b] = defaults[b];
+                cur = td;
+            }
         }
     }
     (void)hipEventDestroy(e0);
