@@ -207,9 +207,13 @@ int mgemm_default_config(int precision, char transA, char transB,
 
 /*
  * Autotuner for single calls: runs the product once per configuration as a
- * warm-up and `reps` times timed (HIP events on `stream`), keeps the fastest
- * (best time over reps) and records it as the choice for this exact
- * (precision, trans pair, M, N, K), so later calls with config = -1 use it.
+ * warm-up and then `reps` timed rounds (HIP events on `stream`; a round is
+ * one call, or as many back-to-back calls as fill about a millisecond, at
+ * most 64), keeps the fastest (best round) and records it as the choice for
+ * this exact (precision, trans pair, M, N, K), so later calls with
+ * config = -1 use it.  A choice other than the built-in rule's is kept only
+ * if it also beats that rule's choice by more than 2% in a head-to-head,
+ * the two timed alternately three times.
  * Arguments as for mgemm_sgemm_ex; C is overwritten (with beta != 0 it is
  * updated once per run), so tune on scratch output.  Synchronises `stream`.
  * *best_config and *best_ms (either may be NULL) receive the result.

@@ -3,6 +3,7 @@
 // that fills it by timing every configuration on the caller's buffers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <functional>
 #include <map>
 #include <mutex>
@@ -11,6 +12,7 @@
 
 #include "host_common.hpp"
 #include "mgemm.h"
+#include "rules.hpp"
 
 namespace mgemm {
 
@@ -43,6 +45,20 @@ void for_each_choice(
 }  // namespace mgemm
 
 using namespace mgemm;
+
+namespace mgemm {
+
+// The built-in rule's choice (no recorded measurement).
+static int builtin_default_config(int precision, int ta, int tb, int64_t M, int64_t N, int64_t K) {
+    switch (precision) {
+        case MGEMM_PREC_FP32: return f32_default_config(ta != 0, tb != 0, M, N, K);
+        case MGEMM_PREC_BF16X3: return bf16x3_default_config(M, N, K);
+        case MGEMM_PREC_FP16_SCALED: return f16s_default_config(M, N, K);
+        default: return -1;
+    }
+}
+
+}  // namespace mgemm
 
 extern "C" {
 
@@ -82,32 +98,73 @@ int mgemm_tune_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, 
         (void)hipGetLastError();
         return fail(MGEMM_ERR_HIP, "hipEventCreate");
     }
+    // One timed round: `calls` back-to-back calls between two events, the
+    // mean per call.
+    auto round_of = [&](int cfg, int calls, float& ms) -> int {
+        hipError_t e = hipEventRecord(e0, s);
+        int r = MGEMM_OK;
+        for (int c = 0; c < calls && e == hipSuccess && r == MGEMM_OK; ++c)
+            r = mgemm_sgemm_ex(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
+                               stream, precision, cfg);
+        if (r) return r;
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float t = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(MGEMM_ERR_HIP, std::string("tuning timer: ") + hipGetErrorString(e));
+        }
+        ms = t / calls;
+        return MGEMM_OK;
+    };
+    // Best of `reps` rounds after a warm-up call; short products take as
+    // many calls per round as fill about a millisecond (at most 64), so
+    // that a round is long against the timer and the clock's drift.
+    auto time_of = [&](int cfg, float& best_ms_out) -> int {
+        float first = 0.0f;
+        int r = round_of(cfg, 1, first);   // warm-up, and a first estimate
+        const int calls = first > 0.0f ? std::max(1, std::min(64, (int)(1.0f / first))) : 64;
+        float t_min = 1e30f;
+        for (int k = 0; k < reps && r == MGEMM_OK; ++k) {
+            float t = 0.0f;
+            r = round_of(cfg, calls, t);
+            if (r == MGEMM_OK && t < t_min) t_min = t;
+        }
+        best_ms_out = t_min;
+        return r;
+    };
     int best = -1;
     float best_t = 0.0f;
     for (int cfg = 0; cfg < n && st == MGEMM_OK; ++cfg) {
-        st = mgemm_sgemm_ex(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc,
-                            stream, precision, cfg);                     // warm-up
-        float t_min = 1e30f;
-        for (int r = 0; r < reps && st == MGEMM_OK; ++r) {
-            hipError_t e = hipEventRecord(e0, s);
-            if (e == hipSuccess)
-                st = mgemm_sgemm_ex(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C,
-                                    ldc, stream, precision, cfg);
-            if (st) break;
-            if (e == hipSuccess) e = hipEventRecord(e1, s);
-            if (e == hipSuccess) e = hipEventSynchronize(e1);
-            float t = 0.0f;
-            if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
-            if (e != hipSuccess) {
-                (void)hipGetLastError();
-                st = fail(MGEMM_ERR_HIP, std::string("tuning timer: ") + hipGetErrorString(e));
-                break;
-            }
-            if (t < t_min) t_min = t;
-        }
+        float t_min = 0.0f;
+        st = time_of(cfg, t_min);
         if (st == MGEMM_OK && (best < 0 || t_min < best_t)) {
             best = cfg;
             best_t = t_min;
+        }
+    }
+    // A choice other than the built-in default is recorded only if it also
+    // beats the default by more than 2% in a head-to-head, the two timed
+    // alternately three times: of near ties, the default stays.
+    const int ta0 = trans_code(transA), tb0 = trans_code(transB);
+    const int dflt = builtin_default_config(precision, ta0, tb0, M, N, K);
+    if (st == MGEMM_OK && best != dflt && dflt >= 0 && dflt < n) {
+        float td = 1e30f, tb_ = 1e30f;
+        for (int k = 0; k < 3 && st == MGEMM_OK; ++k) {
+            float t = 0.0f;
+            st = time_of(dflt, t);
+            if (st == MGEMM_OK) td = std::min(td, t);
+            if (st == MGEMM_OK) st = time_of(best, t);
+            if (st == MGEMM_OK) tb_ = std::min(tb_, t);
+        }
+        if (st == MGEMM_OK) {
+            if (tb_ < 0.98f * td) {
+                best_t = tb_;
+            } else {
+                best = dflt;
+                best_t = td;
+            }
         }
     }
     (void)hipEventDestroy(e0);
