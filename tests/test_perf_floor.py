@@ -67,3 +67,27 @@ def test_small_product_from_a_graph():
     us = 1000 * time_ms(g.replay, reps=5, warmup=2) / 50
     log("perf floor 256^3 from a graph: %.2f us per call" % us)
     assert us < 15.0
+
+
+def test_fp32_one_tile_per_cu():
+    """1024^3 NN (256 tiles of 64 x 64 x 32, about one per CU) measures 83-93
+    TFLOP/s through the Python binding."""
+    n = 1024
+    A, B, C, ld = square_operands(n)
+    assert mg.default_config("fp32", "N", "N", n, n, n) == 12
+    ms = time_ms(lambda: mg.sgemm("N", "N", n, n, n, 1.0, A, ld, B, ld, 0.0, C, ld), reps=50)
+    log("perf floor 1024^3 fp32: %.4f ms, %.1f TFLOP/s" % (ms, 2 * n ** 3 / ms / 1e9))
+    assert 2 * n ** 3 / ms / 1e9 > 55.0
+
+
+def test_grouped_batch_replay():
+    """The 512-problem batch replayed from its graph measures 70-73 TFLOP/s
+    (FP32) and about 100 (BF16x3) with the library's default plans."""
+    from test_grouped import make_batch
+    problems, data, arena, host = make_batch()
+    flops = sum(2.0 * p["M"] * p["N"] * p["K"] for p in problems)
+    for prec, floor in (("fp32", 45.0), ("bf16x3", 60.0)):
+        with mg.GroupedPlan(problems, prec) as plan:
+            ms = time_ms(plan.launch, reps=50, warmup=20)
+        log("perf floor grouped %s: %.4f ms, %.1f TFLOP/s" % (prec, ms, flops / ms / 1e9))
+        assert flops / ms / 1e9 > floor
