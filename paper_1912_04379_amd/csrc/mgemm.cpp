@@ -493,10 +493,12 @@ namespace mgemm {
 // its leading dimension rounded up to a multiple of 4 floats.
 static int pack_b_f32(int tb, int64_t K, int64_t N, const float* B, int64_t ldb, void* stream,
                       mgemm_packed_b** out) {
+    const int64_t ld = (std::max<int64_t>(K, 1) + 3) / 4 * 4;
+    if (N > 0 && ld > INT64_MAX / (int64_t)sizeof(float) / N)
+        return fail(MGEMM_ERR_UNSUPPORTED, "packed B larger than the address space");
     int dev = 0;
     const int st = check_device(&dev);
     if (st) return st;
-    const int64_t ld = (std::max<int64_t>(K, 1) + 3) / 4 * 4;
     const int64_t bytes = K > 0 && N > 0 ? ld * N * (int64_t)sizeof(float) : 0;
     mgemm_packed_b* h =
         new mgemm_packed_b{MGEMM_PREC_FP32, dev, K, N, nullptr, nullptr, nullptr, bytes, ld};

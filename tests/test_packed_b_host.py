@@ -27,6 +27,7 @@ def pack(transB="N", K=10, N=10, B=0x1000, ldb=10, prec=_lib.PREC_BF16X3, out=Tr
     (dict(ldb=9), -10), (dict(transB="T", N=20, ldb=19), -10),
     (dict(prec=7), _lib.ERR_UNSUPPORTED),
     (dict(prec=_lib.PREC_FP32, ldb=9), -10), (dict(prec=_lib.PREC_FP32, transB="X"), -2),
+    (dict(prec=_lib.PREC_FP32, K=2 ** 40, N=2 ** 40, ldb=2 ** 40), _lib.ERR_UNSUPPORTED),
     (dict(out=False), _lib.ERR_UNSUPPORTED)])
 def test_pack_b_rejects_bad_arguments(args, status):
     st, h = pack(**args)
