@@ -171,17 +171,17 @@ __global__ __launch_bounds__(256, 2) void grouped_kernel(const GroupedProblem* _
             using Cfg = VariantF32<V>;
             const int64_t m0 = (int64_t)tm * Cfg::BM, n0 = (int64_t)tn * Cfg::BN;
             float* sm = reinterpret_cast<float*>(grouped_smem);
-            if (!gp.ta && !gp.tb) tile_f32<Cfg, false, true, true>(d, m0, n0, sm, tid);
-            else if (!gp.ta)      tile_f32<Cfg, false, false, true>(d, m0, n0, sm, tid);
-            else if (!gp.tb)      tile_f32<Cfg, true, true, true>(d, m0, n0, sm, tid);
-            else                  tile_f32<Cfg, true, false, true>(d, m0, n0, sm, tid);
+            if (!gp.ta && !gp.tb) tile_f32<Cfg, false, true, true, true>(d, m0, n0, sm, tid);
+            else if (!gp.ta)      tile_f32<Cfg, false, false, true, true>(d, m0, n0, sm, tid);
+            else if (!gp.tb)      tile_f32<Cfg, true, true, true, true>(d, m0, n0, sm, tid);
+            else                  tile_f32<Cfg, true, false, true, true>(d, m0, n0, sm, tid);
         } else {
             using Cfg = VariantLP<V>;
             const int64_t m0 = (int64_t)tm * Cfg::BM, n0 = (int64_t)tn * Cfg::BN;
-            if (!gp.ta && !gp.tb) tile_lowp<Cfg, Form::BF16X3, false, true, true>(d, m0, n0, grouped_smem, tid);
-            else if (!gp.ta)      tile_lowp<Cfg, Form::BF16X3, false, false, true>(d, m0, n0, grouped_smem, tid);
-            else if (!gp.tb)      tile_lowp<Cfg, Form::BF16X3, true, true, true>(d, m0, n0, grouped_smem, tid);
-            else                  tile_lowp<Cfg, Form::BF16X3, true, false, true>(d, m0, n0, grouped_smem, tid);
+            if (!gp.ta && !gp.tb) tile_lowp<Cfg, Form::BF16X3, false, true, true, true>(d, m0, n0, grouped_smem, tid);
+            else if (!gp.ta)      tile_lowp<Cfg, Form::BF16X3, false, false, true, true>(d, m0, n0, grouped_smem, tid);
+            else if (!gp.tb)      tile_lowp<Cfg, Form::BF16X3, true, true, true, true>(d, m0, n0, grouped_smem, tid);
+            else                  tile_lowp<Cfg, Form::BF16X3, true, false, true, true>(d, m0, n0, grouped_smem, tid);
         }
         __syncthreads();  // LDS is reused by the next tile; next_tile was read
         if (threadIdx.x == 0) next_tile = resolve(ticket);

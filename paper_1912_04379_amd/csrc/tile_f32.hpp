@@ -108,8 +108,13 @@ enum class Step { STAGE_LOAD_FULL, STAGE_LOAD_PART, STAGE, LAST };
 // The loop is split into straight-line pieces (full-slab loads, the one
 // partial slab, no load, last slab) so that no step joins two load
 // sequences: a join makes the compiler wait for every load in flight.
-template <class Cfg, bool AK, bool BKC, bool BUF>
-__device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float* smem, int tid) {
+//
+// MF: this wave reads fragments and issues MFMAs (false: a wave whose block
+// of C lies wholly outside C, which still stages its share of every slab
+// and meets every barrier, but computes and stores nothing).
+template <class Cfg, bool AK, bool BKC, bool BUF, bool MF>
+__device__ inline void tile_f32_body(const GemmDesc& d, int64_t m0, int64_t n0, float* smem,
+                                     int tid) {
     constexpr int BM = Cfg::BM, BK = Cfg::BK, NT = Cfg::NT, S = Cfg::S;
     constexpr int FM = Cfg::FM, FN = Cfg::FN, NC = BK / 8;
     static_assert(NC >= 2, "the pipeline needs two k-chunks per slab");
@@ -158,7 +163,7 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
     lds_barrier();
 
     FragF32<Cfg> f[2];
-    f[0].read(smem, smem + BM * S, wm, wn, l32, h, 0);
+    if constexpr (MF) f[0].read(smem, smem + BM * S, wm, wn, l32, h, 0);
 
     // Instruction counts of one step, for the interleaving below.
     constexpr int N_MFMA = 4 * FM * FN;                    // per k-chunk
@@ -175,8 +180,8 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
         float* nxt = smem + ((kt + 1) & 1) * Cfg::STAGE;
 #pragma unroll
         for (int c = 0; c + 2 < NC; ++c) {
-            f[(c + 1) & 1].read(cur, cur + BM * S, wm, wn, l32, h, c + 1);
-            f[c & 1].mfma(acc);
+            if constexpr (MF) f[(c + 1) & 1].read(cur, cur + BM * S, wm, wn, l32, h, c + 1);
+            if constexpr (MF) f[c & 1].mfma(acc);
             // Issue the next chunk's reads before this chunk's MFMAs, so that
             // all of them hide the reads' latency (left alone, the scheduler
             // sinks the reads to the last few MFMAs).
@@ -185,17 +190,17 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
         }
         if constexpr (kind == Step::LAST) {
             if constexpr (NC > 1) {
-                f[(NC - 1) & 1].read(cur, cur + BM * S, wm, wn, l32, h, NC - 1);
-                f[NC & 1].mfma(acc);
+                if constexpr (MF) f[(NC - 1) & 1].read(cur, cur + BM * S, wm, wn, l32, h, NC - 1);
+                if constexpr (MF) f[NC & 1].mfma(acc);
             }
-            f[(NC - 1) & 1].mfma(acc);
+            if constexpr (MF) f[(NC - 1) & 1].mfma(acc);
         } else {
             __builtin_amdgcn_sched_barrier(0);
             // Chunk NC-2's MFMAs, with the read of chunk NC-1, the writes of
             // slab kt+1 to LDS and the loads of slab kt+2 issued between
             // them (their issue then costs no MFMA time).
             if constexpr (NC > 1)
-                f[(NC - 1) & 1].read(cur, cur + BM * S, wm, wn, l32, h, NC - 1);
+                if constexpr (MF) f[(NC - 1) & 1].read(cur, cur + BM * S, wm, wn, l32, h, NC - 1);
             stage_to_lds<LA, BK>(la, nxt, tid, NT);
             stage_to_lds<LB, BK>(lb, nxt + BM * S, tid, NT);
             if constexpr (kind == Step::STAGE_LOAD_FULL) {
@@ -206,7 +211,7 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
                 lb.template load<false>(pb, (kt + 2) * BK);
             }
             if constexpr (NC > 1) {
-                f[NC & 1].mfma(acc);
+                if constexpr (MF) f[NC & 1].mfma(acc);
                 if constexpr (IL) {
                     __builtin_amdgcn_sched_group_barrier(0x100, N_READ, 0);   // DS read
 #pragma unroll
@@ -225,10 +230,10 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
             }
             __builtin_amdgcn_sched_barrier(0);
             lds_barrier();
-            f[NC & 1].read(nxt, nxt + BM * S, wm, wn, l32, h, 0);
+            if constexpr (MF) f[NC & 1].read(nxt, nxt + BM * S, wm, wn, l32, h, 0);
             // Keep the last chunk's MFMAs after the read of the next slab.
             __builtin_amdgcn_sched_barrier(0);
-            f[(NC - 1) & 1].mfma(acc);
+            if constexpr (MF) f[(NC - 1) & 1].mfma(acc);
             ++kt;
         }
     };
@@ -241,12 +246,32 @@ __device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float
     if (kt + 1 < nk) step(SS{});
     step(SL{});
 
-    Epi epi(d, m0, n0);
+    if constexpr (MF) {
+        Epi epi(d, m0, n0);
 #pragma unroll
-    for (int i = 0; i < FM; ++i)
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < FN; ++j)
-            epi.store_block(wm + 32 * i + l32, wn + 32 * j, lane, acc[i][j]);
+            for (int j = 0; j < FN; ++j)
+                epi.store_block(wm + 32 * i + l32, wn + 32 * j, lane, acc[i][j]);
+    }
+}
+
+// One tile.  SKIP (for tiles that are mostly edge, as in a batch of small
+// products): a wave whose rows or columns of the tile all lie beyond M or N
+// takes the body without fragment reads, MFMAs or stores, so the MFMA pipes
+// of its SIMD serve the other work-group's waves.  The test is wave-uniform.
+template <class Cfg, bool AK, bool BKC, bool BUF, bool SKIP = false>
+__device__ inline void tile_f32(const GemmDesc& d, int64_t m0, int64_t n0, float* smem, int tid) {
+    if constexpr (!SKIP) {
+        tile_f32_body<Cfg, AK, BKC, BUF, true>(d, m0, n0, smem, tid);
+    } else {
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int64_t wm = (wave % Cfg::WGM) * Cfg::WM, wn = (wave / Cfg::WGM) * Cfg::WN;
+        if (m0 + wm < d.M && n0 + wn < d.N)
+            tile_f32_body<Cfg, AK, BKC, BUF, true>(d, m0, n0, smem, tid);
+        else
+            tile_f32_body<Cfg, AK, BKC, BUF, false>(d, m0, n0, smem, tid);
+    }
 }
 
 }  // namespace mgemm

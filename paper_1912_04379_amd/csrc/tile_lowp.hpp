@@ -99,8 +99,12 @@ __device__ inline void stage_lowp(const Loader& ld, char* hi, char* lo,
     }
 }
 
-template <class Cfg, Form F, bool AK, bool BKC, bool BUF>
-__device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char* smem, int tid) {
+// MF: this wave reads fragments, issues MFMAs and stores its block (false:
+// a wave whose block of C lies wholly outside C; it still stages its share
+// of every slab and meets every barrier).
+template <class Cfg, Form F, bool AK, bool BKC, bool BUF, bool MF>
+__device__ inline void tile_lowp_body(const GemmDesc& d, int64_t m0, int64_t n0, char* smem,
+                                      int tid) {
     constexpr int BM = Cfg::BM, BN = Cfg::BN, BK = Cfg::BK, NT = Cfg::NT;
     constexpr int FM = Cfg::FM, FN = Cfg::FN;
     constexpr int ARR = (BM + BN) * Cfg::ROW_BYTES;                 // one array, one stage
@@ -230,7 +234,7 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
             lb.template load<false>(pb, (kt + 1) * BK);
         }
         __builtin_amdgcn_sched_barrier(0);
-        compute(cur);
+        if constexpr (MF) compute(cur);
         if constexpr (kind != 2) {
             put(cur ^ 1);
             __syncthreads();
@@ -241,6 +245,7 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
     if (kt + 1 < nk) step(std::integral_constant<int, 1>{});
     step(std::integral_constant<int, 2>{});
 
+    if constexpr (!MF) return;
     Epi epi(d, m0, n0);
 #pragma unroll
     for (int i = 0; i < FM; ++i)
@@ -258,6 +263,24 @@ __device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char
             }
             epi.store_block(wm + 32 * i + l32, wn + 32 * j, lane, v);
         }
+}
+
+// One tile.  SKIP (for tiles that are mostly edge, as in a batch of small
+// products): a wave whose rows or columns of the tile all lie beyond M or N
+// takes the body without fragment reads, MFMAs or stores.  The test is
+// wave-uniform.
+template <class Cfg, Form F, bool AK, bool BKC, bool BUF, bool SKIP = false>
+__device__ inline void tile_lowp(const GemmDesc& d, int64_t m0, int64_t n0, char* smem, int tid) {
+    if constexpr (!SKIP) {
+        tile_lowp_body<Cfg, F, AK, BKC, BUF, true>(d, m0, n0, smem, tid);
+    } else {
+        const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+        const int64_t wm = (wave % Cfg::WGM) * Cfg::WM, wn = (wave / Cfg::WGM) * Cfg::WN;
+        if (m0 + wm < d.M && n0 + wn < d.N)
+            tile_lowp_body<Cfg, F, AK, BKC, BUF, true>(d, m0, n0, smem, tid);
+        else
+            tile_lowp_body<Cfg, F, AK, BKC, BUF, false>(d, m0, n0, smem, tid);
+    }
 }
 
 }  // namespace mgemm
