@@ -245,50 +245,45 @@ def test_grouped_equals_single_calls_with_same_tile():
     assert torch.equal(arena, grouped)
 
 
-# Problems whose edge tiles leave whole 32-row or 32-column wave blocks (64
-# for the 128 x 128 tiles) outside C: those waves stage their share of each
-# slab but issue no MFMAs and store nothing.
-SKIP_SHAPES = [(1, 300, 40, "N"), (300, 1, 40, "T"), (32, 97, 64, "N"), (97, 32, 33, "T"),
-               (33, 160, 17, "N"), (160, 33, 100, "T"), (64, 65, 31, "N"), (65, 64, 48, "T"),
-               (129, 129, 64, "N"), (16, 16, 16, "T"), (200, 70, 7, "N")]
 # Grouped variant -> single-call configuration with the same tile code.
 SAME_TILE = {"fp32": {0: 1, 1: 0, 2: 12}, "bf16x3": {0: 3, 1: 1}}
 
 
-@pytest.mark.gpu
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
-@pytest.mark.parametrize("variant", [0, 1, 2])
-def test_waves_outside_c_skip_their_work(precision, variant):
-    """Every variant on edge-heavy problems: within the bar of the oracle
-    and, where a single-call configuration runs the same tile, bitwise
-    equal to it."""
+def check_variant(precision, variant, shapes, seed):
+    """One plan of `shapes` ((M, N, K, transA, transB), padded leading
+    dimensions, alpha 1.5, beta -0.75) with every bucket on `variant`:
+    each C within the oracle's bar with its padding rows untouched and,
+    where a single-call configuration runs the same tile, bitwise equal
+    to that call."""
     import torch
-    print("skipped waves", precision, variant, flush=True)
-    rng = np.random.default_rng(31 + variant)
+    rng = np.random.default_rng(seed)
     probs, keep, hosts = [], [], []
-    for (M, N, K, ta) in SKIP_SHAPES:
+    for (M, N, K, ta, tb) in shapes:
         lda = K + 3 if ta == "T" else M + 5
+        ldb = N + 2 if tb == "T" else K + 1
         A = synth.matrix(rng, K, M, lda) if ta == "T" else synth.matrix(rng, M, K, lda)
-        B = synth.matrix(rng, K, N, K + 1)
+        B = synth.matrix(rng, N, K, ldb) if tb == "T" else synth.matrix(rng, K, N, ldb)
         C = synth.matrix(rng, M, N, M + 2)
         t = [torch.from_numpy(x.copy()).cuda() for x in (A, B, C)]
         keep.append(t)
         hosts.append((A, B, C))
-        probs.append(dict(transA=ta, transB="N", M=M, N=N, K=K, alpha=1.5, beta=-0.75, A=t[0],
-                          lda=lda, B=t[1], ldb=K + 1, C=t[2], ldc=M + 2))
+        probs.append(dict(transA=ta, transB=tb, M=M, N=N, K=K, alpha=1.5, beta=-0.75, A=t[0],
+                          lda=lda, B=t[1], ldb=ldb, C=t[2], ldc=M + 2))
     with mg.GroupedPlan(probs, precision, bucket_configs=[variant] * 4) as plan:
         plan.launch()
         torch.cuda.synchronize()
     grouped = [t[2].clone() for t in keep]
     for p, (A, B, C), g in zip(probs, hosts, grouped):
-        args = (p["transA"], "N", p["M"], p["N"], p["K"], p["alpha"], A, p["lda"], B, p["ldb"],
-                p["beta"], C, p["ldc"])
+        args = (p["transA"], p["transB"], p["M"], p["N"], p["K"], p["alpha"], A, p["lda"], B,
+                p["ldb"], p["beta"], C, p["ldc"])
         ref = oracle.sgemm(*args)
-        got = g.cpu().numpy().reshape(p["N"], p["ldc"])[:, :p["M"]].T.astype(np.float64)
-        assert oracle.normwise_rel_err(got, ref) <= 1e-5, (precision, variant, p["M"], p["N"])
+        out = g.cpu().numpy().reshape(p["N"], p["ldc"])
+        got = out[:, :p["M"]].T.astype(np.float64)
+        case = (precision, variant, p["M"], p["N"], p["K"], p["transA"], p["transB"])
+        assert oracle.normwise_rel_err(got, ref) <= 1e-5, case
         # the rows between M and ldc are not C: untouched
-        pad = g.cpu().numpy().reshape(p["N"], p["ldc"])[:, p["M"]:]
-        assert np.array_equal(pad, C.reshape(p["N"], p["ldc"])[:, p["M"]:], equal_nan=True)
+        assert np.array_equal(out[:, p["M"]:], C.reshape(p["N"], p["ldc"])[:, p["M"]:],
+                              equal_nan=True), case
     cfg = SAME_TILE[precision].get(variant)
     if cfg is None:
         return
@@ -297,12 +292,44 @@ def test_waves_outside_c_skip_their_work(precision, variant):
     assert (vi["bm"], vi["bn"], vi["bk"]) == (ci["bm"], ci["bn"], ci["bk"])
     for p, (A, B, C), t, g in zip(probs, hosts, keep, grouped):
         t[2].copy_(torch.from_numpy(C))
-        mg.sgemm(p["transA"], "N", p["M"], p["N"], p["K"], p["alpha"], p["A"], p["lda"], p["B"],
-                 p["ldb"], p["beta"], p["C"], p["ldc"], precision=precision, config=cfg)
+        mg.sgemm(p["transA"], p["transB"], p["M"], p["N"], p["K"], p["alpha"], p["A"], p["lda"],
+                 p["B"], p["ldb"], p["beta"], p["C"], p["ldc"], precision=precision, config=cfg)
         torch.cuda.synchronize()
         # bit patterns: the NaN rows between M and ldc compare equal too
         assert torch.equal(t[2].view(torch.int32), g.view(torch.int32)), \
-            (precision, variant, p["M"], p["N"], p["K"])
+            (precision, variant, p["M"], p["N"], p["K"], p["transA"], p["transB"])
+
+
+# Problems whose edge tiles leave whole 32-row or 32-column wave blocks (64
+# for the 128 x 128 tiles) outside C: those waves stage their share of each
+# slab but issue no MFMAs and store nothing.
+SKIP_SHAPES = [(1, 300, 40, "N"), (300, 1, 40, "T"), (32, 97, 64, "N"), (97, 32, 33, "T"),
+               (33, 160, 17, "N"), (160, 33, 100, "T"), (64, 65, 31, "N"), (65, 64, 48, "T"),
+               (129, 129, 64, "N"), (16, 16, 16, "T"), (200, 70, 7, "N")]
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_waves_outside_c_skip_their_work(precision, variant):
+    """Every variant on edge-heavy problems."""
+    print("skipped waves", precision, variant, flush=True)
+    check_variant(precision, variant, [sh + ("N",) for sh in SKIP_SHAPES], 31 + variant)
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_every_trans_pair_in_one_batch(precision, variant):
+    """A batch mixing all four (transA, transB) pairs, so every operand
+    layout of the persistent kernel runs, on ragged shapes."""
+    print("trans pairs", precision, variant, flush=True)
+    rng = np.random.default_rng(41 + variant)
+    shapes = []
+    for i in range(24):
+        M, N, K = (int(v) for v in rng.integers(1, 300, size=3))
+        shapes.append((M, N, K, "NT"[i % 2], "NT"[(i // 2) % 2]))
+    check_variant(precision, variant, shapes, 51 + variant)
 
 
 @pytest.mark.gpu
