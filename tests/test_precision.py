@@ -101,6 +101,17 @@ def test_forms_every_config(prec, cfg):
 
 
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
+@pytest.mark.parametrize("cfg", range(N_CONFIGS))
+def test_forms_every_config_every_trans_pair(prec, cfg):
+    """Each configuration instantiates its tile once per operand layout:
+    every one of them on a ragged product."""
+    for ta, tb in TRANS:
+        c = synth.sgemm_case(33, ta, tb, 301, 259, 97, alpha=-1.25, beta=0.5, pad=7)
+        log("%s cfg %d %s%s" % (prec, cfg, ta, tb))
+        check_form(c, prec, run(c, precision=prec, config=cfg))
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
 @pytest.mark.parametrize("ta,tb", TRANS)
 @pytest.mark.parametrize("shape", [(200, 136, 5000), (300, 260, 3001)])
 def test_forms_split_k(prec, ta, tb, shape, tmp_path, monkeypatch):
