@@ -215,7 +215,27 @@ __global__ __launch_bounds__(256) void f16_amax_kernel(GemmDesc d, int ta, int t
         nan |= x != x;
         amax = fmaxf(amax, fabsf(x));
     };
-    if (pcontig) {
+    if (pcontig && rows == 32 && (ld & 3) == 0 && ((uintptr_t)X & 15) == 0) {
+        // A whole panel with 16-byte aligned columns: 8 lanes read one
+        // column's 32 rows as 16-byte loads, the 32 lane groups take every
+        // 32nd k, 8 loads in flight per lane.
+        const float* col = X + p0 + 4 * (t & 7);
+        int64_t k = k0 + (t >> 3);
+        for (; k + 224 < k1; k += 256) {
+            f32x4 x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) x[u] = *reinterpret_cast<const f32x4*>(col + (k + 32 * u) * ld);
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) take(x[u][e]);
+        }
+        for (; k < k1; k += 32) {
+            const f32x4 x = *reinterpret_cast<const f32x4*>(col + k * ld);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) take(x[e]);
+        }
+    } else if (pcontig) {
         // Lane r reads row r of the panel; the 8 lane groups take every
         // 8th k, 8 loads in flight per lane.
         const int r = t & 31;
