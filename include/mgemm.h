@@ -107,9 +107,12 @@ int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  * tiles (128 x 128, or 64 x 64 for few tiles), their S*M*N*4 bytes of
  * partial products come from the pool too (the FP16 unscale is applied per
  * piece, exactly), and where splitting does not apply configuration 1 runs.
- * The library's choice takes it for BF16x3 products with at most 128 tiles
- * of 128 x 128 and K >= 2048, or at most 256 and K >= 8192, and for FP16
- * products with at most 64 such tiles and K >= 2048.
+ * The FP16 form's 128 x 128 pieces run on packed copies of op(A) and op(B)
+ * (2(M + N)K more bytes of workspace) where those fit, with the same
+ * results bitwise.  The library's choice takes it for BF16x3 products with
+ * at most 128 tiles of 128 x 128 and K >= 2048, or at most 256 and
+ * K >= 8192, and for FP16 products with at most 64 such tiles and
+ * K >= 2048, or at most 160 and K >= 3072.
  * An allocation failure returns MGEMM_ERR_ALLOC before anything runs.  A
  * packed configuration that the product cannot use (K too long for 32-bit
  * block offsets, or an LDS ring larger than a CU) runs configuration 0.

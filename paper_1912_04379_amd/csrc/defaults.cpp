@@ -198,10 +198,17 @@ int f16s_default_config(int64_t M, int64_t N, int64_t K) {
     // of 3072 or more.
     // Few tiles and a long k range: split-K.  Measured NN, TFLOP/s, split
     // against the best unsplit configuration: 512^2 x 16384 95 against 44;
-    // 1024^2 x 8192 181 against 140; 256^2 x 65536 80 against 13; 1000^2 x
-    // 4000 120 against 105; 1024^2 x 2048 83 against 79.  With more tiles the
-    // packed 128 x 128 tile wins (2048 x 1024 x 3072: 186 against 163).
-    if (tile_count(M, N, 128, 128) <= NUM_CUS / 4 && K >= 2048 && lowp_split_fits(M, N, K))
+    // 1024^2 x 8192 240 against 140; 256^2 x 65536 80 against 13; 1000^2 x
+    // 4000 132 against 105; 1024^2 x 2048 83 against 79.  From a quarter
+    // round of 128 x 128 tiles up the pieces run on packed operands, which
+    // beat the packed 128 x 128 tile for K >= 3072 up to about 150 tiles
+    // (1152^2 x 4096 181 against 150, 1280^2 x 8192 290 against 212,
+    // 1536^2 x 4096 270 against 251, 2048 x 1024 x 3072 214 against 198)
+    // and lose below (1280^2 x 2048 129 against 134, 1536^2 x 2048 174
+    // against 186) and at a full round (2048^2 x 4096 377 against 400).
+    const int64_t t128 = tile_count(M, N, 128, 128);
+    if (((t128 <= NUM_CUS / 4 && K >= 2048) || (t128 <= 5 * NUM_CUS / 8 && K >= 3072)) &&
+        lowp_split_fits(M, N, K))
         return LOWP_SPLITK_CONFIG;
     if (K < 512) return lowp_default(M, N);
     const double big = 906.0 * slot_share(M, N, 256, 256);

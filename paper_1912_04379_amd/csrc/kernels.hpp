@@ -58,6 +58,17 @@ hipError_t launch_f16s(int cfg, bool transA, bool transB, const GemmDesc& d,
 // whole K.  Needs buffer_path_ok(d), d.M <= MAX_BUF_LD and p.splits >= 2.
 hipError_t launch_lowp_splitk(bool bf16x3, bool transA, bool transB, const GemmDesc& d,
                               const SplitKPlan& p, float* workspace, hipStream_t stream);
+// The same split of the FP16 form with its pieces on packed operands (the
+// pipelined packed 128 x 128 tile), bitwise equal to launch_lowp_splitk:
+// op(A) and op(B) are packed once into `pack_ws` (f16s_packed_splitk_bytes)
+// and the pieces go to `slices` (S*M*N floats).  Applies where
+// f16s_packed_splitk_supported (128 x 128 pieces, kc a multiple of the
+// block depth, lane offsets within 31 bits).
+int64_t f16s_packed_splitk_bytes(int64_t M, int64_t N, int64_t K);
+bool f16s_packed_splitk_supported(const SplitKPlan& p, int64_t M, int64_t N, int64_t K);
+hipError_t launch_f16s_packed_splitk(bool transA, bool transB, const GemmDesc& d,
+                                     const SplitKPlan& p, char* pack_ws, float* slices,
+                                     hipStream_t stream);
 
 // Pre-packed 16-bit path (direct-to-LDS engine).  Configuration c of this
 // family is configuration LOWP_INSTAGE_CONFIGS + c of the BF16x3 and FP16

@@ -328,10 +328,22 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
         split_bytes = 0;
         cfg = 1;
     }
+    // The FP16 form's split-K pieces run on packed operands where that
+    // applies and the operands fit (same results bitwise; faster than
+    // scaling while staging in every piece).
+    int64_t split_pack_bytes = 0;
+    const int64_t split_room = (split_bytes + 255) / 256 * 256;   // packed operands start aligned
+    if (!bf && split.splits && f16s_packed_splitk_supported(split, M, N, K)) {
+        split_pack_bytes = f16s_packed_splitk_bytes(M, N, K);
+        if (fixed && exp_bytes + split_room + split_pack_bytes > fixed->cap) split_pack_bytes = 0;
+    }
     dp.cfg = cfg;
-    dp.path = packed ? "packed" : split.splits ? "lowp_split_k" : "in_staging";
+    dp.path = packed                             ? "packed"
+              : split.splits && split_pack_bytes ? "lowp_split_k_packed"
+              : split.splits                     ? "lowp_split_k"
+                                                 : "in_staging";
     dp.splits = split.splits;
-    dp.ws_bytes = exp_bytes + pack_bytes + split_bytes;
+    dp.ws_bytes = exp_bytes + pack_bytes + (split_pack_bytes ? split_room + split_pack_bytes : split_bytes);
     char* ws = nullptr;
     if (dp.ws_bytes > 0) {
         e = fault_injected() ? hipErrorOutOfMemory : take_workspace(dev, fixed, dp.ws_bytes, s, &ws);
@@ -351,6 +363,9 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
     if (e == hipSuccess) {
         if (packed)
             e = launch_packed(bf, cfg - LOWP_INSTAGE_CONFIGS, ta, tb, d, ws + exp_bytes, s);
+        else if (split.splits && split_pack_bytes)
+            e = launch_f16s_packed_splitk(ta, tb, d, split, ws + exp_bytes + split_room,
+                                          reinterpret_cast<float*>(ws + exp_bytes), s);
         else if (split.splits)
             e = launch_lowp_splitk(bf, ta, tb, d, split, reinterpret_cast<float*>(ws + exp_bytes),
                                    s);

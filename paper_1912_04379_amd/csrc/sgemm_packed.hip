@@ -152,7 +152,7 @@ __global__ __launch_bounds__(Cfg::NT, Cfg::WPE) void packed_kernel(GemmDesc d, P
     grouped_tile<8>(xcd_remap(blockIdx.x, gridDim.x), tiles_m, tiles_n, tm, tn);
     if constexpr (Cfg::PIPELINED)
         tile_packed_pp<Cfg, F, BUF>(d, pk, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN,
-                                    packed_smem);
+                                    packed_smem, 0, pk.kb);
     else
         tile_packed<Cfg, F, BUF>(d, pk, (int64_t)tm * Cfg::BM, (int64_t)tn * Cfg::BN,
                                  packed_smem);
@@ -356,6 +356,88 @@ hipError_t launch_packed_b_ready(bool bf16x3, int cfg, bool ta, const GemmDesc& 
         }
         return launch_main<C, Form::F16S>(d, pk, s);
     });
+}
+
+// ---------------------------------------------------------------------------
+// Split-K of the scaled-FP16 form over packed operands.  Piece s of every
+// tile runs the pipelined packed 128 x 128 tile over the k blocks
+// [s kbp, min((s+1) kbp, kb)) into slice s of the workspace (alpha 1, beta 0,
+// no activation, unscaled by the panel exponents of the whole K, which are
+// powers of two); the split-K reduction then adds the slices in order.  The
+// pieces take the same MFMAs in the same order as the in-staging pieces, so
+// the results are the same bitwise.
+// ---------------------------------------------------------------------------
+using PKSplitCfg = PKCfg7;
+
+__global__ __launch_bounds__(PKSplitCfg::NT, PKSplitCfg::WPE) void f16s_packed_splitk_kernel(
+    GemmDesc d, PackedArgs pk, uint32_t tiles_m, uint32_t tiles_n, int64_t kbp, float* ws) {
+    extern __shared__ __attribute__((aligned(16))) char packed_smem[];
+    using C = PKSplitCfg;
+    // Logical id -> (piece, tile): one XCD takes consecutive tiles of one
+    // piece, which share panels of A and B.
+    const uint32_t id = xcd_remap(blockIdx.x, gridDim.x);
+    const uint32_t tiles = tiles_m * tiles_n;
+    const uint32_t s = id / tiles;
+    uint32_t tm, tn;
+    grouped_tile<8>(id - s * tiles, tiles_m, tiles_n, tm, tn);
+    const int64_t kb0 = (int64_t)s * kbp;
+    const int64_t cnt = pk.kb - kb0 < kbp ? pk.kb - kb0 : kbp;
+    GemmDesc p = d;
+    p.C = ws + (int64_t)s * d.M * d.N;
+    p.ldc = d.M;
+    p.alpha = 1.0f;
+    p.beta = 0.0f;
+    p.act = ACT_NONE;   // applied once, by the reduction
+    tile_packed_pp<C, Form::F16S, true>(p, pk, (int64_t)tm * C::BM, (int64_t)tn * C::BN,
+                                        packed_smem, kb0, cnt);
+}
+
+int64_t f16s_packed_splitk_bytes(int64_t M, int64_t N, int64_t K) {
+    return packed_operand_bytes(false, PKSplitCfg::KW, M, K) +
+           packed_operand_bytes(false, PKSplitCfg::KW, N, K);
+}
+
+bool f16s_packed_splitk_supported(const SplitKPlan& p, int64_t M, int64_t N, int64_t K) {
+    constexpr int cfg = 7;
+    static_assert(std::is_same<PKSplitCfg, PKCfg7>::value, "split-K pieces use configuration 7");
+    return p.splits >= 2 && !p.small_tile && p.kc % PKSplitCfg::KW == 0 &&
+           packed_supported(false, cfg, M, N, K);
+}
+
+hipError_t launch_f16s_packed_splitk(bool ta, bool tb, const GemmDesc& d, const SplitKPlan& p,
+                                     char* pack_ws, float* slices, hipStream_t s) {
+    using C = PKSplitCfg;
+    constexpr int kw = C::KW;
+    if (!f16s_packed_splitk_supported(p, d.M, d.N, d.K) || !buffer_path_ok(d) ||
+        d.M > MAX_BUF_LD || !d.expA || !d.expB || !pack_ws || !slices)
+        return hipErrorInvalidValue;
+    if ((int64_t)(p.splits - 1) * p.kc >= d.K) return hipErrorInvalidValue;   // empty piece
+    const int64_t kb = (d.K + kw - 1) / kw;
+    PackedArgs pk{};
+    pk.kb = kb;
+    pk.pb_a = (d.M + 31) / 32;
+    pk.pb_b = (d.N + 31) / 32;
+    char* a = pack_ws;
+    char* b = pack_ws + packed_operand_bytes(false, kw, d.M, d.K);
+    pk.a_hi = a;
+    pk.b_hi = b;
+    // op(A) is K-contiguous for A 'T'; op(B) is K-contiguous for B 'N'.
+    hipError_t e = launch_pack<Form::F16S, kw>(ta, d.A, d.lda, d.M, d.K, a, nullptr, d.expA, s);
+    if (e == hipSuccess)
+        e = launch_pack<Form::F16S, kw>(!tb, d.B, d.ldb, d.N, d.K, b, nullptr, d.expB, s);
+    if (e != hipSuccess) return e;
+    const int64_t tiles_m = (d.M + C::BM - 1) / C::BM, tiles_n = (d.N + C::BN - 1) / C::BN;
+    const int64_t grid = tiles_m * tiles_n * p.splits;
+    if (grid > 0xffffffffLL) return hipErrorInvalidValue;
+    constexpr int bytes = PackedStage<C, Form::F16S>::SMEM;
+    e = hipFuncSetAttribute((const void*)f16s_packed_splitk_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(f16s_packed_splitk_kernel, dim3((uint32_t)grid), dim3(C::NT), bytes, s, d, pk,
+                       (uint32_t)tiles_m, (uint32_t)tiles_n, p.kc / kw, slices);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_splitk_reduce(slices, p.splits, d, s);
 }
 
 }  // namespace mgemm

@@ -106,10 +106,12 @@ struct PackedIssuer {
     uint32_t goff[PW];   // lane's byte offset from the piece's first block
     int kb, wave;
 
+    // Stages 0 .. cnt-1 are the blocks kb0 .. kb0+cnt-1 of the operands (the
+    // whole K: kb0 = 0, cnt = pk.kb).
     __device__ inline PackedIssuer(const PackedArgs& pk, int64_t m0, int64_t n0, int wave_,
-                                   int lane) {
+                                   int lane, int64_t kb0, int64_t cnt) {
         constexpr int BM = Cfg::BM, GROUPS = (Cfg::BM + Cfg::BN) / RPC;
-        kb = (int)pk.kb;
+        kb = (int)cnt;
         wave = wave_;
 #pragma unroll
         for (int t = 0; t < PW; ++t) {
@@ -123,7 +125,7 @@ struct PackedIssuer {
             goff[t] = (uint32_t)((int64_t)(p >> 5) * pk.kb * Cfg::BLOCK + (p & 31) * Cfg::ROW_BYTES +
                                  c * 16);
             const char* arr = is_a ? (lo ? pk.a_lo : pk.a_hi) : (lo ? pk.b_lo : pk.b_hi);
-            const int64_t first = (is_a ? m0 : n0) / 32 * pk.kb * Cfg::BLOCK;
+            const int64_t first = ((is_a ? m0 : n0) / 32 * pk.kb + kb0) * Cfg::BLOCK;
             base[t] = arr + first;
             bytes[t] = (is_a ? pk.pb_a : pk.pb_b) * pk.kb * Cfg::BLOCK - first;
         }
@@ -160,7 +162,7 @@ __device__ inline void tile_packed(const GemmDesc& d, const PackedArgs& pk, int6
     const int wn = (wave / Cfg::WGM) * Cfg::WN;
     const int64_t pan_a = (d.M + 31) / 32, pan_b = (d.N + 31) / 32;
 
-    const PackedIssuer<Cfg, F> ld(pk, m0, n0, wave, lane);
+    const PackedIssuer<Cfg, F> ld(pk, m0, n0, wave, lane, 0, pk.kb);
     auto issue = [&](int64_t st) { ld.issue(smem, (int)st); };
 
     f32x16 acc[FM][FN];
@@ -286,7 +288,7 @@ struct PPFrags {
 
 template <class Cfg, Form F, bool BUF>
 __device__ inline void tile_packed_pp(const GemmDesc& d, const PackedArgs& pk, int64_t m0,
-                                      int64_t n0, char* smem) {
+                                      int64_t n0, char* smem, int64_t kb0, int64_t cnt) {
     using St = PackedStage<Cfg, F>;
     constexpr int BM = Cfg::BM, NS = Cfg::NS, FM = Cfg::FM, FN = Cfg::FN;
     constexpr int PW = St::PER_WAVE, KW = Cfg::KW, RB = Cfg::ROW_BYTES;
@@ -301,7 +303,7 @@ __device__ inline void tile_packed_pp(const GemmDesc& d, const PackedArgs& pk, i
     const int wn = (wave / Cfg::WGM) * Cfg::WN;
     const int64_t pan_a = (d.M + 31) / 32, pan_b = (d.N + 31) / 32;
 
-    const PackedIssuer<Cfg, F> ld(pk, m0, n0, wave, lane);
+    const PackedIssuer<Cfg, F> ld(pk, m0, n0, wave, lane, kb0, cnt);
     auto issue = [&](int64_t st) { ld.issue(smem, (int)st); };
     auto co = [](int p, int c) { return p * RB + (pk_slot<KW>(p, c) << 4); };
     auto read = [&](int s, PPFrags<Cfg, F>& f) {
@@ -374,7 +376,7 @@ __device__ inline void tile_packed_pp(const GemmDesc& d, const PackedArgs& pk, i
     using Zero = std::integral_constant<int, 0>;
     using All = std::integral_constant<int, NQ>;
 
-    const int nk = (int)pk.kb;   // the packed path keeps block counts below 2^31
+    const int nk = (int)cnt;   // the packed path keeps block counts below 2^31
 #pragma unroll
     for (int s = 0; s < NS; ++s) issue(s);
     PPFrags<Cfg, F> fr[2];

@@ -260,12 +260,14 @@ def test_bf16x3_default_rule_slot_share(shape, cfg):
     ("bf16x3", (1024, 4096, 8192), True), ("bf16x3", (1024, 1024, 1024), False),
     ("bf16x3", (2048, 2048, 4096), False), ("bf16x3", (8192, 8192, 8192), False),
     ("fp16s", (512, 512, 16384), True), ("fp16s", (1024, 1024, 8192), True),
-    ("fp16s", (1000, 1000, 4000), True), ("fp16s", (2048, 1024, 3072), False),
+    ("fp16s", (1000, 1000, 4000), True), ("fp16s", (2048, 1024, 3072), True),
+    ("fp16s", (1536, 1536, 4096), True), ("fp16s", (1280, 1280, 2048), False),
     ("fp16s", (1024, 4096, 8192), False), ("fp16s", (2048, 2048, 4096), False)])
 def test_lowp_default_rule_split_k(prec, shape, split):
     """The 16-bit split-K rule as documented: BF16x3 for at most half a round
     of 128 x 128 tiles with K >= 2048 or a full round with K >= 8192; FP16
-    for at most a quarter round with K >= 2048."""
+    for at most a quarter round with K >= 2048 or five eighths of a round
+    with K >= 3072."""
     got = mg.default_config(prec, "N", "N", *shape)
     assert (got == mg.config_count(prec) - 1) == split
 

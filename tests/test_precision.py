@@ -142,6 +142,42 @@ def test_forms_split_k_integer_inputs_bitwise(prec):
     assert np.array_equal(got, oracle.sgemm(*args_of(c)))
 
 
+# 81 tiles of 128 x 128 (at least a quarter of the CUs), K = 2080: seven
+# pieces of 320 k (the last 160), each on packed operands for the FP16 form.
+PACKED_SPLIT_SHAPE = (1040, 1030, 2080)
+
+
+@pytest.mark.parametrize("ta,tb", TRANS)
+def test_fp16s_split_k_on_packed_operands(ta, tb, tmp_path, monkeypatch):
+    """Split-K of the scaled-FP16 form with 128 x 128 pieces packs each
+    operand once and runs the pieces on the packed copies: within the form's
+    bars, bitwise the same on a second run, and that path taken."""
+    M, N, K = PACKED_SPLIT_SHAPE
+    logf = tmp_path / "mgemm.log"
+    monkeypatch.setenv("MGEMM_LOG", str(logf))
+    c = synth.sgemm_case(35, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=3, dist="loguni")
+    log("fp16s packed split-K %s%s" % (ta, tb))
+    got = run(c, precision="fp16s", config=SPLITK_CONFIG)
+    check_form(c, "fp16s", got)
+    again = run(c, precision="fp16s", config=SPLITK_CONFIG)
+    assert np.array_equal(got.view(np.uint32), again.view(np.uint32))
+    assert "-> lowp_split_k_packed cfg=%d splits=7" % SPLITK_CONFIG in logf.read_text()
+
+
+def test_fp16s_split_k_on_packed_operands_integers_bitwise(tmp_path, monkeypatch):
+    """Small integers: every partial sum is exact, so a block of k missing
+    from a piece, or taken twice, would show in the sum."""
+    M, N, K = PACKED_SPLIT_SHAPE
+    logf = tmp_path / "mgemm.log"
+    monkeypatch.setenv("MGEMM_LOG", str(logf))
+    c = synth.sgemm_case(36, "T", "N", M, N, K, alpha=1.0, beta=1.0, dist="int16",
+                         dist_c="int16")
+    log("fp16s packed split-K integers")
+    got = logical_c(run(c, precision="fp16s", config=SPLITK_CONFIG), c)
+    assert np.array_equal(got, oracle.sgemm(*args_of(c)))
+    assert "-> lowp_split_k_packed" in logf.read_text()
+
+
 @pytest.mark.parametrize("prec", ["bf16x3", "fp16s"])
 def test_wide_range_inputs_2048(prec):
     """Sign-random magnitudes 2**U[-8, 8], NN at 2048^3, lda = rows + 16,

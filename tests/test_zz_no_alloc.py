@@ -104,3 +104,24 @@ def test_noalloc_argument_errors_match_sgemm_ex():
     L = mg.lib()
     args = (b"N", b"N", 4, 4, 4, 1.0, 0x1000, 3, 0x2000, 4, 0.0, 0x3000, 4, None, 0, -1)
     assert L.mgemm_sgemm_ex_noalloc(*args) == L.mgemm_sgemm_ex(*args) == -8
+
+
+def test_fp16s_split_pieces_staged_and_packed_agree(tmp_path, monkeypatch):
+    """1024 x 1024 x 16384 scaled FP16 in split-K (eight pieces of 2048 k,
+    128 x 128 tiles): the pool holds packed copies of both operands (64 MiB)
+    beside the 32 MiB of partial products and the pieces run on them; the
+    64 MiB scratch array cannot, so there the pieces scale while staging.
+    Both issue the same MFMAs in the same order: equal bitwise."""
+    logf = tmp_path / "mgemm.log"
+    monkeypatch.setenv("MGEMM_LOG", str(logf))
+    log("noalloc fp16s split-K staged against packed pieces")
+    c = synth.sgemm_case(24, "N", "N", 1024, 1024, 16384, alpha=1.5, beta=-0.5, pad=3)
+    got, ref = _both(c, "fp16s", 13)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32)), \
+        "in-staging pieces differ from packed pieces"
+    sampled_check(c, got, count=600, bound_fn=None, normwise=1e-3)
+    lines = _log_lines(logf)
+    noalloc = [l for l in lines if l.startswith("mgemm: sgemm_noalloc")]
+    pooled = [l for l in lines if l.startswith("mgemm: sgemm fp16s")]
+    assert len(noalloc) == 1 and "-> lowp_split_k cfg=13 splits=8" in noalloc[0], lines
+    assert len(pooled) == 1 and "-> lowp_split_k_packed cfg=13 splits=8" in pooled[0], lines
