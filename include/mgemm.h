@@ -174,9 +174,12 @@ int mgemm_sgemm_act(char transA, char transB, int64_t M, int64_t N, int64_t K,
  * packed 16-bit configuration with its packed operands) returns
  * MGEMM_ERR_UNSUPPORTED and launches nothing; with config = -1 the library
  * takes its usual choice when it fits, else a configuration that needs
- * less (unsplit tiles; 16-bit operands split or scaled while staging).  Scaled FP16 always needs its panel exponents and
- * partial maxima (about (M+N)/32 * (4 + 4*ceil(K/2048)) bytes); a product
- * whose exponents exceed the array returns MGEMM_ERR_UNSUPPORTED.
+ * less (unsplit tiles; 16-bit operands split or scaled while staging).
+ * Scaled-FP16 split-K whose packed operands do not fit beside its partial
+ * products runs its pieces scaling while staging, with the same results
+ * bitwise.  Scaled FP16 always needs its panel exponents and partial maxima
+ * (about (M+N)/32 * (4 + 4*ceil(K/2048)) bytes); a product whose exponents
+ * exceed the array returns MGEMM_ERR_UNSUPPORTED.
  */
 #define MGEMM_NOALLOC_SCRATCH_BYTES (64LL << 20)
 int mgemm_sgemm_ex_noalloc(char transA, char transB, int64_t M, int64_t N,
