@@ -116,6 +116,14 @@ int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  * An allocation failure returns MGEMM_ERR_ALLOC before anything runs.  A
  * packed configuration that the product cannot use (K too long for 32-bit
  * block offsets, or an LDS ring larger than a CU) runs configuration 0.
+ * FP32 with config = -1, no choice recorded for the shape and no
+ * activation: a product whose M and N are each a multiple of 256 or at most
+ * 64 past one (at least one past), with a whole-tile block Mm x Nm of at
+ * least 2^37 flops, runs as three products on the same stream, each with
+ * its own default configuration: the block, rows Mm..M-1 of C (all
+ * columns), and columns Nm..N-1 of its first Mm rows (4097^3: 135 against
+ * 124 TFLOP/s whole).  mgemm_default_config reports the whole product's
+ * configuration.
  */
 int mgemm_sgemm_ex(char transA, char transB, int64_t M, int64_t N, int64_t K,
                    float alpha, const float *A, int64_t lda,
@@ -219,7 +227,10 @@ int mgemm_default_config(int precision, char transA, char transB,
  * this exact (precision, trans pair, M, N, K), so later calls with
  * config = -1 use it.  A choice other than the built-in rule's is kept only
  * if it also beats that rule's choice by more than 2% in a head-to-head,
- * the two timed alternately three times.
+ * the two timed alternately three times.  For an FP32 product that the
+ * library's choice splits at its ragged edges (see mgemm_sgemm_ex), that
+ * split is the choice to beat; when it stays, nothing is recorded (any
+ * earlier choice for the shape is dropped) and *best_config is -1.
  * Arguments as for mgemm_sgemm_ex; C is overwritten (with beta != 0 it is
  * updated once per run), so tune on scratch output.  Synchronises `stream`.
  * *best_config and *best_ms (either may be NULL) receive the result.

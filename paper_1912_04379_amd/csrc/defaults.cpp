@@ -130,6 +130,30 @@ int f32_default_config(bool ta, bool tb, int64_t M, int64_t N, int64_t K) {
     return best;
 }
 
+// Ragged edges a little past a multiple of 256.  Measured NN on MI355X,
+// TFLOP/s, whole product (the rule's pick) against the whole-tile block plus
+// the two remainders (each on its own default: split-K for these thin
+// products): 4097^3 124.2 against 135.0, 4128^3 128.4 against 138.8,
+// 5121^3 116.2 against 127.6, 6145^3 130.1 against 138.5, 8193^3 132.0
+// against 140.7, 2049^2 x 16384 105.1 against 123.2, 8193 x 4097 x 2048
+// 128.1 against 134.2, 3073^2 x 8192 121.1 against 123.7.  The remainders
+// cost about a pass over A and B plus two launches, so smaller blocks lose
+// (4097^2 x 1024 -3.4%, 3073^3 -1.1%, 4100^2 x 512 -7.1%): the block must
+// hold at least 2^37 flops (about 0.9 ms).
+bool f32_edge_plan(bool ta, bool tb, int64_t M, int64_t N, int64_t K, int64_t* Mm,
+                   int64_t* Nm) {
+    (void)ta;
+    (void)tb;
+    const int64_t rm = M % 256, rn = N % 256;
+    if (rm > 64 || rn > 64 || (rm == 0 && rn == 0)) return false;
+    const int64_t mm = M - rm, nn = N - rn;
+    if (mm < 256 || nn < 256 || K < 1) return false;
+    if (2.0 * (double)mm * (double)nn * (double)K < 137438953472.0) return false;   // 2^37
+    *Mm = mm;
+    *Nm = nn;
+    return true;
+}
+
 // The split-K plan applies (at least two pieces) and its partial products
 // fit the workspace limit.
 static bool lowp_split_fits(int64_t M, int64_t N, int64_t K) {

@@ -228,6 +228,28 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
         e = launch_scale_c(d, s);
         return e == hipSuccess ? MGEMM_OK : hip_fail(e, "scale kernel launch");
     }
+    // The library's FP32 choice for a product a little past whole 256 x 256
+    // tiles (and no choice recorded for it): the whole-tile block and the
+    // thin remainders as separate products, each with its own default.
+    int64_t Mm = 0, Nm = 0;
+    if (precision == MGEMM_PREC_FP32 && config < 0 && act == MGEMM_ACT_NONE &&
+        recorded_choice(precision, ta, tb, M, N, K) < 0 && buffer_path_ok(d) &&
+        f32_edge_plan(ta, tb, M, N, K, &Mm, &Nm)) {
+        dp.path = "f32_edge_split";
+        dp.cfg = default_config(precision, ta, tb, Mm, Nm, K);
+        auto part = [&](int64_t m, int64_t n, const float* a, const float* b, float* c) {
+            Dispatch sub;
+            return sgemm_body(transA, transB, m, n, K, alpha, a, lda, b, ldb, beta, c, ldc, stream,
+                              precision, default_config(precision, ta, tb, m, n, K), fixed,
+                              MGEMM_ACT_NONE, nullptr, sub);
+        };
+        st = part(Mm, Nm, A, B, C);
+        if (!st && Mm < M)   // rows Mm..M-1 of C, every column
+            st = part(M - Mm, N, ta ? A + Mm * lda : A + Mm, B, C + Mm);
+        if (!st && Nm < N)   // columns Nm..N-1 of the first Mm rows
+            st = part(Mm, N - Nm, A, tb ? B + Nm : B + Nm * ldb, C + Nm * ldc);
+        return st;
+    }
     int cfg = config >= 0 ? config : default_config(precision, ta, tb, M, N, K);
     dp.cfg = cfg;
     dp.path = precision == MGEMM_PREC_FP32 ? "f32" : "in_staging";

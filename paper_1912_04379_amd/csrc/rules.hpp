@@ -43,6 +43,14 @@ constexpr int LOWP_SPLITK_CONFIG = LOWP_INSTAGE_CONFIGS + LOWP_PACKED_CONFIGS;
 
 // Built-in configuration of a single call (no recorded choice).
 int f32_default_config(bool transA, bool transB, int64_t M, int64_t N, int64_t K);
+// FP32 products whose M and N are each a multiple of 256 or at most 64 past
+// one, with at least one of them past: when the whole-tile block Mm x Nm
+// holds at least 2^37 flops, it runs on its own and the thin remainders
+// (rows Mm..M-1 of C, then columns Nm..N-1 of its first Mm rows) as separate
+// products.  Returns false, leaving Mm and Nm alone, when the product stays
+// whole.
+bool f32_edge_plan(bool transA, bool transB, int64_t M, int64_t N, int64_t K, int64_t* Mm,
+                   int64_t* Nm);
 int bf16x3_default_config(int64_t M, int64_t N, int64_t K);
 int f16s_default_config(int64_t M, int64_t N, int64_t K);
 

@@ -32,6 +32,11 @@ static void record(int precision, int ta, int tb, int64_t M, int64_t N, int64_t 
     g_choices[ChoiceKey{precision, ta, tb, M, N, K}] = cfg;
 }
 
+static void forget(int precision, int ta, int tb, int64_t M, int64_t N, int64_t K) {
+    std::lock_guard<std::mutex> lk(g_choice_mu);
+    g_choices.erase(ChoiceKey{precision, ta, tb, M, N, K});
+}
+
 void for_each_choice(
     const std::function<void(int, int, int, int64_t, int64_t, int64_t, int)>& fn) {
     std::lock_guard<std::mutex> lk(g_choice_mu);
@@ -134,6 +139,14 @@ int mgemm_tune_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, 
         best_ms_out = t_min;
         return r;
     };
+    // An FP32 product that the library splits at its ragged edges when no
+    // choice is recorded: the split is the default to beat (timed with no
+    // choice recorded for the shape).
+    const int ta0 = trans_code(transA), tb0 = trans_code(transB);
+    int64_t mm = 0, nn = 0;
+    const bool edge = precision == MGEMM_PREC_FP32 && f32_edge_plan(ta0 != 0, tb0 != 0, M, N, K,
+                                                                    &mm, &nn);
+    if (edge) forget(precision, ta0, tb0, M, N, K);
     int best = -1;
     float best_t = 0.0f;
     for (int cfg = 0; cfg < n && st == MGEMM_OK; ++cfg) {
@@ -147,9 +160,8 @@ int mgemm_tune_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, 
     // A choice other than the built-in default is recorded only if it also
     // beats the default by more than 2% in a head-to-head, the two timed
     // alternately three times: of near ties, the default stays.
-    const int ta0 = trans_code(transA), tb0 = trans_code(transB);
-    const int dflt = builtin_default_config(precision, ta0, tb0, M, N, K);
-    if (st == MGEMM_OK && best != dflt && dflt >= 0 && dflt < n) {
+    const int dflt = edge ? -1 : builtin_default_config(precision, ta0, tb0, M, N, K);
+    if (st == MGEMM_OK && best != dflt && dflt >= -1 && dflt < n) {
         float td = 1e30f, tb_ = 1e30f;
         for (int k = 0; k < 3 && st == MGEMM_OK; ++k) {
             float t = 0.0f;
@@ -171,7 +183,7 @@ int mgemm_tune_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, 
     (void)hipEventDestroy(e1);
     if (st) return st;
     const int ta = trans_code(transA), tb = trans_code(transB);
-    record(precision, ta, tb, M, N, K, best);
+    if (best >= 0) record(precision, ta, tb, M, N, K, best);   // -1: the edge split stays
     if (best_config) *best_config = best;
     if (best_ms) *best_ms = best_t;
     return MGEMM_OK;

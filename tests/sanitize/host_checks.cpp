@@ -9,6 +9,7 @@
 //   O ta tb M N K alpha A lda B ldb C ldc      -> 1 if C overlaps A or B
 //   D prec ta tb M N K                         -> built-in configuration
 //   S M N K cus                                -> small_tile splits kc
+//   E ta tb M N K                              -> 1 Mm Nm (edge split) or 0
 //   L G n cost_1 .. cost_n                     -> work-group of each item
 //   B nc na (lo hi owner) x (nc + na)          -> culprit kind
 #include <cstdio>
@@ -57,6 +58,15 @@ int main() {
                           : prec == 1 ? bf16x3_default_config(M, N, K)
                                       : f16s_default_config(M, N, K);
             std::printf("%d\n", c);
+        } else if (op == 'E') {
+            char ta, tb;
+            long long M, N, K;
+            in >> ta >> tb >> M >> N >> K;
+            int64_t mm = -1, nn = -1;
+            const bool split = f32_edge_plan(trans_code(ta) == 1, trans_code(tb) == 1, M, N, K,
+                                             &mm, &nn);
+            if (split) std::printf("1 %lld %lld\n", (long long)mm, (long long)nn);
+            else std::printf("0 %lld %lld\n", (long long)mm, (long long)nn);
         } else if (op == 'S') {
             long long M, N, K;
             int cus;

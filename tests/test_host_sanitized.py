@@ -183,6 +183,39 @@ def test_default_rules_match_the_library(bins):
         assert 0 <= want < L.mgemm_config_count(p)
 
 
+def test_edge_split_rule(bins):
+    """The FP32 edge split as documented: M and N each a multiple of 256 or
+    at most 64 past one (at least one past), a whole-tile block of at least
+    256 x 256 holding at least 2^37 flops; otherwise the product stays whole
+    and Mm, Nm are left alone."""
+    dims = [1, 255, 256, 257, 300, 320, 321, 1024, 1025, 2048, 2049, 4096, 4097, 4100, 4160,
+            4161, 6145, 8192, 8193, 8256, 8257]
+    rng = np.random.default_rng(5)
+    cases = [("N", "N", 4097, 4097, 4097), ("T", "T", 8193, 8193, 8193),
+             ("N", "T", 4096, 4096, 4096), ("N", "N", 4161, 4097, 4097),
+             ("N", "N", 4097, 4097, 1024)]
+    cases += [(str(rng.choice(list("NT"))), str(rng.choice(list("NT"))), int(rng.choice(dims)),
+               int(rng.choice(dims)), int(rng.choice([512, 4096, 4097, 8193])))
+              for _ in range(800)]
+    out = _host(bins, ["E %s %s %d %d %d" % c for c in cases])
+    split_seen = 0
+    for c, line in zip(cases, out):
+        ta, tb, M, N, K = c
+        flag, mm, nn = (int(x) for x in line.split())
+        rm, rn = M % 256, N % 256
+        want = (rm <= 64 and rn <= 64 and (rm or rn) and M - rm >= 256 and N - rn >= 256
+                and 2 * (M - rm) * (N - rn) * K >= 2 ** 37)
+        assert bool(flag) == bool(want), (c, line)
+        if flag:
+            split_seen += 1
+            assert (mm, nn) == (M - rm, N - rn), c
+        else:
+            assert (mm, nn) == (-1, -1), c
+    assert split_seen >= 20
+    assert out[0].split() == ["1", "4096", "4096"] and out[1].split() == ["1", "8192", "8192"]
+    assert out[2].split()[0] == "0" and out[3].split()[0] == "0" and out[4].split()[0] == "0"
+
+
 def test_split_k_plan_invariants(bins):
     rng = np.random.default_rng(2)
     cases = [(int(rng.integers(1, 9000)), int(rng.integers(1, 9000)),

@@ -37,6 +37,61 @@ def test_square_all_trans_sampled(ta, tb, n):
     sampled_check(c, run(c), count=1500)
 
 
+# Products a little past whole 256 x 256 tiles, run as the whole-tile block
+# and the thin remainders: both remainders, only the rows, only the columns.
+EDGE_CASES = [("N", "N", (4097, 4097, 4097)), ("T", "T", (4160, 4100, 4096)),
+              ("N", "T", (4096, 4127, 5000)), ("T", "N", (4129, 4096, 4097))]
+
+
+@pytest.mark.parametrize("ta,tb,shape", EDGE_CASES)
+def test_edge_split(ta, tb, shape, tmp_path, monkeypatch):
+    """The library's choice splits these products: every entry of the
+    remainders (rows M - M mod 256 .. M-1, columns N - N mod 256 .. N-1)
+    against the oracle, a sample of the block, C's padding untouched, and
+    the path taken."""
+    M, N, K = shape
+    logf = tmp_path / "mgemm.log"
+    monkeypatch.setenv("MGEMM_LOG", str(logf))
+    c = synth.sgemm_case(44, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=3)
+    log("f32 edge split %s %s%s" % (shape, ta, tb))
+    got = run(c)
+    assert "-> f32_edge_split " in logf.read_text()
+    sampled_check(c, got, count=600)
+    mm, nn = M - M % 256, N - N % 256
+    rows = np.concatenate([np.repeat(np.arange(mm, M), N),
+                           np.tile(np.arange(mm), N - nn)]).astype(np.int64)
+    cols = np.concatenate([np.tile(np.arange(N), M - mm),
+                           np.repeat(np.arange(nn, N), mm)]).astype(np.int64)
+    args = (ta, tb, M, N, K, float(c["alpha"]), c["A"], c["lda"], c["B"], c["ldb"],
+            float(c["beta"]), c["C"], c["ldc"])
+    ref = oracle.sgemm_entries(*args, rows, cols)
+    Cg = got.reshape(N, c["ldc"])
+    edge = Cg[cols, rows].astype(np.float64)
+    assert oracle.normwise_rel_err(edge, ref) <= 1e-5
+    finite_abs = lambda x: np.abs(np.where(np.isfinite(x), x, 0)).astype(np.float32)
+    absargs = (ta, tb, M, N, K, abs(float(c["alpha"])), finite_abs(c["A"]), c["lda"],
+               finite_abs(c["B"]), c["ldb"], abs(float(c["beta"])), finite_abs(c["C"]), c["ldc"])
+    scale = oracle.sgemm_entries(*absargs, rows, cols)
+    assert np.all(np.abs(edge - ref) <= oracle.gamma(K + 2, 2.0 ** -23) * scale)
+
+
+def test_edge_split_integers_bitwise():
+    """Small integers: every partial sum is exact, so an entry computed with
+    a wrong operand offset, twice or not at all would show."""
+    M, N, K = 4100, 4097, 4096
+    c = synth.sgemm_case(45, "T", "N", M, N, K, alpha=1.0, beta=1.0, dist="int16",
+                         dist_c="int16", pad=3)
+    log("f32 edge split integers")
+    got = logical_c(run(c), c)
+    rows, cols = synth.sample_entries(1, M, N, 4000)
+    mm, nn = M - M % 256, N - N % 256
+    rows = np.concatenate([rows, np.arange(mm, M), np.full(N - nn, mm - 1)]).astype(np.int64)
+    cols = np.concatenate([cols, np.full(M - mm, N - 1), np.arange(nn, N)]).astype(np.int64)
+    args = ("T", "N", M, N, K, 1.0, c["A"], c["lda"], c["B"], c["ldb"], 1.0, c["C"], c["ldc"])
+    ref = oracle.sgemm_entries(*args, rows, cols)
+    assert np.array_equal(got[rows, cols].astype(np.float64), ref)
+
+
 @pytest.mark.parametrize("ta,tb", TRANS)
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 37, 5), (37, 1, 5), (33, 65, 7),
                                    (127, 129, 1), (130, 3, 300), (5, 300, 17),
@@ -330,5 +385,35 @@ def test_tuner_records_a_valid_choice(prec):
         ref = oracle.sgemm(*(c[k] for k in ("transA", "transB", "M", "N", "K", "alpha", "A",
                                              "lda", "B", "ldb", "beta", "C", "ldc")))
         assert oracle.normwise_rel_err(logical_c(got, c), ref) <= tol
+    finally:
+        mg.clear_choices()
+
+
+def test_tuner_on_an_edge_split_shape(tmp_path, monkeypatch):
+    """4097^3: the library's own choice is the edge split, which the tuner
+    must beat by 2% before it records a whole-product configuration; when
+    the split stays, nothing is recorded (an earlier choice is dropped) and
+    calls keep splitting."""
+    import torch
+    n = 4097
+    c = synth.sgemm_case(13, "N", "N", n, n, n, alpha=1.0, beta=0.0, pad=3)
+    A, B = (torch.from_numpy(c[k]).cuda() for k in ("A", "B"))
+    scratch = torch.from_numpy(c["C"]).cuda()
+    logf = tmp_path / "mgemm.log"
+    try:
+        mg.record_choice("fp32", "N", "N", n, n, n, 3)        # dropped by the tuner
+        cfg, ms = mg.tune_sgemm("N", "N", n, n, n, 1.0, A, c["lda"], B, c["ldb"], 0.0,
+                                scratch, c["ldc"], reps=2)
+        log("tuner at 4097^3: config %d, %.3f ms" % (cfg, ms))
+        assert ms > 0 and -1 <= cfg < mg.config_count("fp32")
+        monkeypatch.setenv("MGEMM_LOG", str(logf))
+        got = run(c)
+        if cfg == -1:
+            assert mg.default_config("fp32", "N", "N", n, n, n) == 12   # nothing recorded
+            assert "-> f32_edge_split " in logf.read_text()
+        else:
+            assert mg.default_config("fp32", "N", "N", n, n, n) == cfg
+            assert "-> f32_edge_split " not in logf.read_text()
+        sampled_check(c, got, count=600)
     finally:
         mg.clear_choices()
