@@ -121,9 +121,13 @@ int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  * 64 past one (at least one past), with a whole-tile block Mm x Nm of at
  * least 2^37 flops, runs as three products on the same stream, each with
  * its own default configuration: the block, rows Mm..M-1 of C (all
- * columns), and columns Nm..N-1 of its first Mm rows (4097^3: 135 against
- * 124 TFLOP/s whole).  mgemm_default_config reports the whole product's
- * configuration.
+ * columns), and columns Nm..N-1 of its first Mm rows (4097^3: 136 against
+ * 124 TFLOP/s whole).  FP32 with config = -1 and no choice recorded: a
+ * product with at most 8 columns (or rows) of C, at least 256 rows (or
+ * columns) and K >= 256 streams the large operand once in k pieces whose
+ * partial sums (S*M*N*4 bytes of workspace from the pool) are added in a
+ * fixed order, as for split-K.  mgemm_default_config reports the
+ * configuration the product would otherwise take.
  */
 int mgemm_sgemm_ex(char transA, char transB, int64_t M, int64_t N, int64_t K,
                    float alpha, const float *A, int64_t lda,

@@ -237,18 +237,42 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
         f32_edge_plan(ta, tb, M, N, K, &Mm, &Nm)) {
         dp.path = "f32_edge_split";
         dp.cfg = default_config(precision, ta, tb, Mm, Nm, K);
-        auto part = [&](int64_t m, int64_t n, const float* a, const float* b, float* c) {
+        auto part = [&](int64_t m, int64_t n, const float* a, const float* b, float* c, int cf) {
             Dispatch sub;
             return sgemm_body(transA, transB, m, n, K, alpha, a, lda, b, ldb, beta, c, ldc, stream,
-                              precision, default_config(precision, ta, tb, m, n, K), fixed,
-                              MGEMM_ACT_NONE, nullptr, sub);
+                              precision, cf, fixed, MGEMM_ACT_NONE, nullptr, sub);
         };
-        st = part(Mm, Nm, A, B, C);
+        // The block on its own default; the remainders on the library's
+        // choice (the thin path for at most THIN_MAX_R rows or columns).
+        st = part(Mm, Nm, A, B, C, default_config(precision, ta, tb, Mm, Nm, K));
         if (!st && Mm < M)   // rows Mm..M-1 of C, every column
-            st = part(M - Mm, N, ta ? A + Mm * lda : A + Mm, B, C + Mm);
+            st = part(M - Mm, N, ta ? A + Mm * lda : A + Mm, B, C + Mm, -1);
         if (!st && Nm < N)   // columns Nm..N-1 of the first Mm rows
-            st = part(Mm, N - Nm, A, tb ? B + Nm : B + Nm * ldb, C + Nm * ldc);
+            st = part(Mm, N - Nm, A, tb ? B + Nm : B + Nm * ldb, C + Nm * ldc, -1);
         return st;
+    }
+    // The library's FP32 choice for a matrix-vector-like product (at most
+    // THIN_MAX_R columns or rows of C, no choice recorded for it): the thin
+    // path, which streams the large operand once.
+    if (precision == MGEMM_PREC_FP32 && config < 0 && act == MGEMM_ACT_NONE &&
+        recorded_choice(precision, ta, tb, M, N, K) < 0 && buffer_path_ok(d) && M <= MAX_BUF_LD) {
+        const ThinPlan tp = thin_plan(M, N, K, lda, ldb, ta, tb, device_cus(dev));
+        const int64_t bytes = thin_workspace_bytes(tp, M, N);
+        if (tp.ok && bytes <= (fixed ? fixed->cap : F32_SPLITK_MAX_WORKSPACE)) {
+            dp.path = "f32_thin";
+            dp.splits = tp.splits;
+            dp.ws_bytes = bytes;
+            char* ws = nullptr;
+            e = fault_injected() ? hipErrorOutOfMemory : take_workspace(dev, fixed, bytes, s, &ws);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(MGEMM_ERR_ALLOC, "stream-ordered thin-product workspace");
+            }
+            e = launch_thin(ta, tb, d, tp, reinterpret_cast<float*>(ws), s);
+            const hipError_t e2 = give_back_workspace(fixed, ws, s);
+            if (e == hipSuccess) e = e2;
+            return e == hipSuccess ? MGEMM_OK : hip_fail(e, "GEMM kernel launch");
+        }
     }
     int cfg = config >= 0 ? config : default_config(precision, ta, tb, M, N, K);
     dp.cfg = cfg;
