@@ -732,7 +732,10 @@ def bench_sweep(args, mg, torch, oracle, synth):
     import numpy as np
     stream = torch.cuda.current_stream()
     out = {"workload": "sgemm M=N=K in {1000,1024,2048,3001,4096,4097} x NN/NT/TN/TT, "
-                       "ld = rows + 16, alpha 1.5, beta -0.5, uniform[-1,1) seed 0"}
+                       "ld = rows + 16, alpha 1.5, beta -0.5, uniform[-1,1) seed 0",
+           "tile_config": "mgemm_default_config for the whole product; 4097 runs as its "
+                          "4096^2 whole-tile block (configuration 8) plus one-row and "
+                          "one-column remainders on the thin path"}
     steps, warmup = max(5, args.steps // 2), 3
     for n in (1000, 1024, 2048, 3001, 4096, 4097):
         c = synth.sgemm_case(0, "N", "N", n, n, n, alpha=1.5, beta=-0.5)
