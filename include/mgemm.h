@@ -124,7 +124,8 @@ int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  * columns), and columns Nm..N-1 of its first Mm rows (4097^3: 136 against
  * 124 TFLOP/s whole).  FP32 with config = -1 and no choice recorded: a
  * product with at most 8 columns (or rows) of C, at least 256 rows (or
- * columns) and K >= 256 streams the large operand once in k pieces whose
+ * columns), K >= 256 and leading dimensions (and M) below 2^21 - 64
+ * streams the large operand once in k pieces whose
  * partial sums (S*M*N*4 bytes of workspace from the pool) are added in a
  * fixed order, as for split-K.  mgemm_default_config reports the
  * configuration the product would otherwise take.
@@ -232,9 +233,10 @@ int mgemm_default_config(int precision, char transA, char transB,
  * config = -1 use it.  A choice other than the built-in rule's is kept only
  * if it also beats that rule's choice by more than 2% in a head-to-head,
  * the two timed alternately three times.  For an FP32 product that the
- * library's choice splits at its ragged edges (see mgemm_sgemm_ex), that
- * split is the choice to beat; when it stays, nothing is recorded (any
- * earlier choice for the shape is dropped) and *best_config is -1.
+ * library's choice splits at its ragged edges or runs on the thin path (see
+ * mgemm_sgemm_ex), that choice is the one to beat; when it stays, nothing is
+ * recorded (any earlier choice for the shape is dropped) and *best_config
+ * is -1.
  * Arguments as for mgemm_sgemm_ex; C is overwritten (with beta != 0 it is
  * updated once per run), so tune on scratch output.  Synchronises `stream`.
  * *best_config and *best_ms (either may be NULL) receive the result.

@@ -181,8 +181,9 @@ def tune_sgemm(transA, transB, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, *,
                precision="fp32", reps=3, stream=None):
     """Time every tile configuration for this product (C is overwritten) and
     record the fastest as the library's choice for it.  Returns
-    (config, milliseconds); config is -1 when the library's own split of an
-    FP32 product at its ragged edges stays the choice (nothing recorded)."""
+    (config, milliseconds); config is -1 when the library's own path for an
+    FP32 product (the split at its ragged edges, or the thin path for at most
+    8 rows or columns of C) stays the choice (nothing recorded)."""
     check_operands(transA, transB, M, N, K, alpha, A, lda, B, ldb, C, ldc)
     cfg = ctypes.c_int(-1)
     ms = ctypes.c_float(0.0)

@@ -240,4 +240,42 @@ int f16s_default_config(int64_t M, int64_t N, int64_t K) {
     return K >= 3072 && big > mid ? LOWP_INSTAGE_CONFIGS + 8 : LOWP_INSTAGE_CONFIGS + 7;
 }
 
+ThinPlan thin_plan(int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb, int64_t ldc,
+                   bool ta, bool tb, int cus) {
+    ThinPlan p{0, 0, 0, 0};
+    if (K < 256 || M < 1 || N < 1 || cus < 1) return p;
+    // The buffer path: leading dimensions, and the slices' ld M, within its
+    // limit.
+    if (lda > THIN_MAX_LD || ldb > THIN_MAX_LD || ldc > THIN_MAX_LD || M > THIN_MAX_LD) return p;
+    const bool cols = N <= THIN_MAX_R;   // few columns of C: the large operand is op(A)
+    const bool rows = !cols && M <= THIN_MAX_R;
+    if (!cols && !rows) return p;
+    const int64_t P = cols ? M : N;
+    if (P < 256) return p;
+    // 32-bit byte offsets from the bases of A and B as referenced.
+    const int64_t aext = ta ? K + (M - 1) * lda : M + (K - 1) * lda;
+    const int64_t bext = tb ? N + (K - 1) * ldb : K + (N - 1) * ldb;
+    if (4 * aext >= THIN_MAX_RANGE || 4 * bext >= THIN_MAX_RANGE) return p;
+    const bool kcontig = cols ? ta : !tb;
+    const int64_t per = kcontig ? THIN_ROWS_K : THIN_ROWS_I;
+    const int64_t blocks = (P + per - 1) / per;
+    // About eight work-groups per CU, so that the loads in flight cover the
+    // memory latency with short chains per work-group; pieces a multiple of
+    // 64 k, at most 64 of them.
+    int64_t S = (8 * (int64_t)cus + blocks - 1) / blocks;
+    if (S > 64) S = 64;
+    int64_t kc = (K + S - 1) / S;
+    kc = (kc + 63) / 64 * 64;
+    S = (K + kc - 1) / kc;
+    p.splits = (int)S;
+    p.kc = kc;
+    p.rows = rows ? 1 : 0;
+    p.ok = 1;
+    return p;
+}
+
+int64_t thin_workspace_bytes(const ThinPlan& p, int64_t M, int64_t N) {
+    return p.ok ? (int64_t)p.splits * M * N * 4 : 0;
+}
+
 }  // namespace mgemm

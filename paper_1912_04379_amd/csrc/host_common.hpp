@@ -43,6 +43,9 @@ int64_t batch_alias(std::vector<Extent> cs, const std::vector<Extent>& ab, int* 
 // MGEMM_OK when the current device is a gfx950; otherwise an error status.
 int check_device(int* out_dev);
 
+// Compute units of device dev (cached; 0 if unknown).
+int device_cus(int dev);
+
 // Number of tile configurations of a precision.
 int config_count(int precision);
 

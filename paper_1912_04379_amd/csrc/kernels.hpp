@@ -51,20 +51,9 @@ hipError_t launch_f16_exponents(bool transA, bool transB, const GemmDesc& d,
                                 int* expA, int* expB, float* partial, hipStream_t stream);
 hipError_t launch_f16s(int cfg, bool transA, bool transB, const GemmDesc& d,
                        hipStream_t stream);
-// FP32 products with at most THIN_MAX_R columns (or rows) of C, P >= 256 on
-// the other side and K >= 256: the large operand streamed once in S pieces
-// of kc along k into S*M*N floats of workspace, then launch_splitk_reduce
-// (the library's choice for such products; see sgemm_thin.hip).
-constexpr int THIN_MAX_R = 8;
-struct ThinPlan {
-    int ok;       // the thin path applies
-    int rows;     // few rows of C (the product taken through its transpose)
-    int splits;   // S
-    int64_t kc;   // k per piece, a multiple of 64
-};
-ThinPlan thin_plan(int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb, bool transA,
-                   bool transB, int cus);
-int64_t thin_workspace_bytes(const ThinPlan& p, int64_t M, int64_t N);
+// The thin path (plan in rules.hpp): the large operand streamed once in S
+// pieces of kc along k into S*M*N floats of workspace, then
+// launch_splitk_reduce (see sgemm_thin.hip).
 hipError_t launch_thin(bool transA, bool transB, const GemmDesc& d, const ThinPlan& p,
                        float* workspace, hipStream_t stream);
 

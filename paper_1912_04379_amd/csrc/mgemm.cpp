@@ -76,10 +76,9 @@ int check_device(int* out_dev) {
 // so the next call would map it again: up to a few tenths of a millisecond
 // for the hundreds of megabytes that packed 8192^3 operands take.)
 // ---------------------------------------------------------------------------
-// Compute units of a device (cached; 0 if unknown).
 static std::atomic<int> g_cus[64];
 
-static int device_cus(int dev) {
+int device_cus(int dev) {
     if (dev < 0 || dev >= 64) return 0;
     int n = g_cus[dev].load(std::memory_order_relaxed);
     if (n > 0) return n;
@@ -255,8 +254,8 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
     // THIN_MAX_R columns or rows of C, no choice recorded for it): the thin
     // path, which streams the large operand once.
     if (precision == MGEMM_PREC_FP32 && config < 0 && act == MGEMM_ACT_NONE &&
-        recorded_choice(precision, ta, tb, M, N, K) < 0 && buffer_path_ok(d) && M <= MAX_BUF_LD) {
-        const ThinPlan tp = thin_plan(M, N, K, lda, ldb, ta, tb, device_cus(dev));
+        recorded_choice(precision, ta, tb, M, N, K) < 0) {
+        const ThinPlan tp = thin_plan(M, N, K, lda, ldb, ldc, ta, tb, device_cus(dev));
         const int64_t bytes = thin_workspace_bytes(tp, M, N);
         if (tp.ok && bytes <= (fixed ? fixed->cap : F32_SPLITK_MAX_WORKSPACE)) {
             dp.path = "f32_thin";

@@ -51,6 +51,27 @@ int f32_default_config(bool transA, bool transB, int64_t M, int64_t N, int64_t K
 // whole.
 bool f32_edge_plan(bool transA, bool transB, int64_t M, int64_t N, int64_t K, int64_t* Mm,
                    int64_t* Nm);
+// FP32 products with at most THIN_MAX_R columns of C (or rows: then taken
+// through the transpose), at least 256 of the other and K >= 256, whose
+// operands stay within 32-bit buffer offsets (leading dimensions, M and the
+// referenced extents): the library's choice is the thin path, the large
+// operand P x K streamed once in S pieces of kc along k (about eight
+// work-groups of THIN_ROWS_I or THIN_ROWS_K rows per CU) into S*M*N floats
+// of workspace, then the split-K reduction.
+constexpr int THIN_MAX_R = 8;
+constexpr int THIN_ROWS_I = 64;   // rows per work-group, row-contiguous large operand
+constexpr int THIN_ROWS_K = 16;   // rows per work-group, k-contiguous large operand
+constexpr int64_t THIN_MAX_LD = (1LL << 21) - 64;       // the buffer path's ld limit
+constexpr int64_t THIN_MAX_RANGE = 0x7ffffff0LL;         // bytes one buffer resource spans
+struct ThinPlan {
+    int ok;       // the thin path applies
+    int rows;     // few rows of C (the product taken through its transpose)
+    int splits;   // S
+    int64_t kc;   // k per piece, a multiple of 64
+};
+ThinPlan thin_plan(int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb, int64_t ldc,
+                   bool transA, bool transB, int cus);
+int64_t thin_workspace_bytes(const ThinPlan& p, int64_t M, int64_t N);
 int bf16x3_default_config(int64_t M, int64_t N, int64_t K);
 int f16s_default_config(int64_t M, int64_t N, int64_t K);
 

@@ -25,8 +25,9 @@ struct ThinArgs {
     int64_t xbytes, ybytes;   // bytes referenced from X and from Y
 };
 
-constexpr int THIN_ROWS_I = 64;   // rows per work-group, i-contiguous X
-constexpr int THIN_ROWS_K = 16;   // rows per work-group, k-contiguous X
+// The plan's limits are the buffer path's.
+static_assert(THIN_MAX_LD == MAX_BUF_LD && THIN_MAX_RANGE == BUF_MAX_RANGE,
+              "thin plan limits");
 constexpr int THIN_UNROLL = 4;
 
 // i-contiguous X: a lane loads 4 consecutive rows (16 bytes); 16 lanes cover
@@ -167,43 +168,6 @@ static void launch_thin_r(bool kcontig, const ThinArgs& t, int64_t S, hipStream_
         const dim3 grid((uint32_t)((t.P + THIN_ROWS_I - 1) / THIN_ROWS_I), (uint32_t)S);
         hipLaunchKernelGGL(thin_icontig_kernel<R>, grid, dim3(256), 0, s, t);
     }
-}
-
-ThinPlan thin_plan(int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb, bool ta, bool tb,
-                   int cus) {
-    ThinPlan p{0, 0, 0, 0};
-    if (K < 256 || M < 1 || N < 1) return p;
-    const bool cols = N <= THIN_MAX_R;   // few columns of C: X = op(A)
-    const bool rows = !cols && M <= THIN_MAX_R;
-    if (!cols && !rows) return p;
-    const int64_t P = cols ? M : N;
-    if (P < 256) return p;
-    // 32-bit element offsets from the bases: X and Y as referenced.
-    const int64_t xext = cols ? (ta ? K + (M - 1) * lda : M + (K - 1) * lda)
-                              : (tb ? N + (K - 1) * ldb : K + (N - 1) * ldb);
-    const int64_t yext = cols ? (tb ? N + (K - 1) * ldb : K + (N - 1) * ldb)
-                              : (ta ? K + (M - 1) * lda : M + (K - 1) * lda);
-    if (4 * xext >= BUF_MAX_RANGE || 4 * yext >= BUF_MAX_RANGE) return p;
-    const bool kcontig = cols ? ta : !tb;
-    const int64_t blocks = (P + (kcontig ? THIN_ROWS_K : THIN_ROWS_I) - 1) /
-                           (kcontig ? THIN_ROWS_K : THIN_ROWS_I);
-    // About eight work-groups per CU, so that the loads in flight cover the
-    // memory latency with short chains per work-group; pieces a multiple of
-    // 64 k.
-    int64_t S = (8 * (int64_t)cus + blocks - 1) / blocks;
-    if (S > 64) S = 64;
-    int64_t kc = (K + S - 1) / S;
-    kc = (kc + 63) / 64 * 64;
-    S = (K + kc - 1) / kc;
-    p.splits = (int)S;
-    p.kc = kc;
-    p.rows = rows ? 1 : 0;
-    p.ok = 1;
-    return p;
-}
-
-int64_t thin_workspace_bytes(const ThinPlan& p, int64_t M, int64_t N) {
-    return p.ok ? (int64_t)p.splits * M * N * 4 : 0;
 }
 
 hipError_t launch_thin(bool ta, bool tb, const GemmDesc& d, const ThinPlan& p, float* ws,

@@ -94,7 +94,8 @@ int mgemm_tune_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, 
     const int n = config_count(precision);
     if (n == 0) return fail(MGEMM_ERR_UNSUPPORTED, "unknown precision");
     if (reps < 1) reps = 1;
-    int st = check_device(nullptr);
+    int dev = 0;
+    int st = check_device(&dev);
     if (st) return st;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -139,14 +140,18 @@ int mgemm_tune_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, 
         best_ms_out = t_min;
         return r;
     };
-    // An FP32 product that the library splits at its ragged edges when no
-    // choice is recorded: the split is the default to beat (timed with no
-    // choice recorded for the shape).
+    // An FP32 product that the library, when no choice is recorded, splits
+    // at its ragged edges or runs on the thin path: that choice is the
+    // default to beat (timed with no choice recorded for the shape).
     const int ta0 = trans_code(transA), tb0 = trans_code(transB);
     int64_t mm = 0, nn = 0;
-    const bool edge = precision == MGEMM_PREC_FP32 && f32_edge_plan(ta0 != 0, tb0 != 0, M, N, K,
-                                                                    &mm, &nn);
-    if (edge) forget(precision, ta0, tb0, M, N, K);
+    bool own = false;
+    if (precision == MGEMM_PREC_FP32) {
+        const ThinPlan tp = thin_plan(M, N, K, lda, ldb, ldc, ta0 != 0, tb0 != 0, device_cus(dev));
+        own = f32_edge_plan(ta0 != 0, tb0 != 0, M, N, K, &mm, &nn) ||
+              (tp.ok && thin_workspace_bytes(tp, M, N) <= F32_SPLITK_MAX_WORKSPACE);
+    }
+    if (own) forget(precision, ta0, tb0, M, N, K);
     int best = -1;
     float best_t = 0.0f;
     for (int cfg = 0; cfg < n && st == MGEMM_OK; ++cfg) {
@@ -160,7 +165,7 @@ int mgemm_tune_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, 
     // A choice other than the built-in default is recorded only if it also
     // beats the default by more than 2% in a head-to-head, the two timed
     // alternately three times: of near ties, the default stays.
-    const int dflt = edge ? -1 : builtin_default_config(precision, ta0, tb0, M, N, K);
+    const int dflt = own ? -1 : builtin_default_config(precision, ta0, tb0, M, N, K);
     if (st == MGEMM_OK && best != dflt && dflt >= -1 && dflt < n) {
         float td = 1e30f, tb_ = 1e30f;
         for (int k = 0; k < 3 && st == MGEMM_OK; ++k) {
@@ -183,7 +188,7 @@ int mgemm_tune_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, 
     (void)hipEventDestroy(e1);
     if (st) return st;
     const int ta = trans_code(transA), tb = trans_code(transB);
-    if (best >= 0) record(precision, ta, tb, M, N, K, best);   // -1: the edge split stays
+    if (best >= 0) record(precision, ta, tb, M, N, K, best);   // -1: the library's own path stays
     if (best_config) *best_config = best;
     if (best_ms) *best_ms = best_t;
     return MGEMM_OK;

@@ -1,6 +1,7 @@
 // host_checks.cpp -- drives the library's host-only decision code (argument
 // validation, operand overlap, default tile rules, the split-K plan, the
-// grouped list schedule and batch aliasing) from commands on stdin, one
+// edge split, the thin-product plan, the grouped list schedule and batch
+// aliasing) from commands on stdin, one
 // result line per command.  Built with AddressSanitizer and
 // UndefinedBehaviorSanitizer by tests/test_host_sanitized.py, which checks
 // the results against the library itself and against brute force.
@@ -10,6 +11,7 @@
 //   D prec ta tb M N K                         -> built-in configuration
 //   S M N K cus                                -> small_tile splits kc
 //   E ta tb M N K                              -> 1 Mm Nm (edge split) or 0
+//   T ta tb M N K lda ldb ldc cus              -> ok rows splits kc bytes (thin path)
 //   L G n cost_1 .. cost_n                     -> work-group of each item
 //   B nc na (lo hi owner) x (nc + na)          -> culprit kind
 #include <cstdio>
@@ -67,6 +69,15 @@ int main() {
                                              &mm, &nn);
             if (split) std::printf("1 %lld %lld\n", (long long)mm, (long long)nn);
             else std::printf("0 %lld %lld\n", (long long)mm, (long long)nn);
+        } else if (op == 'T') {
+            char ta, tb;
+            long long M, N, K, lda, ldb, ldc;
+            int cus;
+            in >> ta >> tb >> M >> N >> K >> lda >> ldb >> ldc >> cus;
+            const ThinPlan p = thin_plan(M, N, K, lda, ldb, ldc, trans_code(ta) == 1,
+                                         trans_code(tb) == 1, cus);
+            std::printf("%d %d %d %lld %lld\n", p.ok, p.rows, p.splits, (long long)p.kc,
+                        (long long)thin_workspace_bytes(p, M, N));
         } else if (op == 'S') {
             long long M, N, K;
             int cus;

@@ -388,3 +388,64 @@ def test_oracle_under_sanitizers_matches_the_ordinary_build(bins, case):
             c["B"].astype(np.float64), c["ldb"], float(np.float32(beta)),
             c["C"].astype(np.float64), c["ldc"])
     assert np.array_equal(dfull, oracle.dgemm(*wide), equal_nan=True)
+
+
+def test_thin_plan_rule(bins):
+    """The thin-product plan as documented: at most 8 columns of C (else at
+    most 8 rows, through the transpose), at least 256 on the other side,
+    K >= 256, leading dimensions and M within the buffer path's limit and
+    the referenced extents of A and B below 2^31 bytes; the k pieces are
+    multiples of 64, at most 64 of them, every one non-empty, for about
+    eight work-groups per CU; the workspace holds S partial products."""
+    lim, rng_bytes = (1 << 21) - 64, 0x7ffffff0
+    rng = np.random.default_rng(7)
+    cases = [("N", "N", 8192, 1, 8193, 8192, 8193, 8192, 256),
+             ("N", "N", 1, 8193, 8193, 1, 8193, 1, 256),
+             ("T", "T", 4096, 8, 4097, 4097, 8, 4096, 256),
+             ("N", "N", 4096, 9, 4097, 4096, 4097, 4096, 256),
+             ("N", "N", 255, 1, 4096, 255, 4096, 255, 256),
+             ("N", "N", 4096, 1, 255, 4096, 255, 4096, 256),
+             ("N", "N", 4096, 1, 4096, lim + 1, 4096, 4096, 256),
+             ("N", "N", 4096, 1, 4096, 4096, 4096, lim + 1, 256),
+             ("T", "N", 300000, 2, 2000, 2000, 2000, 300000, 256),
+             ("N", "N", 4096, 1, 4096, 4096, 4096, 4096, 0)]
+    dims = [1, 2, 3, 5, 8, 9, 16, 255, 256, 257, 1000, 4097, 8193]
+    for _ in range(1500):
+        ta, tb = str(rng.choice(list("NT"))), str(rng.choice(list("NT")))
+        M, N = int(rng.choice(dims)), int(rng.choice(dims))
+        K = int(rng.choice([64, 255, 256, 300, 4097, 65536, 1 << 20]))
+        lda = (K if ta == "T" else M) + int(rng.choice([0, 3, 64]))
+        ldb = (N if tb == "T" else K) + int(rng.choice([0, 5]))
+        cases.append((ta, tb, M, N, K, lda, ldb, M + int(rng.choice([0, 7])),
+                      int(rng.choice([1, 80, 256]))))
+    out = _host(bins, ["T %s %s %d %d %d %d %d %d %d" % c for c in cases])
+    seen = {0: 0, 1: 0}
+    for c, line in zip(cases, out):
+        ta, tb, M, N, K, lda, ldb, ldc, cus = c
+        ok, rows, S, kc, nbytes = (int(x) for x in line.split())
+        cols = N <= 8
+        few_rows = not cols and M <= 8
+        P = M if cols else N
+        aext = K + (M - 1) * lda if ta == "T" else M + (K - 1) * lda
+        bext = N + (K - 1) * ldb if tb == "T" else K + (N - 1) * ldb
+        want = ((cols or few_rows) and P >= 256 and K >= 256 and cus >= 1
+                and max(lda, ldb, ldc, M) <= lim and 4 * aext < rng_bytes and 4 * bext < rng_bytes)
+        assert bool(ok) == want, (c, line)
+        if not ok:
+            assert (rows, S, kc, nbytes) == (0, 0, 0, 0), (c, line)
+            continue
+        seen[rows] += 1
+        assert rows == int(few_rows), c
+        assert kc % 64 == 0 and 1 <= S <= 64, (c, line)
+        assert (S - 1) * kc < K <= S * kc, (c, line)        # every piece non-empty
+        assert nbytes == 4 * S * M * N, (c, line)
+        kcontig = (ta == "T") if cols else (tb == "N")
+        blocks = -(-P // (16 if kcontig else 64))
+        target = min(64, -(-8 * cus // blocks))
+        assert S <= target, (c, line)                      # at most the target pieces
+        assert S == -(-K // kc) and kc == -(-(-(-K // target)) // 64) * 64, (c, line)
+    assert seen[0] >= 30 and seen[1] >= 30, seen
+    assert out[0].split()[:2] == ["1", "0"] and out[1].split()[:2] == ["1", "1"]
+    assert out[2].split()[0] == "1"
+    for line in out[3:10]:
+        assert line.split()[0] == "0", line

@@ -60,3 +60,29 @@ def test_thin_is_deterministic():
     a = run(c)
     b = run(c)
     assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+
+
+def test_thin_tuner_keeps_the_library_path(tmp_path, monkeypatch):
+    """8192 x 1 x 8193: the thin path is the library's choice and the one
+    the tuner must beat by 2% before it records a configuration; no tile
+    configuration does (they compute at least 64 columns), so nothing is
+    recorded (an earlier choice is dropped) and calls stay on the thin path."""
+    import paper_1912_04379_amd as mg
+    import torch
+    M, N, K = 8192, 1, 8193
+    c = synth.sgemm_case(64, "N", "N", M, N, K, alpha=1.0, beta=0.0, pad=3)
+    A, B = (torch.from_numpy(c[k]).cuda() for k in ("A", "B"))
+    scratch = torch.from_numpy(c["C"]).cuda()
+    logf = tmp_path / "mgemm.log"
+    try:
+        mg.record_choice("fp32", "N", "N", M, N, K, 3)        # dropped by the tuner
+        cfg, ms = mg.tune_sgemm("N", "N", M, N, K, 1.0, A, c["lda"], B, c["ldb"], 0.0,
+                                scratch, c["ldc"], reps=2)
+        log("tuner at 8192x1x8193: config %d, %.4f ms" % (cfg, ms))
+        assert cfg == -1 and ms > 0
+        monkeypatch.setenv("MGEMM_LOG", str(logf))
+        full_check(c, run(c))
+        assert "-> f32_thin " in logf.read_text()
+    finally:
+        mg.clear_choices()
+

@@ -48,6 +48,8 @@ def _log_lines(path):
 PAIRS = [
     # FP32 split-K: S partial products in the scratch array.
     ("fp32", (512, 512, 16384, "T", "N"), (200, 136, 5000, "N", "T"), "f32_split_k"),
+    # FP32 thin products (the library's choice): k-piece partial sums.
+    ("fp32", (8192, 3, 8193, "N", "N"), (1000, 1, 700, "T", "T"), "f32_thin"),
     # Scaled FP16: panel exponents and partial maxima, plus packed operands
     # (2048^3: 16 MiB) on the first call.
     ("fp16s", (2048, 2048, 2048, "N", "N"), (300, 260, 700, "T", "N"), "packed"),
@@ -56,11 +58,11 @@ PAIRS = [
 ]
 
 
-@pytest.mark.parametrize("prec,first,second,path", PAIRS, ids=[p[0] for p in PAIRS])
+@pytest.mark.parametrize("prec,first,second,path", PAIRS, ids=["%s-%s" % (p[0], p[3]) for p in PAIRS])
 def test_noalloc_equals_sgemm_ex_twice(prec, first, second, path, tmp_path, monkeypatch):
     logf = tmp_path / "mgemm.log"
     monkeypatch.setenv("MGEMM_LOG", str(logf))
-    cfg = 11 if prec == "fp32" else -1
+    cfg = 11 if path == "f32_split_k" else -1
     for i, (M, N, K, ta, tb) in enumerate((first, second)):
         log("noalloc %s call %d: %s%s %dx%dx%d config %d" % (prec, i + 1, ta, tb, M, N, K, cfg))
         c = synth.sgemm_case(20 + i, ta, tb, M, N, K, alpha=1.5, beta=-0.5, pad=3)
