@@ -199,6 +199,7 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-mlp", action="store_true")
     ap.add_argument("--no-splitk", action="store_true")
+    ap.add_argument("--no-thin", action="store_true")
     ap.add_argument("--no-prepacked", action="store_true")
     ap.add_argument("--grouped-defaults", action="store_true",
                     help="replay the library's default grouped plans instead of tuned ones "
@@ -378,6 +379,8 @@ def main():
         line["mlp_training"] = bench_mlp(args, mg, torch)
     if not args.no_splitk:
         line["split_k"] = bench_splitk(args, mg, torch)
+    if not args.no_thin:
+        line["thin"] = bench_thin(args, mg, torch, oracle, synth)
     if not (args.no_prepacked or args.no_forms):
         line["prepacked_b"] = bench_prepacked(args, mg, torch, n)
     if not args.no_sweep:
@@ -718,6 +721,47 @@ def bench_splitk(args, mg, torch):
              res["bf16x3"]["speedup"], res["fp16s"]["default"]["tflops"],
              res["fp16s"]["speedup"]))
         del A, B, C
+    return out
+
+
+def bench_thin(args, mg, torch, oracle, synth):
+    """FP32 products with at most 8 columns (or rows) of C (ld = rows + 16,
+    alpha 1.5, beta -0.5, uniform inputs): the library's choice (the thin
+    path) against split-K (configuration 11, the choice before it); rate in
+    algorithmic bytes (op(A), op(B) read once, C read and written once) and
+    the normwise error of the whole product against the oracle."""
+    import numpy as np
+    stream = torch.cuda.current_stream()
+    out = {"workload": "FP32, ld = rows + 16, alpha 1.5, beta -0.5, uniform[-1,1) seed 0; "
+                       "bytes = 4 (MK + KN + 2MN)"}
+    for (M, N, K, ta, tb) in ((8192, 1, 8193, "N", "N"), (8192, 8, 8193, "N", "N"),
+                              (8192, 1, 8193, "T", "N"), (1, 8193, 8193, "N", "N"),
+                              (4096, 1, 4097, "N", "N")):
+        c = synth.sgemm_case(0, ta, tb, M, N, K, alpha=1.5, beta=-0.5)
+        A, B, C0 = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))
+        C = C0.clone()
+        nbytes = 4.0 * (M * K + K * N + 2 * M * N)
+        res = {}
+        for name, cfg in (("thin", -1), ("split_k_config_11", 11)):
+            fn = lambda: mg.sgemm(ta, tb, M, N, K, 1.5, A, c["lda"], B, c["ldb"], -0.5, C,
+                                  c["ldc"], config=cfg)
+            C.copy_(C0)
+            fn()
+            torch.cuda.synchronize()
+            ref = oracle.sgemm(ta, tb, M, N, K, 1.5, c["A"], c["lda"], c["B"], c["ldb"], -0.5,
+                               c["C"], c["ldc"])
+            flat, ldc = C.cpu().numpy(), c["ldc"]
+            got = np.stack([flat[j * ldc:j * ldc + M] for j in range(N)], axis=1)
+            err = oracle.normwise_rel_err(got.astype(np.float64), ref)
+            ms = timed(fn, max(10, args.steps), 3, stream, min_ms=50)
+            res[name] = {"us": round(ms * 1e3, 2), "gbs": round(nbytes / ms / 1e6, 1),
+                         "normwise_err": float("%.3e" % err)}
+        res["speedup"] = round(res["split_k_config_11"]["us"] / res["thin"]["us"], 3)
+        key = "%s%s %dx%dx%d" % (ta, tb, M, N, K)
+        out[key] = res
+        log("thin %s: %.1f us (%.0f GB/s), split-K %.1f us" %
+            (key, res["thin"]["us"], res["thin"]["gbs"], res["split_k_config_11"]["us"]))
+        del A, B, C0, C
     return out
 
 
