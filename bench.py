@@ -735,7 +735,8 @@ def bench_thin(args, mg, torch, oracle, synth):
     out = {"workload": "FP32, ld = rows + 16, alpha 1.5, beta -0.5, uniform[-1,1) seed 0; "
                        "bytes = 4 (MK + KN + 2MN)"}
     for (M, N, K, ta, tb) in ((8192, 1, 8193, "N", "N"), (8192, 8, 8193, "N", "N"),
-                              (8192, 1, 8193, "T", "N"), (1, 8193, 8193, "N", "N"),
+                              (8192, 1, 8193, "T", "N"), (8192, 1, 8193, "T", "T"),
+                              (1, 8193, 8193, "N", "N"),
                               (4096, 1, 4097, "N", "N")):
         c = synth.sgemm_case(0, ta, tb, M, N, K, alpha=1.5, beta=-0.5)
         A, B, C0 = (torch.from_numpy(c[k]).cuda() for k in ("A", "B", "C"))

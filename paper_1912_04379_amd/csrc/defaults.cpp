@@ -242,7 +242,7 @@ int f16s_default_config(int64_t M, int64_t N, int64_t K) {
 
 ThinPlan thin_plan(int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb, int64_t ldc,
                    bool ta, bool tb, int cus) {
-    ThinPlan p{0, 0, 0, 0};
+    ThinPlan p{0, 0, 0, 0, 0};
     if (K < 256 || M < 1 || N < 1 || cus < 1) return p;
     // The buffer path: leading dimensions, and the slices' ld M, within its
     // limit.
@@ -270,12 +270,16 @@ ThinPlan thin_plan(int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb, in
     p.splits = (int)S;
     p.kc = kc;
     p.rows = rows ? 1 : 0;
+    const bool strided = cols ? (tb && ldb != 1) : (!ta && lda != 1);
+    p.gather = strided && kcontig && P * K >= THIN_GATHER_MIN ? 1 : 0;
     p.ok = 1;
     return p;
 }
 
-int64_t thin_workspace_bytes(const ThinPlan& p, int64_t M, int64_t N) {
-    return p.ok ? (int64_t)p.splits * M * N * 4 : 0;
+int64_t thin_workspace_bytes(const ThinPlan& p, int64_t M, int64_t N, int64_t K) {
+    if (!p.ok) return 0;
+    const int64_t r = p.rows ? M : N;
+    return 4 * ((int64_t)p.splits * M * N + (p.gather ? K * r : 0));
 }
 
 }  // namespace mgemm

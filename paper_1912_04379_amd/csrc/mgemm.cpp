@@ -256,7 +256,7 @@ static int sgemm_body(char transA, char transB, int64_t M, int64_t N, int64_t K,
     if (precision == MGEMM_PREC_FP32 && config < 0 && act == MGEMM_ACT_NONE &&
         recorded_choice(precision, ta, tb, M, N, K) < 0) {
         const ThinPlan tp = thin_plan(M, N, K, lda, ldb, ldc, ta, tb, device_cus(dev));
-        const int64_t bytes = thin_workspace_bytes(tp, M, N);
+        const int64_t bytes = thin_workspace_bytes(tp, M, N, K);
         if (tp.ok && bytes <= (fixed ? fixed->cap : F32_SPLITK_MAX_WORKSPACE)) {
             dp.path = "f32_thin";
             dp.splits = tp.splits;

@@ -63,15 +63,24 @@ constexpr int THIN_ROWS_I = 64;   // rows per work-group, row-contiguous large o
 constexpr int THIN_ROWS_K = 16;   // rows per work-group, k-contiguous large operand
 constexpr int64_t THIN_MAX_LD = (1LL << 21) - 64;       // the buffer path's ld limit
 constexpr int64_t THIN_MAX_RANGE = 0x7ffffff0LL;         // bytes one buffer resource spans
+// With a k-contiguous large operand, a small operand whose k elements are
+// not adjacent in memory (op(B) with transB, or op(A)^T without transA) is
+// first gathered into K*r floats in k-major order after the partial sums,
+// when the large operand holds at least THIN_GATHER_MIN elements: the
+// streaming kernel's lanes would otherwise touch a cache line per k.  (The
+// row-contiguous kernel reads few k at a time and gains nothing from it.)
+constexpr int64_t THIN_GATHER_MIN = 1LL << 25;
 struct ThinPlan {
     int ok;       // the thin path applies
     int rows;     // few rows of C (the product taken through its transpose)
     int splits;   // S
     int64_t kc;   // k per piece, a multiple of 64
+    int gather;   // the small operand is gathered first
 };
 ThinPlan thin_plan(int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb, int64_t ldc,
                    bool transA, bool transB, int cus);
-int64_t thin_workspace_bytes(const ThinPlan& p, int64_t M, int64_t N);
+// S*M*N partial sums, then the gathered small operand (K*r) if any.
+int64_t thin_workspace_bytes(const ThinPlan& p, int64_t M, int64_t N, int64_t K);
 int bf16x3_default_config(int64_t M, int64_t N, int64_t K);
 int f16s_default_config(int64_t M, int64_t N, int64_t K);
 

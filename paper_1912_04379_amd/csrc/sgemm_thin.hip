@@ -23,6 +23,10 @@ struct ThinArgs {
     float* ws;
     int64_t P, K, xld, yks, yjs, wis, wjs, kc;
     int64_t xbytes, ybytes;   // bytes referenced from X and from Y
+    // How the k-contiguous kernel reads 4 consecutive k of Y: 0 one element
+    // at a time, 1 16 bytes per column (yks == 1), 2 16 bytes at a time
+    // over the 4r adjacent elements (yks == r, yjs == 1).
+    int ymode;
 };
 
 // The plan's limits are the buffer path's.
@@ -131,12 +135,29 @@ __global__ __launch_bounds__(256) void thin_kcontig_kernel(ThinArgs t) {
                                                       : BUF_OOB);
                 }
             }
+            if (k + 3 < k1 && t.ymode == 1) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+                for (int j = 0; j < R; ++j) {
+                    const f32x4 v = buf_load_f32x4(ry, (uint32_t)(4 * (k + j * t.yjs)));
 #pragma unroll
-                for (int j = 0; j < R; ++j)
-                    y[u][e][j] = buf_load_f32(
-                        ry, k + e < k1 ? (uint32_t)(4 * ((k + e) * t.yks + j * t.yjs)) : BUF_OOB);
+                    for (int e = 0; e < 4; ++e) y[u][e][j] = v[e];
+                }
+            } else if (k + 3 < k1 && t.ymode == 2) {
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const f32x4 v = buf_load_f32x4(ry, (uint32_t)(4 * (k * R + 4 * q)));
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) y[u][(4 * q + c) / R][(4 * q + c) % R] = v[c];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+#pragma unroll
+                    for (int j = 0; j < R; ++j)
+                        y[u][e][j] = buf_load_f32(
+                            ry, k + e < k1 ? (uint32_t)(4 * ((k + e) * t.yks + j * t.yjs))
+                                           : BUF_OOB);
+            }
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -157,6 +178,17 @@ __global__ __launch_bounds__(256) void thin_kcontig_kernel(ThinArgs t) {
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
             if (lane == 0 && live[q]) t.ws[s * t.P * R + (i0 + q) * t.wis + j * t.wjs] = v;
         }
+}
+
+// Yc[k*r + j] = Y[k*yks + j*yjs] for k < K, j < r: the small operand in
+// k-major order, so that the streaming kernels read it in whole lines.
+__global__ __launch_bounds__(256) void thin_gather_kernel(const float* Y, int64_t yks,
+                                                          int64_t yjs, int64_t K, int r,
+                                                          float* Yc) {
+    const int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= K * r) return;
+    const int64_t k = p / r, j = p - k * r;
+    Yc[p] = Y[k * yks + j * yjs];
 }
 
 template <int R>
@@ -211,6 +243,18 @@ hipError_t launch_thin(bool ta, bool tb, const GemmDesc& d, const ThinPlan& p, f
     t.K = K;
     t.kc = p.kc;
     if (r < 1 || r > THIN_MAX_R) return hipErrorInvalidValue;
+    if (p.gather) {
+        // After the S slices of partial sums.
+        float* yc = ws + (int64_t)p.splits * M * N;
+        const int64_t n = K * r;
+        hipLaunchKernelGGL(thin_gather_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s,
+                           t.Y, t.yks, t.yjs, K, r, yc);
+        t.Y = yc;
+        t.yks = r;
+        t.yjs = 1;
+        t.ybytes = 4 * n;
+    }
+    t.ymode = t.yks == 1 ? 1 : (t.yks == r && t.yjs == 1 ? 2 : 0);
     switch (r) {
         case 1: launch_thin_r<1>(kcontig, t, p.splits, s); break;
         case 2: launch_thin_r<2>(kcontig, t, p.splits, s); break;

@@ -149,7 +149,7 @@ int mgemm_tune_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K, 
     if (precision == MGEMM_PREC_FP32) {
         const ThinPlan tp = thin_plan(M, N, K, lda, ldb, ldc, ta0 != 0, tb0 != 0, device_cus(dev));
         own = f32_edge_plan(ta0 != 0, tb0 != 0, M, N, K, &mm, &nn) ||
-              (tp.ok && thin_workspace_bytes(tp, M, N) <= F32_SPLITK_MAX_WORKSPACE);
+              (tp.ok && thin_workspace_bytes(tp, M, N, K) <= F32_SPLITK_MAX_WORKSPACE);
     }
     if (own) forget(precision, ta0, tb0, M, N, K);
     int best = -1;

@@ -11,7 +11,7 @@
 //   D prec ta tb M N K                         -> built-in configuration
 //   S M N K cus                                -> small_tile splits kc
 //   E ta tb M N K                              -> 1 Mm Nm (edge split) or 0
-//   T ta tb M N K lda ldb ldc cus              -> ok rows splits kc bytes (thin path)
+//   T ta tb M N K lda ldb ldc cus              -> ok rows splits kc bytes gather (thin)
 //   L G n cost_1 .. cost_n                     -> work-group of each item
 //   B nc na (lo hi owner) x (nc + na)          -> culprit kind
 #include <cstdio>
@@ -76,8 +76,8 @@ int main() {
             in >> ta >> tb >> M >> N >> K >> lda >> ldb >> ldc >> cus;
             const ThinPlan p = thin_plan(M, N, K, lda, ldb, ldc, trans_code(ta) == 1,
                                          trans_code(tb) == 1, cus);
-            std::printf("%d %d %d %lld %lld\n", p.ok, p.rows, p.splits, (long long)p.kc,
-                        (long long)thin_workspace_bytes(p, M, N));
+            std::printf("%d %d %d %lld %lld %d\n", p.ok, p.rows, p.splits, (long long)p.kc,
+                        (long long)thin_workspace_bytes(p, M, N, K), p.gather);
         } else if (op == 'S') {
             long long M, N, K;
             int cus;

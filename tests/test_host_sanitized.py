@@ -396,7 +396,10 @@ def test_thin_plan_rule(bins):
     K >= 256, leading dimensions and M within the buffer path's limit and
     the referenced extents of A and B below 2^31 bytes; the k pieces are
     multiples of 64, at most 64 of them, every one non-empty, for about
-    eight work-groups per CU; the workspace holds S partial products."""
+    eight work-groups per CU; a small operand with non-adjacent k elements
+    is gathered first when the large one is k-contiguous and holds at least
+    2^25 elements; the
+    workspace holds S partial products and the gathered operand."""
     lim, rng_bytes = (1 << 21) - 64, 0x7ffffff0
     rng = np.random.default_rng(7)
     cases = [("N", "N", 8192, 1, 8193, 8192, 8193, 8192, 256),
@@ -419,10 +422,10 @@ def test_thin_plan_rule(bins):
         cases.append((ta, tb, M, N, K, lda, ldb, M + int(rng.choice([0, 7])),
                       int(rng.choice([1, 80, 256]))))
     out = _host(bins, ["T %s %s %d %d %d %d %d %d %d" % c for c in cases])
-    seen = {0: 0, 1: 0}
+    seen, seen_gather = {0: 0, 1: 0}, {0: 0, 1: 0}
     for c, line in zip(cases, out):
         ta, tb, M, N, K, lda, ldb, ldc, cus = c
-        ok, rows, S, kc, nbytes = (int(x) for x in line.split())
+        ok, rows, S, kc, nbytes, gather = (int(x) for x in line.split())
         cols = N <= 8
         few_rows = not cols and M <= 8
         P = M if cols else N
@@ -432,19 +435,24 @@ def test_thin_plan_rule(bins):
                 and max(lda, ldb, ldc, M) <= lim and 4 * aext < rng_bytes and 4 * bext < rng_bytes)
         assert bool(ok) == want, (c, line)
         if not ok:
-            assert (rows, S, kc, nbytes) == (0, 0, 0, 0), (c, line)
+            assert (rows, S, kc, nbytes, gather) == (0, 0, 0, 0, 0), (c, line)
             continue
         seen[rows] += 1
         assert rows == int(few_rows), c
         assert kc % 64 == 0 and 1 <= S <= 64, (c, line)
         assert (S - 1) * kc < K <= S * kc, (c, line)        # every piece non-empty
-        assert nbytes == 4 * S * M * N, (c, line)
+        strided = (tb == "T" and ldb != 1) if cols else (ta == "N" and lda != 1)
         kcontig = (ta == "T") if cols else (tb == "N")
+        assert gather == int(strided and kcontig and P * K >= 2 ** 25), (c, line)
+        seen_gather[gather] += 1
+        r = N if cols else M
+        assert nbytes == 4 * (S * M * N + (K * r if gather else 0)), (c, line)
         blocks = -(-P // (16 if kcontig else 64))
         target = min(64, -(-8 * cus // blocks))
         assert S <= target, (c, line)                      # at most the target pieces
         assert S == -(-K // kc) and kc == -(-(-(-K // target)) // 64) * 64, (c, line)
     assert seen[0] >= 30 and seen[1] >= 30, seen
+    assert seen_gather[0] >= 30 and seen_gather[1] >= 8, seen_gather
     assert out[0].split()[:2] == ["1", "0"] and out[1].split()[:2] == ["1", "1"]
     assert out[2].split()[0] == "1"
     for line in out[3:10]:

@@ -14,7 +14,10 @@ TRANS = [("N", "N"), ("N", "T"), ("T", "N"), ("T", "T")]
 # (M, N, K): few columns, few rows, ragged everywhere, K not a multiple of
 # 4 or of the 256-deep pieces.
 SHAPES = [(1000, 1, 1000), (4097, 3, 513), (300, 8, 2049), (1, 1000, 1000), (5, 4097, 777),
-          (8, 256, 4097), (2, 2, 300)]
+          (8, 256, 4097), (2, 2, 300),
+          # At least 2^25 elements of the large operand: with TT (few
+          # columns) or NN (few rows) the small operand is gathered first.
+          (8200, 2, 4099), (3, 8200, 4099)]
 
 
 @pytest.mark.parametrize("ta,tb", TRANS)
@@ -46,7 +49,8 @@ def test_thin_integers_bitwise():
     """Small integers: every partial sum is exact, so a k block missing from
     a piece, or taken twice, would show."""
     for (M, N, K, ta, tb) in ((3000, 7, 4099, "N", "N"), (6, 3000, 4099, "T", "T"),
-                              (2500, 1, 2000, "T", "N"), (1, 2500, 2000, "N", "T")):
+                              (2500, 1, 2000, "T", "N"), (1, 2500, 2000, "N", "T"),
+                              (8200, 7, 4099, "T", "T"), (6, 8200, 4099, "N", "N")):
         c = synth.sgemm_case(62, ta, tb, M, N, K, alpha=1.0, beta=1.0, dist="int16",
                              dist_c="int16")
         got = logical_c(run(c), c)

@@ -48,8 +48,9 @@ def _log_lines(path):
 PAIRS = [
     # FP32 split-K: S partial products in the scratch array.
     ("fp32", (512, 512, 16384, "T", "N"), (200, 136, 5000, "N", "T"), "f32_split_k"),
-    # FP32 thin products (the library's choice): k-piece partial sums.
-    ("fp32", (8192, 3, 8193, "N", "N"), (1000, 1, 700, "T", "T"), "f32_thin"),
+    # FP32 thin products (the library's choice): k-piece partial sums and,
+    # on the first call, the gathered small operand.
+    ("fp32", (8192, 3, 8193, "T", "T"), (1000, 1, 700, "T", "T"), "f32_thin"),
     # Scaled FP16: panel exponents and partial maxima, plus packed operands
     # (2048^3: 16 MiB) on the first call.
     ("fp16s", (2048, 2048, 2048, "N", "N"), (300, 260, 700, "T", "N"), "packed"),
