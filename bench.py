@@ -736,6 +736,7 @@ def bench_thin(args, mg, torch, oracle, synth):
                        "bytes = 4 (MK + KN + 2MN)"}
     for (M, N, K, ta, tb) in ((8192, 1, 8193, "N", "N"), (8192, 8, 8193, "N", "N"),
                               (8192, 1, 8193, "T", "N"), (8192, 1, 8193, "T", "T"),
+                              (8192, 8, 8193, "T", "T"),
                               (1, 8193, 8193, "N", "N"),
                               (4096, 1, 4097, "N", "N")):
         c = synth.sgemm_case(0, ta, tb, M, N, K, alpha=1.5, beta=-0.5)
