@@ -98,11 +98,11 @@ __global__ __launch_bounds__(256) void thin_icontig_kernel(ThinArgs t) {
 // lanes load 16 bytes (4 consecutive k) of each row, 256 k per wave, the
 // loads of Y shared by the 4 rows, and each sum is reduced across the lanes
 // in a fixed butterfly order.
-template <int R>
+template <int R, int YM>
 __global__ __launch_bounds__(256) void thin_kcontig_kernel(ThinArgs t) {
     // Fewer loads in flight per lane as r grows, so that the registers stay
     // within 128.
-    constexpr int U = R <= 2 ? THIN_UNROLL : (R <= 4 ? 2 : 1);
+    constexpr int U = R == 1 ? THIN_UNROLL : (R <= 4 ? 2 : 1);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * THIN_ROWS_K + 4 * wave, s = blockIdx.y;
     const int64_t k0 = s * t.kc, k1 = k0 + t.kc < t.K ? k0 + t.kc : t.K;
@@ -135,14 +135,14 @@ __global__ __launch_bounds__(256) void thin_kcontig_kernel(ThinArgs t) {
                                                       : BUF_OOB);
                 }
             }
-            if (k + 3 < k1 && t.ymode == 1) {
+            if (YM == 1 && k + 3 < k1) {
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
                     const f32x4 v = buf_load_f32x4(ry, (uint32_t)(4 * (k + j * t.yjs)));
 #pragma unroll
                     for (int e = 0; e < 4; ++e) y[u][e][j] = v[e];
                 }
-            } else if (k + 3 < k1 && t.ymode == 2) {
+            } else if (YM == 2 && k + 3 < k1) {
 #pragma unroll
                 for (int q = 0; q < R; ++q) {
                     const f32x4 v = buf_load_f32x4(ry, (uint32_t)(4 * (k * R + 4 * q)));
@@ -194,8 +194,15 @@ __global__ __launch_bounds__(256) void thin_gather_kernel(const float* Y, int64_
 template <int R>
 static void launch_thin_r(bool kcontig, const ThinArgs& t, int64_t S, hipStream_t s) {
     if (kcontig) {
+        // One way of reading Y per kernel, so that the registers of the
+        // others are not held.
         const dim3 grid((uint32_t)((t.P + THIN_ROWS_K - 1) / THIN_ROWS_K), (uint32_t)S);
-        hipLaunchKernelGGL(thin_kcontig_kernel<R>, grid, dim3(256), 0, s, t);
+        if (t.ymode == 1)
+            hipLaunchKernelGGL((thin_kcontig_kernel<R, 1>), grid, dim3(256), 0, s, t);
+        else if (t.ymode == 2)
+            hipLaunchKernelGGL((thin_kcontig_kernel<R, 2>), grid, dim3(256), 0, s, t);
+        else
+            hipLaunchKernelGGL((thin_kcontig_kernel<R, 0>), grid, dim3(256), 0, s, t);
     } else {
         const dim3 grid((uint32_t)((t.P + THIN_ROWS_I - 1) / THIN_ROWS_I), (uint32_t)S);
         hipLaunchKernelGGL(thin_icontig_kernel<R>, grid, dim3(256), 0, s, t);
