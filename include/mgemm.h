@@ -125,6 +125,8 @@ int mgemm_sgemm(char transA, char transB, int64_t M, int64_t N, int64_t K,
  * 124 TFLOP/s whole).  FP32 with config = -1 and no choice recorded: a
  * product with at most 8 columns (or rows) of C, at least 256 rows (or
  * columns), K >= 256 and leading dimensions (and M) below 2^21 - 64
+ * (with a k-contiguous large operand, i.e. op(A) stored transposed or op(B)
+ * not, and more than 4 such columns or rows: at least 2^25 elements of it)
  * streams the large operand once in k pieces whose
  * partial sums (S*M*N*4 bytes of workspace from the pool) are added in a
  * fixed order, as for split-K.  mgemm_default_config reports the

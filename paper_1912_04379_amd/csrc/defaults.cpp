@@ -257,6 +257,10 @@ ThinPlan thin_plan(int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb, in
     const int64_t bext = tb ? N + (K - 1) * ldb : K + (N - 1) * ldb;
     if (4 * aext >= THIN_MAX_RANGE || 4 * bext >= THIN_MAX_RANGE) return p;
     const bool kcontig = cols ? ta : !tb;
+    const int64_t r = cols ? N : M;
+    // Five to eight columns on the k-contiguous kernel run below the rate
+    // of split-K unless the large operand is big.
+    if (kcontig && r > 4 && P * K < THIN_GATHER_MIN) return p;
     const int64_t per = kcontig ? THIN_ROWS_K : THIN_ROWS_I;
     const int64_t blocks = (P + per - 1) / per;
     // About eight work-groups per CU, so that the loads in flight cover the
@@ -271,7 +275,7 @@ ThinPlan thin_plan(int64_t M, int64_t N, int64_t K, int64_t lda, int64_t ldb, in
     p.kc = kc;
     p.rows = rows ? 1 : 0;
     const bool strided = cols ? (tb && ldb != 1) : (!ta && lda != 1);
-    p.gather = strided && kcontig && P * K >= THIN_GATHER_MIN ? 1 : 0;
+    p.gather = strided && kcontig && (r >= 2 || P * K >= THIN_GATHER_MIN) ? 1 : 0;
     p.ok = 1;
     return p;
 }

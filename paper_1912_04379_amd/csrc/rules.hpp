@@ -54,7 +54,9 @@ bool f32_edge_plan(bool transA, bool transB, int64_t M, int64_t N, int64_t K, in
 // FP32 products with at most THIN_MAX_R columns of C (or rows: then taken
 // through the transpose), at least 256 of the other and K >= 256, whose
 // operands stay within 32-bit buffer offsets (leading dimensions, M and the
-// referenced extents): the library's choice is the thin path, the large
+// referenced extents) -- with a k-contiguous large operand and more than 4
+// of them, only when it holds at least THIN_GATHER_MIN elements -- the
+// library's choice is the thin path, the large
 // operand P x K streamed once in S pieces of kc along k (about eight
 // work-groups of THIN_ROWS_I or THIN_ROWS_K rows per CU) into S*M*N floats
 // of workspace, then the split-K reduction.
@@ -66,9 +68,10 @@ constexpr int64_t THIN_MAX_RANGE = 0x7ffffff0LL;         // bytes one buffer res
 // With a k-contiguous large operand, a small operand whose k elements are
 // not adjacent in memory (op(B) with transB, or op(A)^T without transA) is
 // first gathered into K*r floats in k-major order after the partial sums,
-// when the large operand holds at least THIN_GATHER_MIN elements: the
-// streaming kernel's lanes would otherwise touch a cache line per k.  (The
-// row-contiguous kernel reads few k at a time and gains nothing from it.)
+// when r >= 2 or the large operand holds at least THIN_GATHER_MIN elements:
+// the streaming kernel's lanes would otherwise touch a cache line per k and
+// column.  (The row-contiguous kernel reads few k at a time and gains
+// nothing from it.)
 constexpr int64_t THIN_GATHER_MIN = 1LL << 25;
 struct ThinPlan {
     int ok;       // the thin path applies

@@ -394,17 +394,18 @@ def test_thin_plan_rule(bins):
     """The thin-product plan as documented: at most 8 columns of C (else at
     most 8 rows, through the transpose), at least 256 on the other side,
     K >= 256, leading dimensions and M within the buffer path's limit and
-    the referenced extents of A and B below 2^31 bytes; the k pieces are
+    the referenced extents of A and B below 2^31 bytes, and with a
+    k-contiguous large operand and more than 4 of them, 2^25 elements of it; the k pieces are
     multiples of 64, at most 64 of them, every one non-empty, for about
     eight work-groups per CU; a small operand with non-adjacent k elements
-    is gathered first when the large one is k-contiguous and holds at least
-    2^25 elements; the
+    is gathered first when the large one is k-contiguous and r >= 2 or it
+    holds at least 2^25 elements; the
     workspace holds S partial products and the gathered operand."""
     lim, rng_bytes = (1 << 21) - 64, 0x7ffffff0
     rng = np.random.default_rng(7)
     cases = [("N", "N", 8192, 1, 8193, 8192, 8193, 8192, 256),
              ("N", "N", 1, 8193, 8193, 1, 8193, 1, 256),
-             ("T", "T", 4096, 8, 4097, 4097, 8, 4096, 256),
+             ("N", "T", 4096, 8, 4097, 4096, 8, 4096, 256),
              ("N", "N", 4096, 9, 4097, 4096, 4097, 4096, 256),
              ("N", "N", 255, 1, 4096, 255, 4096, 255, 256),
              ("N", "N", 4096, 1, 255, 4096, 255, 4096, 256),
@@ -431,8 +432,11 @@ def test_thin_plan_rule(bins):
         P = M if cols else N
         aext = K + (M - 1) * lda if ta == "T" else M + (K - 1) * lda
         bext = N + (K - 1) * ldb if tb == "T" else K + (N - 1) * ldb
+        kcontig = (ta == "T") if cols else (tb == "N")
+        r = N if cols else M
         want = ((cols or few_rows) and P >= 256 and K >= 256 and cus >= 1
-                and max(lda, ldb, ldc, M) <= lim and 4 * aext < rng_bytes and 4 * bext < rng_bytes)
+                and max(lda, ldb, ldc, M) <= lim and 4 * aext < rng_bytes and 4 * bext < rng_bytes
+                and not (kcontig and r > 4 and P * K < 2 ** 25))
         assert bool(ok) == want, (c, line)
         if not ok:
             assert (rows, S, kc, nbytes, gather) == (0, 0, 0, 0, 0), (c, line)
@@ -442,10 +446,8 @@ def test_thin_plan_rule(bins):
         assert kc % 64 == 0 and 1 <= S <= 64, (c, line)
         assert (S - 1) * kc < K <= S * kc, (c, line)        # every piece non-empty
         strided = (tb == "T" and ldb != 1) if cols else (ta == "N" and lda != 1)
-        kcontig = (ta == "T") if cols else (tb == "N")
-        assert gather == int(strided and kcontig and P * K >= 2 ** 25), (c, line)
+        assert gather == int(strided and kcontig and (r >= 2 or P * K >= 2 ** 25)), (c, line)
         seen_gather[gather] += 1
-        r = N if cols else M
         assert nbytes == 4 * (S * M * N + (K * r if gather else 0)), (c, line)
         blocks = -(-P // (16 if kcontig else 64))
         target = min(64, -(-8 * cus // blocks))
