@@ -3,7 +3,9 @@
 // large operand once.  The large operand X (P x K) is streamed with
 // coalesced loads, cut along k into S pieces so that every CU has several
 // work-groups of loads in flight; the small operand Y (K x r) is read
-// through the cache.  Piece s writes its partial sums to slice s of a
+// through the cache (for the k-contiguous kernel, from a k-major copy
+// gathered first when its k elements are not adjacent, as the plan in
+// defaults.cpp decides).  Piece s writes its partial sums to slice s of a
 // workspace, and the split-K reduction adds the slices in the order
 // s = 0..S-1 and applies alpha and beta: results do not depend on timing.
 #include <hip/hip_runtime.h>
